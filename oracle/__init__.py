@@ -1,0 +1,175 @@
+"""FP64 CPU oracle for the DFT -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``oracle.c`` (plain C, built
+with gcc) through ctypes and never touches the GPU library.
+
+Conventions (the paper names the DFT and Cooley-Tukey in section III-A but
+prints no formula, so the textbook definition is used):
+forward ``X[k] = sum_j x[j] exp(-2 pi i j k / N)``; inverse uses ``exp(+...)``
+and ``1/N``; the 2D transform is the separable product, inverse ``1/(N1 N2)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
+    """Compile ``src`` (default oracle.c) to the shared library ``out`` with gcc
+    (FP64, OpenMP, no fast-math)."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-fno-fast-math", "-Wall", "-I", _HERE, "-o", tmp, src, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, out)
+    return out
+
+
+def _c128(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+
+
+def _c64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.complex64))
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError("oracle call failed")
+
+
+class OracleLib:
+    """ctypes view of one build of oracle.c (the default build, or a copy with a
+    planted mistake used to show that the pins catch it)."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.POINTER(ctypes.c_float)
+        ip = ctypes.POINTER(ctypes.c_int64)
+        i64, ci = ctypes.c_int64, ctypes.c_int
+        lib.oracle_dft.argtypes = [dp, dp, i64, ci]
+        lib.oracle_fft.argtypes = [dp, dp, i64, ci]
+        lib.oracle_fft_batch_f32.argtypes = [fp, dp, i64, i64, ci, ci]
+        lib.oracle_fft_ragged_f32.argtypes = [fp, dp, ip, ip, i64, ci, ci]
+        lib.oracle_fft2d_f32.argtypes = [fp, dp, i64, i64, i64, ci, ci]
+        lib.oracle_threads.argtypes = [ci]
+        for f in (lib.oracle_dft, lib.oracle_fft, lib.oracle_fft_batch_f32,
+                  lib.oracle_fft_ragged_f32, lib.oracle_fft2d_f32, lib.oracle_threads):
+            f.restype = ci
+        self.lib = lib
+        self.path = path
+
+    def dft(self, x, inverse: bool = False) -> np.ndarray:
+        """O(N^2) DFT of one signal from the definition (complex128 in/out)."""
+        x = _c128(x).reshape(-1)
+        y = np.empty_like(x)
+        _check(self.lib.oracle_dft(_ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double),
+                                   x.size, int(inverse)))
+        return y
+
+    def fft(self, x, inverse: bool = False) -> np.ndarray:
+        """Recursive mixed-radix Cooley-Tukey FFT of one signal (complex128 in/out)."""
+        x = _c128(x).reshape(-1)
+        y = np.empty_like(x)
+        _check(self.lib.oracle_fft(_ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double),
+                                   x.size, int(inverse)))
+        return y
+
+    def fft_batch(self, x, inverse: bool = False, threads: int = 0) -> np.ndarray:
+        """Batched FFT over the last axis of a complex64 array -> complex128."""
+        x = _c64(x)
+        n = x.shape[-1]
+        batch = x.size // n if n else 0
+        y = np.empty(x.shape, dtype=np.complex128)
+        _check(self.lib.oracle_fft_batch_f32(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_double),
+                                             n, batch, int(inverse), threads))
+        return y
+
+    def fft_ragged(self, flat, sizes, offsets, inverse: bool = False,
+                   threads: int = 0) -> np.ndarray:
+        """Ragged batch: signal i = flat[offsets[i] : offsets[i]+sizes[i]] -> complex128."""
+        flat = _c64(flat).reshape(-1)
+        sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        y = np.zeros(flat.shape, dtype=np.complex128)
+        _check(self.lib.oracle_fft_ragged_f32(
+            _ptr(flat, ctypes.c_float), _ptr(y, ctypes.c_double),
+            _ptr(sizes, ctypes.c_int64), _ptr(offsets, ctypes.c_int64),
+            len(sizes), int(inverse), threads))
+        return y
+
+    def fft2d(self, x, inverse: bool = False, threads: int = 0) -> np.ndarray:
+        """2D FFT of images shaped (..., ny, nx) complex64 -> complex128."""
+        x = _c64(x)
+        ny, nx = x.shape[-2:]
+        batch = x.size // (ny * nx)
+        y = np.empty(x.shape, dtype=np.complex128)
+        _check(self.lib.oracle_fft2d_f32(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_double),
+                                         ny, nx, batch, int(inverse), threads))
+        return y
+
+    def threads(self, requested: int = 0) -> int:
+        return self.lib.oracle_threads(requested)
+
+
+_default = None
+
+
+def default() -> OracleLib:
+    """The oracle built from oracle.c (built on first use if absent)."""
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _default = OracleLib(_LIB)
+    return _default
+
+
+def dft(x, inverse: bool = False) -> np.ndarray:
+    return default().dft(x, inverse)
+
+
+def fft(x, inverse: bool = False) -> np.ndarray:
+    return default().fft(x, inverse)
+
+
+def fft_batch(x, inverse: bool = False, threads: int = 0) -> np.ndarray:
+    return default().fft_batch(x, inverse, threads)
+
+
+def fft_ragged(flat, sizes, offsets, inverse: bool = False, threads: int = 0) -> np.ndarray:
+    return default().fft_ragged(flat, sizes, offsets, inverse, threads)
+
+
+def fft2d(x, inverse: bool = False, threads: int = 0) -> np.ndarray:
+    return default().fft2d(x, inverse, threads)
+
+
+def threads(requested: int = 0) -> int:
+    """OpenMP thread count the batch routines use for ``requested`` (0 = default)."""
+    return default().threads(requested)
+
+
+def rel_l2(y, ref) -> np.ndarray:
+    """Per-signal relative L2 error ||y - ref|| / ||ref|| over the last axis
+    (or the last two axes for 3D input)."""
+    y = np.asarray(y)
+    ref = np.asarray(ref)
+    axes = tuple(range(1, ref.ndim)) if ref.ndim > 1 else None
+    num = np.sqrt(np.sum(np.abs(y.astype(np.complex128) - ref) ** 2, axis=axes))
+    den = np.sqrt(np.sum(np.abs(ref) ** 2, axis=axes))
+    return num / np.where(den == 0, 1.0, den)

@@ -1,0 +1,298 @@
+/*
+ * FP64 CPU oracle for the discrete Fourier transform -- TEST INFRASTRUCTURE.
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg use it; the
+ * GPU library never links or calls it.  See oracle.h for the conventions.
+ *
+ * Two independent routes to the same numbers:
+ *   1. oracle_dft: the defining sum, O(N^2), every angle 2*pi*((j*k) mod N)/N
+ *      evaluated with libm cos/sin in double (no table, no recursion).
+ *   2. oracle_fft: the Cooley-Tukey recursion the paper describes (section
+ *      III-A): a length-N DFT is assembled from p interleaved DFTs of length
+ *      N/p.  The paper uses p = 2 throughout (radix-2 decimation in time);
+ *      here p is the smallest prime factor of N, so powers of two recurse
+ *      exactly as radix-2 DIT and 7-smooth lengths use p in {3, 5, 7} where
+ *      needed.  A length whose smallest prime factor exceeds 7 is summed
+ *      directly.  Combination step, for k = 0..N-1 with m = N/p:
+ *          X[k] = sum_{r=0}^{p-1} w_N^{(r k) mod N} * Y_r[k mod m],
+ *      where Y_r is the length-m DFT of x[r], x[r+p], x[r+2p], ...
+ *      Twiddles w_N^t come from one table per top-level N, each entry computed
+ *      directly with cos/sin (no recurrence); a sub-problem of length n reads
+ *      w_n^t = w_N^{t N/n}.
+ * The inverse uses the identity  ifft(x) = conj(fft(conj(x))) / N.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double re, im;
+} cplx;
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+static inline cplx cmul(cplx a, cplx b) {
+    cplx r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return r;
+}
+
+static int64_t smallest_prime_factor(int64_t n) {
+    for (int64_t p = 2; p * p <= n; ++p)
+        if (n % p == 0) return p;
+    return n;
+}
+
+/* w_N^t = exp(-2 pi i t / N) for t in [0, N) */
+static cplx *make_table(int64_t n) {
+    cplx *tab = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!tab) return NULL;
+    for (int64_t t = 0; t < n; ++t) {
+        double ang = -TWO_PI * ((double)t / (double)n);
+        tab[t].re = cos(ang);
+        tab[t].im = sin(ang);
+    }
+    return tab;
+}
+
+/*
+ * Length-n DFT of x[0], x[stride], ..., x[(n-1)*stride] into out[0..n).
+ * tab holds w_{n*tstride}^t, so w_n^t = tab[t * tstride].
+ * tmp is scratch of n elements, disjoint from out.
+ */
+static void fft_rec(const cplx *x, int64_t stride, int64_t n, cplx *out,
+                    cplx *tmp, const cplx *tab, int64_t tstride) {
+    if (n == 1) {
+        out[0] = x[0];
+        return;
+    }
+    int64_t p = smallest_prime_factor(n);
+    if (p > 7) {
+        for (int64_t k = 0; k < n; ++k) {
+            cplx acc = {0.0, 0.0};
+            for (int64_t j = 0; j < n; ++j) {
+                cplx t = cmul(x[j * stride], tab[((j * k) % n) * tstride]);
+                acc.re += t.re;
+                acc.im += t.im;
+            }
+            out[k] = acc;
+        }
+        return;
+    }
+    int64_t m = n / p;
+    /* Y_r = DFT_m of the r-th interleaved subsequence, stored at tmp + r*m;
+     * each child uses its own slice of `out` as scratch. */
+    for (int64_t r = 0; r < p; ++r)
+        fft_rec(x + r * stride, stride * p, m, tmp + r * m, out + r * m, tab,
+                tstride * p);
+    for (int64_t k = 0; k < n; ++k) {
+        cplx acc = {0.0, 0.0};
+        for (int64_t r = 0; r < p; ++r) {
+            cplx t = cmul(tab[((r * k) % n) * tstride], tmp[r * m + (k % m)]);
+            acc.re += t.re;
+            acc.im += t.im;
+        }
+        out[k] = acc;
+    }
+}
+
+/* One signal: x (double pairs) -> y; tab = make_table(n); tmp of n elements. */
+static void fft_one(const cplx *x, cplx *y, int64_t n, const cplx *tab,
+                    cplx *tmp, cplx *conj_buf, int inverse) {
+    if (!inverse) {
+        fft_rec(x, 1, n, y, tmp, tab, 1);
+        return;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        conj_buf[j].re = x[j].re;
+        conj_buf[j].im = -x[j].im;
+    }
+    fft_rec(conj_buf, 1, n, y, tmp, tab, 1);
+    double s = 1.0 / (double)n;
+    for (int64_t k = 0; k < n; ++k) {
+        y[k].re = y[k].re * s;
+        y[k].im = -y[k].im * s;
+    }
+}
+
+int oracle_threads(int threads) {
+#ifdef _OPENMP
+    return threads > 0 ? threads : omp_get_max_threads();
+#else
+    (void)threads;
+    return 1;
+#endif
+}
+
+int oracle_dft(const double *xd, double *yd, int64_t n, int inverse) {
+    if (!xd || !yd || n <= 0) return -1;
+    const cplx *x = (const cplx *)xd;
+    cplx *y = (cplx *)yd;
+    double sign = inverse ? 1.0 : -1.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t t = (j * k) % n;
+            double ang = sign * TWO_PI * ((double)t / (double)n);
+            double c = cos(ang), s = sin(ang);
+            sr += x[j].re * c - x[j].im * s;
+            si += x[j].re * s + x[j].im * c;
+        }
+        if (inverse) {
+            sr /= (double)n;
+            si /= (double)n;
+        }
+        y[k].re = sr;
+        y[k].im = si;
+    }
+    return 0;
+}
+
+int oracle_fft(const double *xd, double *yd, int64_t n, int inverse) {
+    if (!xd || !yd || n <= 0) return -1;
+    cplx *tab = make_table(n);
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *cb = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    int rc = -1;
+    if (tab && tmp && cb) {
+        fft_one((const cplx *)xd, (cplx *)yd, n, tab, tmp, cb, inverse);
+        rc = 0;
+    }
+    free(tab);
+    free(tmp);
+    free(cb);
+    return rc;
+}
+
+int oracle_fft_batch_f32(const float *x, double *yd, int64_t n, int64_t batch,
+                         int inverse, int threads) {
+    if (!x || !yd || n <= 0 || batch < 0) return -1;
+    cplx *tab = make_table(n);
+    if (!tab) return -1;
+    int failed = 0;
+#pragma omp parallel num_threads(oracle_threads(threads))
+    {
+        cplx *xin = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+        cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+        cplx *cb = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+        if (!xin || !tmp || !cb) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t b = 0; b < batch; ++b) {
+                const float *src = x + 2 * b * n;
+                for (int64_t j = 0; j < n; ++j) {
+                    xin[j].re = (double)src[2 * j];
+                    xin[j].im = (double)src[2 * j + 1];
+                }
+                fft_one(xin, (cplx *)yd + b * n, n, tab, tmp, cb, inverse);
+            }
+        }
+        free(xin);
+        free(tmp);
+        free(cb);
+    }
+    free(tab);
+    return failed ? -1 : 0;
+}
+
+int oracle_fft_ragged_f32(const float *x, double *yd, const int64_t *sizes,
+                          const int64_t *offsets, int64_t count, int inverse,
+                          int threads) {
+    if (!x || !yd || !sizes || !offsets || count < 0) return -1;
+    for (int64_t i = 0; i < count; ++i)
+        if (sizes[i] <= 0 || offsets[i] < 0) return -1;
+    int failed = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(oracle_threads(threads))
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t n = sizes[i];
+        cplx *tab = make_table(n);
+        cplx *xin = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+        cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+        cplx *cb = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+        if (!tab || !xin || !tmp || !cb) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+            const float *src = x + 2 * offsets[i];
+            for (int64_t j = 0; j < n; ++j) {
+                xin[j].re = (double)src[2 * j];
+                xin[j].im = (double)src[2 * j + 1];
+            }
+            fft_one(xin, (cplx *)yd + offsets[i], n, tab, tmp, cb, inverse);
+        }
+        free(tab);
+        free(xin);
+        free(tmp);
+        free(cb);
+    }
+    return failed ? -1 : 0;
+}
+
+int oracle_fft2d_f32(const float *x, double *yd, int64_t ny, int64_t nx,
+                     int64_t batch, int inverse, int threads) {
+    if (!x || !yd || ny <= 0 || nx <= 0 || batch < 0) return -1;
+    cplx *tab_x = make_table(nx);
+    cplx *tab_y = make_table(ny);
+    if (!tab_x || !tab_y) {
+        free(tab_x);
+        free(tab_y);
+        return -1;
+    }
+    int64_t big = nx > ny ? nx : ny;
+    int nthr = oracle_threads(threads);
+    int failed = 0;
+    cplx *y = (cplx *)yd;
+    for (int64_t b = 0; b < batch; ++b) {
+        const float *img = x + 2 * b * ny * nx;
+        cplx *out = y + b * ny * nx;
+        /* rows: 1D forward transform of each row (conjugated input if inverse) */
+#pragma omp parallel num_threads(nthr)
+        {
+            cplx *xin = (cplx *)malloc(sizeof(cplx) * (size_t)big);
+            cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)big);
+            cplx *col = (cplx *)malloc(sizeof(cplx) * (size_t)big);
+            cplx *res = (cplx *)malloc(sizeof(cplx) * (size_t)big);
+            if (!xin || !tmp || !col || !res) {
+#pragma omp atomic write
+                failed = 1;
+            } else {
+#pragma omp for schedule(static)
+                for (int64_t r = 0; r < ny; ++r) {
+                    const float *src = img + 2 * r * nx;
+                    double sg = inverse ? -1.0 : 1.0;
+                    for (int64_t j = 0; j < nx; ++j) {
+                        xin[j].re = (double)src[2 * j];
+                        xin[j].im = sg * (double)src[2 * j + 1];
+                    }
+                    fft_rec(xin, 1, nx, out + r * nx, tmp, tab_x, 1);
+                }
+                /* columns: explicit gather, 1D transform, scatter */
+#pragma omp for schedule(static)
+                for (int64_t c = 0; c < nx; ++c) {
+                    for (int64_t r = 0; r < ny; ++r) col[r] = out[r * nx + c];
+                    fft_rec(col, 1, ny, res, tmp, tab_y, 1);
+                    for (int64_t r = 0; r < ny; ++r) out[r * nx + c] = res[r];
+                }
+            }
+            free(xin);
+            free(tmp);
+            free(col);
+            free(res);
+        }
+        if (inverse) {
+            double s = 1.0 / ((double)nx * (double)ny);
+            for (int64_t i = 0; i < nx * ny; ++i) {
+                out[i].re = out[i].re * s;
+                out[i].im = -out[i].im * s;
+            }
+        }
+    }
+    free(tab_x);
+    free(tab_y);
+    return failed ? -1 : 0;
+}

@@ -1,0 +1,59 @@
+/*
+ * FP64 CPU oracle for the discrete Fourier transform -- TEST INFRASTRUCTURE.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may link or call this code.  It shares nothing with the GPU
+ * library: no headers, tables or helpers.  Its purpose is to be slow, plain
+ * and obviously correct.
+ *
+ * What it computes (the paper, section III-A, names the DFT and the
+ * Cooley-Tukey algorithm but prints no formula; the textbook definition is
+ * used, with the sign and scaling conventions below):
+ *   forward  X[k] = sum_{j=0}^{N-1} x[j] * w_N^{j k},      w_N = exp(-2 pi i / N)
+ *   inverse  x[j] = (1/N) sum_{k=0}^{N-1} X[k] * w_N^{-j k}
+ *   2D       separable product of the 1D forward transform over both axes;
+ *            inverse scaled by 1/(N1*N2).
+ *
+ * Data: interleaved complex (re, im).  Inputs are float32 pairs (the
+ * library's element type), upcast exactly to double; outputs are double pairs.
+ * All functions return 0 on success, -1 on a bad argument or allocation
+ * failure.  Threads: OpenMP over independent signals; `threads <= 0` means the
+ * OpenMP default.
+ */
+#ifndef DP_ORACLE_H
+#define DP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* O(N^2) DFT straight from the definition (angles reduced as integers mod N). */
+int oracle_dft(const double *x, double *y, int64_t n, int inverse);
+
+/* Recursive mixed-radix decimation-in-time Cooley-Tukey FFT (double in/out). */
+int oracle_fft(const double *x, double *y, int64_t n, int inverse);
+
+/* Batch of `batch` signals of length n, consecutive signals `n` apart.
+ * x: float32 pairs, y: double pairs. */
+int oracle_fft_batch_f32(const float *x, double *y, int64_t n, int64_t batch,
+                         int inverse, int threads);
+
+/* Ragged batch: signal i has length sizes[i] and starts at element offsets[i]
+ * in both x and y. */
+int oracle_fft_ragged_f32(const float *x, double *y, const int64_t *sizes,
+                          const int64_t *offsets, int64_t count, int inverse,
+                          int threads);
+
+/* 2D transform of `batch` images of ny rows by nx columns (row-major, x
+ * contiguous): 1D transform of every row, then of every column. */
+int oracle_fft2d_f32(const float *x, double *y, int64_t ny, int64_t nx,
+                     int64_t batch, int inverse, int threads);
+
+/* Number of OpenMP threads a parallel region will use with `threads`. */
+int oracle_threads(int threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
