@@ -1,0 +1,144 @@
+/*
+ * dpfft -- batched complex-to-complex FFTs on one AMD MI355X (gfx950).
+ *
+ * The operation.  Section III-A of Cabellos, "Advanced Programming Platform
+ * for efficient use of Data Parallel Hardware" (arXiv 1203.4938) offloads the
+ * discrete Fourier transform of a stream of signals, computed by Cooley-Tukey
+ * decimation, as a flow of many independent DFTs, one data-parallel work item
+ * each (section II-A: one work item per element of the stream; the stream is
+ * cut into chunks and re-joined in order).  This library computes the same
+ * operation for a batch of signals:
+ *
+ *   forward (FFT_FORWARD)  X[k] = sum_{j=0}^{N-1} x[j] exp(-2 pi i j k / N)
+ *   inverse (FFT_INVERSE)  x[j] = (1/N) sum_{k=0}^{N-1} X[k] exp(+2 pi i j k / N)
+ *   rank 2 (images)        the product of the 1D transforms over both axes;
+ *                          the inverse is scaled by 1/(N1 N2)
+ *
+ * for every signal of the batch, outputs in natural order.  The plan-once /
+ * execute-many split mirrors the paper's run protocol (section II-D: a
+ * program is uploaded once, receives an identifier, and is then run on many
+ * input flows).
+ *
+ * Data.  Interleaved complex64: each element is two float32 (re, im).  All
+ * data pointers passed to fft_exec are device pointers (hipMalloc'd, or torch
+ * CUDA tensors) owned by the caller, at least 8-byte aligned.
+ *
+ * Streams.  fft_exec only enqueues work on the given HIP stream (NULL = the
+ * default stream) and never synchronizes.  A plan is immutable once created;
+ * executions of one plan on different streams may run concurrently if each
+ * has its own workspace.
+ *
+ * Errors.  Every function returns fft_status_t.  Argument validation happens
+ * before any device work and has no side effects.  fft_last_error() returns a
+ * thread-local message describing the most recent failure on the calling
+ * thread.
+ */
+#ifndef DPFFT_H
+#define DPFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dpfft_plan_s *fft_plan_t; /* opaque, owned by the library */
+
+typedef enum {
+  FFT_OK = 0,
+  FFT_E_INVALID = 1,     /* bad argument (NULL pointer, negative size, ...) */
+  FFT_E_UNSUPPORTED = 2, /* valid request this library does not implement */
+  FFT_E_NOMEM = 3,       /* device or host allocation failed */
+  FFT_E_DEVICE = 4,      /* a HIP call or kernel launch failed */
+  FFT_E_INTERNAL = 5     /* an internal consistency check failed */
+} fft_status_t;
+
+/* Direction: the sign of the exponent. */
+#define FFT_FORWARD (-1)
+#define FFT_INVERSE (+1)
+
+/* Arithmetic of the transform. FP32: float32 butterflies everywhere.  The
+ * *_MFMA forms run the DFT-16 stages as FP16/BF16 matrix products on the
+ * matrix cores with FP32 accumulation; *_SPLIT forms split inputs and
+ * twiddles into hi + lo pieces to recover FP32-level accuracy. */
+typedef enum {
+  FFT_FP32 = 0,
+  FFT_FP16_MFMA = 1,
+  FFT_BF16_MFMA = 2,
+  FFT_FP16_SPLIT = 3,
+  FFT_BF16_SPLIT = 4,
+  FFT_BF16_SPLIT3 = 5
+} fft_precision_t;
+
+/* Plan flags. */
+#define FFT_F_INPLACE 1u     /* in == out is allowed */
+#define FFT_F_NO_AUTOTUNE 2u /* ignore the autotune cache, use the heuristic plan */
+#define FFT_F_GRAPH 4u       /* ragged plans: replay the launch as a captured HIP graph */
+
+typedef struct {
+  int32_t rank;     /* 1: batched 1D signals; 2: batched images */
+  int64_t n[2];     /* rank 1: n[0] = N; rank 2: {ny, nx}, nx contiguous */
+  int64_t batch;    /* number of transforms (ragged: number of signals) */
+  int64_t dist;     /* elements between consecutive transforms; 0 = dense
+                       (N for rank 1, ny*nx for rank 2); same for in and out */
+  const int64_t *ragged_sizes;   /* rank 1 only, optional: per-signal N
+                                    (then n[0] is ignored); host pointer,
+                                    copied by fft_plan */
+  const int64_t *ragged_offsets; /* optional with ragged_sizes: element offset
+                                    of each signal; NULL = packed prefix sum */
+  int32_t precision; /* fft_precision_t */
+  uint32_t flags;    /* FFT_F_* */
+} fft_desc_t;
+
+/*
+ * Create a plan.  Validates *desc, factors each length into radices
+ * {16, 8, 4, 2, 3, 5, 7}, chooses the kernels (single pass through LDS, or the
+ * two-pass four-step decomposition for lengths that do not fit on chip, or the
+ * MFMA DFT-16 form, or the ragged persistent kernel), builds the twiddle
+ * tables in FP64 on the host, rounds them to the kernel precision and uploads
+ * them (hipMalloc + copy; this call may synchronize the device).
+ *   out        receives the handle (set to NULL on failure)
+ *   desc       host pointer, read only during the call
+ *   hip_stream stream used for the table uploads (NULL = default)
+ * Supported: 1 <= N <= 2^24 with all prime factors <= 7 (FFT_E_UNSUPPORTED
+ * otherwise); batch >= 0; rank 2 with each side a power of two <= 16384.
+ */
+fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream);
+
+/*
+ * Execute a plan: transform `in` into `out` (device pointers, interleaved
+ * complex64, laid out as described by the plan's desc).  direction is
+ * FFT_FORWARD or FFT_INVERSE (the inverse includes the 1/N scale).
+ *   workspace  device buffer of at least fft_workspace_bytes(plan) bytes,
+ *              owned by the caller; may be NULL when that size is 0
+ *   hip_stream stream to enqueue on (NULL = default stream)
+ * in == out requires FFT_F_INPLACE at plan time; partial overlap is undefined.
+ * `in` is not modified unless in == out.  Asynchronous: returns after the
+ * launches are enqueued.
+ */
+fft_status_t fft_exec(fft_plan_t plan, const void *in, void *out, int direction,
+                      void *workspace, void *hip_stream);
+
+/* Release a plan and its device tables.  fft_destroy(NULL) returns FFT_OK.
+ * The caller must ensure no execution of the plan is still pending. */
+fft_status_t fft_destroy(fft_plan_t plan);
+
+/* Device workspace bytes fft_exec needs for this plan (0 = none). */
+size_t fft_workspace_bytes(fft_plan_t plan);
+
+/* Static string naming a status code. */
+const char *fft_status_str(fft_status_t s);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *fft_last_error(void);
+
+/* Human-readable description of the plan (variant, radices, kernels, grid,
+ * LDS bytes, HBM passes) written into buf (NUL-terminated, truncated to len).
+ * Returns the number of characters the full description needs. */
+size_t fft_plan_describe(fft_plan_t plan, char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPFFT_H */

@@ -1,0 +1,261 @@
+"""dpfft: batched complex-to-complex FFTs on an AMD MI355X (gfx950).
+
+Thin ctypes binding of ``libdpfft.so`` (see ``include/dpfft.h``).  The
+functions ``fft_plan``, ``fft_exec``, ``fft_destroy``, ``fft_workspace_bytes``,
+``fft_status_str``, ``fft_last_error`` and ``fft_plan_describe`` mirror the C
+entry points one to one and only marshal arguments; :class:`Plan` wraps them
+for torch tensors (device memory and the current stream come from torch).
+Every transform runs in the library's HIP kernels; there is no fallback: if
+the library is missing or fails to load, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch  # loaded first so the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpfft.so")
+
+FFT_OK, FFT_E_INVALID, FFT_E_UNSUPPORTED, FFT_E_NOMEM, FFT_E_DEVICE, FFT_E_INTERNAL = range(6)
+FFT_FORWARD, FFT_INVERSE = -1, +1
+FFT_F_INPLACE, FFT_F_NO_AUTOTUNE, FFT_F_GRAPH = 1, 2, 4
+PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4, "bf16_split3": 5}
+
+#: names of every C entry point declared in include/dpfft.h
+EXPORTS = ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
+           "fft_last_error", "fft_plan_describe")
+
+
+class FftError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        self.status = status
+        super().__init__(f"{where}: {_status_name(status)}: {msg}")
+
+
+class FftDesc(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("n", ctypes.c_int64 * 2), ("batch", ctypes.c_int64),
+                ("dist", ctypes.c_int64), ("ragged_sizes", ctypes.POINTER(ctypes.c_int64)),
+                ("ragged_offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1203_4938_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.fft_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(FftDesc), vp]
+    lib.fft_plan.restype = ctypes.c_int
+    lib.fft_exec.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
+    lib.fft_exec.restype = ctypes.c_int
+    lib.fft_destroy.argtypes = [vp]
+    lib.fft_destroy.restype = ctypes.c_int
+    lib.fft_workspace_bytes.argtypes = [vp]
+    lib.fft_workspace_bytes.restype = ctypes.c_size_t
+    lib.fft_status_str.argtypes = [ctypes.c_int]
+    lib.fft_status_str.restype = ctypes.c_char_p
+    lib.fft_last_error.argtypes = []
+    lib.fft_last_error.restype = ctypes.c_char_p
+    lib.fft_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.fft_plan_describe.restype = ctypes.c_size_t
+    return lib
+
+
+_lib = _load()
+
+
+def _status_name(s: int) -> str:
+    return _lib.fft_status_str(s).decode()
+
+
+# ---------------------------------------------------------------------------
+# one-to-one wrappers of the C entry points
+# ---------------------------------------------------------------------------
+def fft_status_str(status: int) -> str:
+    return _status_name(status)
+
+
+def fft_last_error() -> str:
+    return _lib.fft_last_error().decode()
+
+
+def fft_plan(desc: FftDesc, stream: int = 0) -> tuple[int, Optional[int]]:
+    """Returns (status, handle or None)."""
+    h = ctypes.c_void_p()
+    st = _lib.fft_plan(ctypes.byref(h), ctypes.byref(desc), ctypes.c_void_p(stream))
+    return st, (h.value if st == FFT_OK else None)
+
+
+def fft_exec(handle: int, in_ptr: int, out_ptr: int, direction: int, workspace: int = 0,
+             stream: int = 0) -> int:
+    return _lib.fft_exec(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                         direction, ctypes.c_void_p(workspace), ctypes.c_void_p(stream))
+
+
+def fft_destroy(handle: Optional[int]) -> int:
+    return _lib.fft_destroy(ctypes.c_void_p(handle))
+
+
+def fft_workspace_bytes(handle: Optional[int]) -> int:
+    return _lib.fft_workspace_bytes(ctypes.c_void_p(handle))
+
+
+def fft_plan_describe(handle: Optional[int]) -> str:
+    need = _lib.fft_plan_describe(ctypes.c_void_p(handle), None, 0)
+    buf = ctypes.create_string_buffer(need + 1)
+    _lib.fft_plan_describe(ctypes.c_void_p(handle), buf, need + 1)
+    return buf.value.decode()
+
+
+def make_desc(n=None, batch: int = 1, *, rank: int = 1, shape=None, dist: int = 0,
+              ragged_sizes: Optional[Sequence[int]] = None,
+              ragged_offsets: Optional[Sequence[int]] = None,
+              precision: str = "fp32", flags: int = 0):
+    """Builds an FftDesc; returns (desc, keepalive) -- keep the second alive
+    while the desc is in use (it owns the ragged arrays)."""
+    d = FftDesc()
+    d.rank = rank
+    if rank == 2:
+        d.n[0], d.n[1] = int(shape[0]), int(shape[1])
+    else:
+        d.n[0] = int(n) if n is not None else 0
+    d.batch = int(batch)
+    d.dist = int(dist)
+    keep = []
+    if ragged_sizes is not None:
+        arr = (ctypes.c_int64 * len(ragged_sizes))(*[int(v) for v in ragged_sizes])
+        keep.append(arr)
+        d.ragged_sizes = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int64))
+        d.batch = len(ragged_sizes)
+    if ragged_offsets is not None:
+        arr = (ctypes.c_int64 * len(ragged_offsets))(*[int(v) for v in ragged_offsets])
+        keep.append(arr)
+        d.ragged_offsets = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int64))
+    d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d.flags = flags
+    return d, keep
+
+
+# ---------------------------------------------------------------------------
+# torch-facing plan object
+# ---------------------------------------------------------------------------
+class Plan:
+    """A dpfft plan for torch complex64 CUDA tensors.
+
+    ``Plan(n, batch)`` -- batch of length-n signals (last axis);
+    ``Plan(shape=(ny, nx), batch=b, rank=2)`` -- batch of images;
+    ``Plan(ragged_sizes=[...])`` -- ragged batch packed back to back.
+    """
+
+    def __init__(self, n: Optional[int] = None, batch: int = 1, *, rank: int = 1, shape=None,
+                 dist: int = 0, ragged_sizes=None, ragged_offsets=None, precision: str = "fp32",
+                 inplace: bool = False, graph: bool = False, autotune: bool = True, stream=None):
+        flags = (FFT_F_INPLACE if inplace else 0) | (FFT_F_GRAPH if graph else 0) | \
+                (0 if autotune else FFT_F_NO_AUTOTUNE)
+        self.desc, self._keep = make_desc(n, batch, rank=rank, shape=shape, dist=dist,
+                                          ragged_sizes=ragged_sizes, ragged_offsets=ragged_offsets,
+                                          precision=precision, flags=flags)
+        self.rank = rank
+        self.batch = int(self.desc.batch)
+        self.ragged = ragged_sizes is not None
+        if self.ragged:
+            sizes = [int(v) for v in ragged_sizes]
+            if ragged_offsets is None:
+                offs, acc = [], 0
+                for v in sizes:
+                    offs.append(acc)
+                    acc += v
+            else:
+                offs = [int(v) for v in ragged_offsets]
+            self.sizes, self.offsets = sizes, offs
+            self.numel = max((o + s for o, s in zip(offs, sizes)), default=0)
+        else:
+            per = int(self.desc.n[0]) * (int(self.desc.n[1]) if rank == 2 else 1)
+            d = int(dist) if dist else per
+            self.numel = (self.batch - 1) * d + per if self.batch else 0
+        s = _stream_handle(stream)
+        st, h = fft_plan(self.desc, s)
+        if st != FFT_OK:
+            raise FftError(st, "fft_plan", fft_last_error())
+        self.handle = h
+        self.workspace_bytes = fft_workspace_bytes(h)
+        self._ws = None
+
+    def describe(self) -> str:
+        return fft_plan_describe(self.handle)
+
+    def workspace(self, device) -> Optional[torch.Tensor]:
+        if self.workspace_bytes == 0:
+            return None
+        if self._ws is None or self._ws.device != device:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def exec(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, inverse: bool = False,
+             stream=None) -> torch.Tensor:
+        _check_tensor(x, self.numel, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            _check_tensor(out, self.numel, "out")
+        ws = self.workspace(x.device)
+        st = fft_exec(self.handle, x.data_ptr(), out.data_ptr(),
+                      FFT_INVERSE if inverse else FFT_FORWARD,
+                      ws.data_ptr() if ws is not None else 0, _stream_handle(stream))
+        if st != FFT_OK:
+            raise FftError(st, "fft_exec", fft_last_error())
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return 0
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _check_tensor(t: torch.Tensor, numel: int, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be complex64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, the plan needs {numel}")
+
+
+_cache: dict = {}
+
+
+def fft(x: torch.Tensor, inverse: bool = False) -> torch.Tensor:
+    """Batched FFT over the last axis of a contiguous complex64 CUDA tensor."""
+    n = x.shape[-1]
+    b = x.numel() // n if n else 0
+    key = (n, b)
+    p = _cache.get(key)
+    if p is None:
+        p = _cache[key] = Plan(n, b)
+    return p.exec(x, inverse=inverse)
+
+
+def ifft(x: torch.Tensor) -> torch.Tensor:
+    return fft(x, inverse=True)

@@ -1,0 +1,432 @@
+// C ABI of dpfft: validation, plan construction and execution.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <sstream>
+#include <string>
+
+#include "plan.h"
+#include "twiddle.h"
+
+using namespace dpfft;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fft_status_t fail(fft_status_t s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v) {
+  int k = 0;
+  while ((int64_t(1) << k) < v) ++k;
+  return k;
+}
+
+// largest prime factor of n (1 for n == 1)
+int64_t largest_prime_factor(int64_t n) {
+  int64_t best = 1;
+  for (int64_t p = 2; p * p <= n; ++p)
+    while (n % p == 0) {
+      best = p;
+      n /= p;
+    }
+  return n > 1 ? n : best;
+}
+
+constexpr int64_t kMaxN = int64_t(1) << 24;
+constexpr int kSinglePassMax = 16384;  // largest L of a one-workgroup transform
+constexpr int kLdsBytes = 160 * 1024;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// TableSet / steps
+// ---------------------------------------------------------------------------
+namespace dpfft {
+
+static void align_tables(std::vector<float2> &h) {
+  while (h.size() % 32) h.push_back(make_float2(0.f, 0.f));  // 256-byte alignment
+}
+
+size_t TableSet::add(const std::vector<std::complex<double>> &t) {
+  align_tables(host);
+  size_t off = host.size();
+  for (const auto &w : t) host.push_back(make_float2((float)w.real(), (float)w.imag()));
+  return off;
+}
+
+size_t TableSet::add_raw(const std::vector<float2> &t) {
+  align_tables(host);
+  size_t off = host.size();
+  host.insert(host.end(), t.begin(), t.end());
+  return off;
+}
+
+size_t TableSet::add_bytes(const void *p, size_t bytes) {
+  align_tables(host);
+  size_t off = host.size();
+  size_t n = (bytes + sizeof(float2) - 1) / sizeof(float2);
+  host.resize(off + n, make_float2(0.f, 0.f));
+  memcpy(host.data() + off, p, bytes);
+  return off;
+}
+
+void LineStep::bind(const float2 *tables) {
+  a.tw = tables + tw_off;
+  if (has_tw4) {
+    a.tw4_lo = tables + tw4_lo_off;
+    a.tw4_hi = tables + tw4_hi_off;
+  }
+}
+
+hipError_t LineStep::launch(const ExecCtx &ctx) const {
+  LineArgs args = a;
+  if (ctx.inverse) {
+    if (first) args.flags |= F_SWAP_IN;
+    if (last) {
+      args.flags |= F_SWAP_OUT;
+      args.scale = inv_scale;
+    }
+  }
+  const float2 *s = buf_c(ctx, src, 0);
+  float2 *d = buf_m(ctx, dst, 0);
+  void *kargs[] = {(void *)&s, (void *)&d, (void *)&args};
+  return hipLaunchKernel(k.fn, grid, dim3(k.threads), kargs, 0, ctx.stream);
+}
+
+void LineStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const {
+  const int64_t nb = (int64_t)grid.x / a.tiles_per_batch;  // batch items covered by the grid
+  const int64_t last_line = std::min<int64_t>(a.lines, a.tiles_per_batch * k.lines) - 1;
+  max_in = (nb - 1) * a.in_b + last_line * a.in_l + (int64_t)(L - 1) * a.in_e;
+  max_out = (nb - 1) * a.out_b + last_line * a.out_l + (int64_t)(L - 1) * a.out_e;
+  src_id = src;
+  dst_id = dst;
+}
+
+std::string LineStep::describe() const {
+  std::ostringstream o;
+  o << name << ": L=" << L << " C=" << k.lines << " threads=" << k.threads
+    << " grid=" << grid.x << " lds=" << k.lds_bytes << "B";
+  return o.str();
+}
+
+}  // namespace dpfft
+
+dpfft_plan_s::~dpfft_plan_s() {
+  if (tables.dev) (void)hipFree(tables.dev);
+}
+
+// ---------------------------------------------------------------------------
+// plan builders
+// ---------------------------------------------------------------------------
+namespace {
+
+std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, int C, int map,
+                                    int omap, bool tw4) {
+  auto s = std::make_unique<LineStep>();
+  if (!find_line_kernel(L, C, map, omap, tw4, &s->k)) return nullptr;
+  s->L = L;
+  s->name = name;
+  s->tw_off = P->tables.add(stockham_table_pow2(L));
+  s->a.scale = 1.0f;
+  return s;
+}
+
+fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
+  const int64_t N = P->n, B = P->batch, D = P->dist;
+  if (N <= kSinglePassMax) {
+    const int L = (int)N;
+    int C = best_line_c(L, ELEM_FAST, ELEM_FAST, false, 256);
+    auto s = make_line(P, "stockham_rows", L, C, ELEM_FAST, ELEM_FAST, false);
+    if (!s) return fail(FFT_E_INTERNAL, "no row kernel for L=" + std::to_string(L));
+    s->a.in_b = s->a.out_b = 0;
+    s->a.in_l = s->a.out_l = D;
+    s->a.in_e = s->a.out_e = 1;
+    s->a.lines = B;
+    s->a.tiles_per_batch = (B + C - 1) / C;
+    s->grid = dim3((unsigned)s->a.tiles_per_batch);
+    s->first = s->last = true;
+    s->inv_scale = (float)(1.0 / (double)N);
+    s->src = BUF_IN;
+    s->dst = BUF_OUT;
+    P->steps.push_back(std::move(s));
+    P->variant = "single-pass";
+    return FFT_OK;
+  }
+  // four-step: N = N1 * N2, x[n1*N2 + n2]; pass A: N1-point column FFTs
+  // (stride N2) and twiddle w_N^{n2 k1} into the workspace Y[k1][n2]; pass B:
+  // N2-point FFTs along the rows of Y, stored transposed: X[k1 + N1 k2].
+  const int lg = ilog2(N);
+  const int N1 = 1 << (lg / 2), N2 = 1 << (lg - lg / 2);
+  const int CA = best_line_c(N1, LINE_FAST, LINE_FAST, true, 16);
+  const int CB = best_line_c(N2, ELEM_FAST, LINE_FAST, false, 16);
+  if (!CA || !CB) return fail(FFT_E_UNSUPPORTED, "no four-step kernels for N=" + std::to_string(N));
+  auto a = make_line(P, "fourstep_columns", N1, CA, LINE_FAST, LINE_FAST, true);
+  auto b = make_line(P, "fourstep_rows_transposed", N2, CB, ELEM_FAST, LINE_FAST, false);
+  if (!a || !b) return fail(FFT_E_INTERNAL, "four-step kernel lookup failed");
+  std::vector<std::complex<double>> lo, hi;
+  const int shift = (lg + 1) / 2;
+  fourstep_tables(N, shift, lo, hi);
+  a->has_tw4 = true;
+  a->tw4_lo_off = P->tables.add(lo);
+  a->tw4_hi_off = P->tables.add(hi);
+  a->a.tw4_shift = shift;
+  a->a.in_b = D;
+  a->a.in_l = 1;
+  a->a.in_e = N2;
+  a->a.out_b = N;
+  a->a.out_l = 1;
+  a->a.out_e = N2;
+  a->a.lines = N2;
+  a->a.tiles_per_batch = N2 / CA;
+  a->a.flags = F_REMAP;
+  a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
+  a->first = true;
+  a->src = BUF_IN;
+  a->dst = BUF_WS;
+
+  b->a.in_b = N;
+  b->a.in_l = N2;
+  b->a.in_e = 1;
+  b->a.out_b = D;
+  b->a.out_l = 1;
+  b->a.out_e = N1;
+  b->a.lines = N1;
+  b->a.tiles_per_batch = N1 / CB;
+  b->a.flags = F_REMAP;
+  b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
+  b->last = true;
+  b->inv_scale = (float)(1.0 / (double)N);
+  b->src = BUF_WS;
+  b->dst = BUF_OUT;
+  P->steps.push_back(std::move(a));
+  P->steps.push_back(std::move(b));
+  P->ws_bytes = (size_t)B * (size_t)N * sizeof(float2);
+  P->variant = "four-step " + std::to_string(N1) + "x" + std::to_string(N2);
+  return FFT_OK;
+}
+
+fft_status_t plan_pow2_2d(dpfft_plan_s *P) {
+  const int64_t NY = P->ny, NX = P->nx, B = P->batch, D = P->dist;
+  const int CR = best_line_c((int)NX, ELEM_FAST, ELEM_FAST, false, 256);
+  const int CC = best_line_c((int)NY, LINE_FAST, LINE_FAST, false, 64);
+  if (!CR || !CC) return fail(FFT_E_UNSUPPORTED, "no 2D kernels for this shape");
+  // row pass: in -> out; column pass: in place on out (column tiles read and
+  // written by the same workgroup, so no transpose and no workspace)
+  auto r = make_line(P, "rows", (int)NX, CR, ELEM_FAST, ELEM_FAST, false);
+  auto c = make_line(P, "columns", (int)NY, CC, LINE_FAST, LINE_FAST, false);
+  if (!r || !c) return fail(FFT_E_INTERNAL, "2D kernel lookup failed");
+  r->a.in_b = r->a.out_b = D;
+  r->a.in_l = r->a.out_l = NX;
+  r->a.in_e = r->a.out_e = 1;
+  r->a.lines = NY;
+  r->a.tiles_per_batch = (NY + CR - 1) / CR;
+  r->grid = dim3((unsigned)(B * r->a.tiles_per_batch));
+  r->first = true;
+  r->src = BUF_IN;
+  r->dst = BUF_OUT;
+  c->a.in_b = c->a.out_b = D;
+  c->a.in_l = c->a.out_l = 1;
+  c->a.in_e = c->a.out_e = NX;
+  c->a.lines = NX;
+  c->a.tiles_per_batch = (NX + CC - 1) / CC;
+  c->a.flags = F_REMAP;
+  c->grid = dim3((unsigned)(B * c->a.tiles_per_batch));
+  c->last = true;
+  c->inv_scale = (float)(1.0 / ((double)NX * (double)NY));
+  c->src = BUF_OUT;
+  c->dst = BUF_OUT;
+  P->steps.push_back(std::move(r));
+  P->steps.push_back(std::move(c));
+  P->variant = "2d rows+columns";
+  return FFT_OK;
+}
+
+fft_status_t validate_desc(const fft_desc_t *d) {
+  if (!d) return fail(FFT_E_INVALID, "desc is NULL");
+  if (d->rank != 1 && d->rank != 2) return fail(FFT_E_INVALID, "rank must be 1 or 2");
+  if (d->batch < 0) return fail(FFT_E_INVALID, "batch must be >= 0");
+  if (d->dist < 0) return fail(FFT_E_INVALID, "dist must be >= 0");
+  if (d->precision < FFT_FP32 || d->precision > FFT_BF16_SPLIT3)
+    return fail(FFT_E_INVALID, "unknown precision");
+  if (d->flags & ~(FFT_F_INPLACE | FFT_F_NO_AUTOTUNE | FFT_F_GRAPH))
+    return fail(FFT_E_INVALID, "unknown flag bits");
+  if (d->ragged_offsets && !d->ragged_sizes)
+    return fail(FFT_E_INVALID, "ragged_offsets given without ragged_sizes");
+  if (d->rank == 1) {
+    if (d->ragged_sizes) {
+      for (int64_t i = 0; i < d->batch; ++i) {
+        int64_t n = d->ragged_sizes[i];
+        if (n <= 0) return fail(FFT_E_INVALID, "ragged size must be >= 1");
+        if (n > kMaxN) return fail(FFT_E_UNSUPPORTED, "ragged size above 2^24");
+        if (largest_prime_factor(n) > 7)
+          return fail(FFT_E_UNSUPPORTED, "ragged size has a prime factor above 7");
+        if (d->ragged_offsets && d->ragged_offsets[i] < 0)
+          return fail(FFT_E_INVALID, "ragged offset must be >= 0");
+      }
+      return FFT_OK;
+    }
+    const int64_t n = d->n[0];
+    if (n <= 0) return fail(FFT_E_INVALID, "N must be >= 1");
+    if (n > kMaxN) return fail(FFT_E_UNSUPPORTED, "N above 2^24");
+    if (largest_prime_factor(n) > 7) return fail(FFT_E_UNSUPPORTED, "N has a prime factor above 7");
+    if (d->dist != 0 && d->dist < n) return fail(FFT_E_INVALID, "dist must be 0 or >= N");
+  } else {
+    if (d->ragged_sizes) return fail(FFT_E_INVALID, "ragged batches are rank 1 only");
+    if (d->n[0] <= 0 || d->n[1] <= 0) return fail(FFT_E_INVALID, "image sides must be >= 1");
+    if (!is_pow2(d->n[0]) || !is_pow2(d->n[1]) || d->n[0] > kSinglePassMax ||
+        d->n[1] > kSinglePassMax)
+      return fail(FFT_E_UNSUPPORTED, "rank 2 needs power-of-two sides <= 16384");
+    if (d->dist != 0 && d->dist < d->n[0] * d->n[1])
+      return fail(FFT_E_INVALID, "dist must be 0 or >= ny*nx");
+  }
+  return FFT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fft_status_str(fft_status_t s) {
+  switch (s) {
+    case FFT_OK: return "FFT_OK";
+    case FFT_E_INVALID: return "FFT_E_INVALID";
+    case FFT_E_UNSUPPORTED: return "FFT_E_UNSUPPORTED";
+    case FFT_E_NOMEM: return "FFT_E_NOMEM";
+    case FFT_E_DEVICE: return "FFT_E_DEVICE";
+    case FFT_E_INTERNAL: return "FFT_E_INTERNAL";
+  }
+  return "FFT_E_UNKNOWN";
+}
+
+const char *fft_last_error(void) { return g_last_error.c_str(); }
+
+fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream) {
+  if (!out) return fail(FFT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fft_status_t st = validate_desc(desc);
+  if (st != FFT_OK) return st;
+  auto P = std::make_unique<dpfft_plan_s>();
+  P->rank = desc->rank;
+  P->batch = desc->batch;
+  P->precision = desc->precision;
+  P->flags = desc->flags;
+  if (desc->rank == 1) {
+    P->n = desc->n[0];
+    P->dist = desc->dist ? desc->dist : desc->n[0];
+  } else {
+    P->ny = desc->n[0];
+    P->nx = desc->n[1];
+    P->dist = desc->dist ? desc->dist : desc->n[0] * desc->n[1];
+  }
+  if (desc->rank == 1 && desc->ragged_sizes)
+    return fail(FFT_E_UNSUPPORTED, "ragged batches are not implemented yet");
+  if (desc->precision != FFT_FP32)
+    return fail(FFT_E_UNSUPPORTED, "only FFT_FP32 is implemented for this shape");
+
+  if (desc->rank == 1) {
+    if (!is_pow2(P->n)) return fail(FFT_E_UNSUPPORTED, "mixed-radix lengths are not implemented yet");
+    st = plan_pow2_1d(P.get());
+  } else {
+    st = plan_pow2_2d(P.get());
+  }
+  if (st != FFT_OK) return st;
+
+  // every index a kernel forms must stay inside its buffer
+  P->io_elems = P->batch == 0 ? 0
+                : P->rank == 1 ? (P->batch - 1) * P->dist + P->n
+                               : (P->batch - 1) * P->dist + P->ny * P->nx;
+  if (P->batch > 0) {
+    for (auto &s : P->steps) {
+      int64_t mi, mo;
+      int si, di;
+      s->extent(mi, mo, si, di);
+      auto cap = [&](int id) -> int64_t {
+        return id == BUF_WS ? (int64_t)(P->ws_bytes / sizeof(float2)) : P->io_elems;
+      };
+      if (mi >= cap(si) || mo >= cap(di))
+        return fail(FFT_E_INTERNAL, "plan bounds check failed in " + s->describe());
+    }
+  }
+
+  // upload every table in one allocation
+  hipStream_t stream = (hipStream_t)hip_stream;
+  size_t bytes = P->tables.host.size() * sizeof(float2);
+  if (bytes) {
+    hipError_t e = hipMalloc((void **)&P->tables.dev, bytes);
+    if (e != hipSuccess) {
+      P->tables.dev = nullptr;
+      return fail(e == hipErrorOutOfMemory ? FFT_E_NOMEM : FFT_E_DEVICE,
+                  std::string("hipMalloc(tables): ") + hipGetErrorString(e));
+    }
+    e = hipMemcpyAsync(P->tables.dev, P->tables.host.data(), bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+      return fail(FFT_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+  }
+  for (auto &s : P->steps) s->bind(P->tables.dev);
+
+  std::ostringstream o;
+  if (P->rank == 1)
+    o << "rank=1 N=" << P->n;
+  else
+    o << "rank=2 ny=" << P->ny << " nx=" << P->nx;
+  o << " batch=" << P->batch << " dist=" << P->dist << " variant=" << P->variant
+    << " hbm_passes=" << P->steps.size() << " workspace=" << P->ws_bytes << "B"
+    << " tables=" << bytes << "B";
+  for (auto &s : P->steps) o << "\n  " << s->describe();
+  P->text = o.str();
+  if (getenv("DPFFT_LOG")) fprintf(stderr, "[dpfft] plan %s\n", P->text.c_str());
+  *out = P.release();
+  return FFT_OK;
+}
+
+fft_status_t fft_exec(fft_plan_t plan, const void *in, void *out, int direction, void *workspace,
+                      void *hip_stream) {
+  if (!plan) return fail(FFT_E_INVALID, "plan is NULL");
+  if (direction != FFT_FORWARD && direction != FFT_INVERSE)
+    return fail(FFT_E_INVALID, "direction must be FFT_FORWARD or FFT_INVERSE");
+  if (plan->batch == 0) return FFT_OK;
+  if (!in || !out) return fail(FFT_E_INVALID, "in/out is NULL");
+  if (((uintptr_t)in | (uintptr_t)out) & 7u) return fail(FFT_E_INVALID, "in/out not 8-byte aligned");
+  if (in == out && !(plan->flags & FFT_F_INPLACE))
+    return fail(FFT_E_INVALID, "in == out needs FFT_F_INPLACE");
+  if (plan->ws_bytes && !workspace) return fail(FFT_E_INVALID, "plan needs a workspace");
+  ExecCtx ctx{in, out, workspace, (hipStream_t)hip_stream, direction == FFT_INVERSE};
+  for (auto &s : plan->steps) {
+    hipError_t e = s->launch(ctx);
+    if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  }
+  return FFT_OK;
+}
+
+fft_status_t fft_destroy(fft_plan_t plan) {
+  delete plan;
+  return FFT_OK;
+}
+
+size_t fft_workspace_bytes(fft_plan_t plan) { return plan ? plan->ws_bytes : 0; }
+
+size_t fft_plan_describe(fft_plan_t plan, char *buf, size_t len) {
+  if (!plan) return 0;
+  const std::string &t = plan->text;
+  if (buf && len) {
+    size_t n = t.size() < len - 1 ? t.size() : len - 1;
+    memcpy(buf, t.data(), n);
+    buf[n] = 0;
+  }
+  return t.size();
+}
+
+}  // extern "C"

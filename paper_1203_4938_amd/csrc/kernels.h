@@ -1,0 +1,88 @@
+// Host-visible descriptions of the device kernels: argument blocks and the
+// registry that maps a kernel shape to its compiled instance.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpfft {
+
+// Lane-to-data mapping of a line kernel.  ELEM_FAST: consecutive lanes walk
+// along a line (rows, contiguous signals).  LINE_FAST: consecutive lanes walk
+// across lines (column tiles of a row-major matrix).
+enum : int { ELEM_FAST = 0, LINE_FAST = 1 };
+
+enum : uint32_t {
+  F_SWAP_IN = 1u,   // exchange re/im on load (inverse transform)
+  F_SWAP_OUT = 2u,  // exchange re/im on store (inverse transform)
+  F_REMAP = 4u,     // XCD-aware workgroup -> tile order
+};
+
+// One launch of a line kernel: length-L transforms of `lines` lines per batch
+// item; element (batch b, line l, index i) lives at
+//   base + b*x_b + l*x_l + i*x_e   (in complex elements).
+struct LineArgs {
+  int64_t in_b, in_l, in_e;
+  int64_t out_b, out_l, out_e;
+  int64_t lines;           // lines per batch item
+  int64_t tiles_per_batch; // ceil(lines / C)
+  const float2 *tw;        // Stockham pass twiddles for length L
+  const float2 *tw4_lo;    // four-step twiddles w_N^l, l < 2^tw4_shift
+  const float2 *tw4_hi;    // four-step twiddles w_N^{h 2^tw4_shift}
+  int32_t tw4_shift;
+  float scale;             // applied to every output (1 or 1/N)
+  uint32_t flags;
+};
+
+// Radix plan of the power-of-two line kernels, shared by the device code and
+// the host twiddle generator.  E elements per thread, T threads per line,
+// NP passes: radix 16 first, then one radix 2/4/8 remainder pass.
+template <int L> struct P2 {
+  static constexpr int lg() {
+    int k = 0;
+    while ((1 << k) < L) ++k;
+    return k;
+  }
+  static constexpr int LG = lg();
+  static constexpr int E = L >= 16 ? 16 : L;
+  static constexpr int T = L / E;
+  static constexpr int NP = (LG + 3) / 4;
+  static constexpr int radix(int p) { return (p < LG / 4) ? 16 : (1 << (LG % 4)); }
+  static constexpr int ns(int p) {
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= radix(i);
+    return s;
+  }
+  static constexpr int twoff(int p) {
+    int o = 0;
+    for (int i = 1; i < p; ++i) o += ns(i) * (radix(i) - 1);
+    return o;
+  }
+};
+
+// Runtime twin of P2<L> for the host.
+inline int pow2_radix(int L, int p) {
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  return (p < lg / 4) ? 16 : (1 << (lg % 4));
+}
+inline int pow2_passes(int L) {
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  return (lg + 3) / 4;
+}
+
+struct KernelInfo {
+  const void *fn = nullptr;
+  int threads = 0;      // workgroup size
+  int lines = 0;        // lines per workgroup (C)
+  int lds_bytes = 0;    // static LDS of the instance
+};
+
+// Power-of-two line kernel with compile-time length L and C lines per
+// workgroup.  tw4 = apply the four-step twiddle w_N^{line*i} before the store.
+bool find_line_kernel(int L, int C, int map, int omap, bool tw4, KernelInfo *out);
+
+// Largest C available for (L, map, omap, tw4) with C <= cmax; 0 if none.
+int best_line_c(int L, int map, int omap, bool tw4, int cmax);
+
+}  // namespace dpfft

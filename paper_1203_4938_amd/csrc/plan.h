@@ -1,0 +1,92 @@
+// Plan object: an ordered list of kernel launches plus the device tables they
+// read.  Built once by fft_plan, replayed by fft_exec.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <complex>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dpfft.h"
+#include "kernels.h"
+
+namespace dpfft {
+
+enum BufId : int { BUF_IN = 0, BUF_OUT = 1, BUF_WS = 2 };
+
+struct ExecCtx {
+  const void *in;
+  void *out;
+  void *ws;
+  hipStream_t stream;
+  bool inverse;
+};
+
+inline const float2 *buf_c(const ExecCtx &c, int id, int64_t off) {
+  const float2 *p = id == BUF_IN ? (const float2 *)c.in
+                    : id == BUF_OUT ? (const float2 *)c.out
+                                    : (const float2 *)c.ws;
+  return p + off;
+}
+inline float2 *buf_m(const ExecCtx &c, int id, int64_t off) {
+  float2 *p = id == BUF_IN ? (float2 *)c.in : id == BUF_OUT ? (float2 *)c.out : (float2 *)c.ws;
+  return p + off;
+}
+
+// Host staging for all device tables of a plan: one allocation per plan.
+struct TableSet {
+  std::vector<float2> host;
+  size_t add(const std::vector<std::complex<double>> &t);  // returns element offset
+  size_t add_raw(const std::vector<float2> &t);
+  size_t add_bytes(const void *p, size_t bytes);           // 8-byte units
+  float2 *dev = nullptr;
+};
+
+struct Step {
+  virtual ~Step() = default;
+  // resolve table offsets against the uploaded device tables
+  virtual void bind(const float2 *tables) = 0;
+  virtual hipError_t launch(const ExecCtx &ctx) const = 0;
+  virtual std::string describe() const = 0;
+  // largest element index read from `src` / written to `dst` (-1 = none)
+  virtual void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const = 0;
+};
+
+struct LineStep : Step {
+  KernelInfo k;
+  int L = 0;
+  dim3 grid;
+  int src = BUF_IN, dst = BUF_OUT;
+  LineArgs a{};
+  size_t tw_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
+  bool has_tw4 = false;
+  bool first = false, last = false;  // receive the inverse swap / scale
+  float inv_scale = 1.0f;
+  std::string name;
+  void bind(const float2 *tables) override;
+  hipError_t launch(const ExecCtx &ctx) const override;
+  std::string describe() const override;
+  void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
+};
+
+}  // namespace dpfft
+
+struct dpfft_plan_s {
+  int32_t rank = 1;
+  int64_t n = 0;              // rank 1 length
+  int64_t ny = 0, nx = 0;     // rank 2
+  int64_t batch = 0;
+  int64_t dist = 0;
+  int32_t precision = FFT_FP32;
+  uint32_t flags = 0;
+  std::vector<int64_t> rsizes, roffsets;  // ragged
+  std::vector<std::unique_ptr<dpfft::Step>> steps;
+  dpfft::TableSet tables;
+  size_t ws_bytes = 0;
+  int64_t io_elems = 0;       // complex elements of `in` / `out` the plan touches
+  std::string variant;
+  std::string text;  // fft_plan_describe output
+  ~dpfft_plan_s();
+};
