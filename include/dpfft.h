@@ -120,6 +120,16 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
 fft_status_t fft_exec(fft_plan_t plan, const void *in, void *out, int direction,
                       void *workspace, void *hip_stream);
 
+/* Number of kernel launches one fft_exec of this plan enqueues (0 if plan is
+ * NULL). */
+int fft_plan_num_steps(fft_plan_t plan);
+
+/* Enqueue only launches [first, first + count) of fft_exec (for timing one
+ * kernel at a time and for tests).  Same arguments, ownership and errors as
+ * fft_exec; FFT_E_INVALID if the range is outside [0, fft_plan_num_steps). */
+fft_status_t fft_exec_steps(fft_plan_t plan, const void *in, void *out, int direction,
+                            void *workspace, void *hip_stream, int first, int count);
+
 /* Release a plan and its device tables.  fft_destroy(NULL) returns FFT_OK.
  * The caller must ensure no execution of the plan is still pending. */
 fft_status_t fft_destroy(fft_plan_t plan);

@@ -26,7 +26,7 @@ PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4,
 
 #: names of every C entry point declared in include/dpfft.h
 EXPORTS = ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
-           "fft_last_error", "fft_plan_describe")
+           "fft_last_error", "fft_plan_describe", "fft_plan_num_steps", "fft_exec_steps")
 
 
 class FftError(RuntimeError):
@@ -62,6 +62,10 @@ def _load() -> ctypes.CDLL:
     lib.fft_last_error.restype = ctypes.c_char_p
     lib.fft_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.fft_plan_describe.restype = ctypes.c_size_t
+    lib.fft_plan_num_steps.argtypes = [vp]
+    lib.fft_plan_num_steps.restype = ctypes.c_int
+    lib.fft_exec_steps.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int]
+    lib.fft_exec_steps.restype = ctypes.c_int
     return lib
 
 
@@ -94,6 +98,17 @@ def fft_exec(handle: int, in_ptr: int, out_ptr: int, direction: int, workspace: 
              stream: int = 0) -> int:
     return _lib.fft_exec(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
                          direction, ctypes.c_void_p(workspace), ctypes.c_void_p(stream))
+
+
+def fft_plan_num_steps(handle: Optional[int]) -> int:
+    return _lib.fft_plan_num_steps(ctypes.c_void_p(handle))
+
+
+def fft_exec_steps(handle: int, in_ptr: int, out_ptr: int, direction: int, workspace: int,
+                   stream: int, first: int, count: int) -> int:
+    return _lib.fft_exec_steps(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr),
+                               ctypes.c_void_p(out_ptr), direction, ctypes.c_void_p(workspace),
+                               ctypes.c_void_p(stream), first, count)
 
 
 def fft_destroy(handle: Optional[int]) -> int:
@@ -208,6 +223,21 @@ class Plan:
                       ws.data_ptr() if ws is not None else 0, _stream_handle(stream))
         if st != FFT_OK:
             raise FftError(st, "fft_exec", fft_last_error())
+        return out
+
+    def num_steps(self) -> int:
+        return fft_plan_num_steps(self.handle)
+
+    def exec_steps(self, x: torch.Tensor, out: torch.Tensor, first: int, count: int,
+                   inverse: bool = False, stream=None) -> torch.Tensor:
+        """Enqueue launches [first, first+count) only (timing one kernel)."""
+        ws = self.workspace(x.device)
+        st = fft_exec_steps(self.handle, x.data_ptr(), out.data_ptr(),
+                            FFT_INVERSE if inverse else FFT_FORWARD,
+                            ws.data_ptr() if ws is not None else 0, _stream_handle(stream),
+                            first, count)
+        if st != FFT_OK:
+            raise FftError(st, "fft_exec_steps", fft_last_error())
         return out
 
     def close(self):

@@ -81,25 +81,28 @@ size_t TableSet::add_bytes(const void *p, size_t bytes) {
 
 void LineStep::bind(const float2 *tables) {
   a.tw = tables + tw_off;
+  a.tw2 = tables + tw2_off;
   if (has_tw4) {
     a.tw4_lo = tables + tw4_lo_off;
     a.tw4_hi = tables + tw4_hi_off;
   }
 }
 
+int LineStep::inverse_sw() const { return (first ? 1 : 0) | (last ? 2 : 0); }
+
 hipError_t LineStep::launch(const ExecCtx &ctx) const {
   LineArgs args = a;
+  dim3 g = grid;
+  if (k.persistent) g.x = (unsigned)std::min<int64_t>(a.ntiles, (int64_t)resident);
+  const void *fn = k.fn_sw[0];
   if (ctx.inverse) {
-    if (first) args.flags |= F_SWAP_IN;
-    if (last) {
-      args.flags |= F_SWAP_OUT;
-      args.scale = inv_scale;
-    }
+    fn = k.fn_sw[inverse_sw()];
+    if (last) args.scale = inv_scale;
   }
   const float2 *s = buf_c(ctx, src, 0);
   float2 *d = buf_m(ctx, dst, 0);
   void *kargs[] = {(void *)&s, (void *)&d, (void *)&args};
-  return hipLaunchKernel(k.fn, grid, dim3(k.threads), kargs, 0, ctx.stream);
+  return hipLaunchKernel(fn, g, dim3(k.threads), kargs, 0, ctx.stream);
 }
 
 void LineStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const {
@@ -111,10 +114,63 @@ void LineStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_i
   dst_id = dst;
 }
 
+bool LineStep::valid() const {
+  // unit strides the kernel assumes, 32-bit in-line offsets, instances present
+  const bool in_ok = k.map == ELEM_FAST ? a.in_e == 1 : a.in_l == 1;
+  const bool out_ok = k.omap == ELEM_FAST ? a.out_e == 1 : a.out_l == 1;
+  const bool off_ok = (int64_t)(L - 1) * std::max(a.in_e, a.out_e) < (int64_t(1) << 31);
+  return in_ok && out_ok && off_ok && k.fn_sw[0] && k.fn_sw[inverse_sw()];
+}
+
 std::string LineStep::describe() const {
   std::ostringstream o;
   o << name << ": L=" << L << " C=" << k.lines << " threads=" << k.threads
     << " grid=" << grid.x << " lds=" << k.lds_bytes << "B";
+  return o.str();
+}
+
+// ---- runtime-radix steps ----
+void MixedStep::bind(const float2 *tables) {
+  a.tw2 = tables + tw2_off;
+  if (tw4) {
+    a.tw4_lo = tables + tw4_lo_off;
+    a.tw4_hi = tables + tw4_hi_off;
+  }
+}
+
+hipError_t MixedStep::launch(const ExecCtx &ctx) const {
+  MixedArgs args = a;
+  const void *fn = fn_sw[0];
+  if (ctx.inverse) {
+    fn = fn_sw[inverse_sw()];
+    if (last) args.scale = inv_scale;
+  }
+  const float2 *s = buf_c(ctx, src, 0);
+  float2 *d = buf_m(ctx, dst, 0);
+  void *kargs[] = {(void *)&s, (void *)&d, (void *)&args};
+  return hipLaunchKernel(fn, grid, dim3(threads), kargs, (size_t)lds_bytes, ctx.stream);
+}
+
+void MixedStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const {
+  const int64_t nb = (int64_t)grid.x / a.tiles_per_batch;
+  const int64_t last_line = std::min<int64_t>(a.lines, a.tiles_per_batch * a.mp.C) - 1;
+  max_in = (nb - 1) * a.in_b + last_line * a.in_l + (int64_t)(a.mp.L - 1) * a.in_e;
+  max_out = (nb - 1) * a.out_b + last_line * a.out_l + (int64_t)(a.mp.L - 1) * a.out_e;
+  src_id = src;
+  dst_id = dst;
+}
+
+bool MixedStep::valid() const {
+  return fn_sw[0] && fn_sw[inverse_sw()] && threads > 0 && threads <= 1024 &&
+         threads == a.mp.C * a.mp.T && lds_bytes <= kLdsBytes && a.mp.T * 16 >= a.mp.L;
+}
+
+std::string MixedStep::describe() const {
+  std::ostringstream o;
+  o << name << ": L=" << a.mp.L << " radices=";
+  for (int p = 0; p < a.mp.P; ++p) o << (p ? "x" : "") << a.mp.radix[p];
+  o << " C=" << a.mp.C << " threads=" << threads << " grid=" << grid.x << " lds=" << lds_bytes
+    << "B";
   return o.str();
 }
 
@@ -129,30 +185,109 @@ dpfft_plan_s::~dpfft_plan_s() {
 // ---------------------------------------------------------------------------
 namespace {
 
-std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, int C, int map,
-                                    int omap, bool tw4) {
+// Per-step tile-width overrides "c<i>=<C>" from DPFFT_FORCE_PLAN (a testing
+// and tuning hook); -1 = no override.
+struct Override {
+  int c[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int p[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+};
+
+Override read_override() {
+  Override o;
+  const char *env = getenv("DPFFT_FORCE_PLAN");
+  if (!env) return o;
+  std::istringstream in(env);
+  std::string tok;
+  while (in >> tok) {
+    char kind = 0;
+    int idx = -1, val = -1;
+    if (sscanf(tok.c_str(), "%c%d=%d", &kind, &idx, &val) == 3 && idx >= 0 && idx < 8) {
+      if (kind == 'c') o.c[idx] = val;
+      if (kind == 'p') o.p[idx] = val;
+    }
+  }
+  return o;
+}
+
+// Workgroups of a persistent instance that stay resident on the device: the
+// CU count times what one CU holds by LDS and threads.
+int resident_workgroups(const KernelInfo &k) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 8;
+  int by_thr = 2048 / k.threads;
+  return cus * std::max(1, std::min(by_lds, by_thr));
+}
+
+// Heuristic choice among the compiled instances of a line kernel: the most
+// resident waves per CU that the 160 KB LDS allows (counted up to 16), then
+// for row tiles the smaller tile (more workgroups to overlap), for column
+// tiles the wider tile (longer contiguous segments).
+bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const Override &ov,
+                 KernelInfo *out) {
+  KernelInfo cand[32];
+  int n = list_line_kernels(L, map, omap, tw4, cand, 32);
+  if (n > 32) n = 32;
+  double best = -1;
+  for (int i = 0; i < n; ++i) {
+    const KernelInfo &k = cand[i];
+    if (ov.c[step] >= 0 && k.lines != ov.c[step]) continue;
+    if (ov.c[step] < 0 && k.lines > cmax) continue;
+    if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
+    if (ov.p[step] < 0 && k.persistent) continue;  // opt-in until measured
+    if (k.threads > 1024) continue;
+    int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 64;
+    int by_thr = 2048 / k.threads;
+    int wg = std::min(by_lds, by_thr);
+    double waves = wg * (k.threads / 64.0);
+    double tie = map == LINE_FAST ? k.lines : 1.0 / k.lines;
+    double score = std::min(waves, 16.0) * 1000 + tie;
+    if (score > best) {
+      best = score;
+      *out = k;
+    }
+  }
+  return best >= 0;
+}
+
+std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, int map, int omap,
+                                    bool tw4, int cmax, int step, const Override &ov) {
   auto s = std::make_unique<LineStep>();
-  if (!find_line_kernel(L, C, map, omap, tw4, &s->k)) return nullptr;
+  if (!choose_line(L, map, omap, tw4, cmax, step, ov, &s->k)) return nullptr;
   s->L = L;
   s->name = name;
   s->tw_off = P->tables.add(stockham_table_pow2(L));
   s->a.scale = 1.0f;
+  if (s->k.persistent) {
+    std::vector<std::complex<double>> lo, hi;
+    const int sh = tw2_shift(ilog2(L));
+    fourstep_tables(L, sh, lo, hi);
+    lo.insert(lo.end(), hi.begin(), hi.end());
+    s->tw2_off = P->tables.add(lo);
+    s->resident = resident_workgroups(s->k);
+  }
   return s;
 }
 
 fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch, D = P->dist;
+  const Override ov = read_override();
   if (N <= kSinglePassMax) {
     const int L = (int)N;
-    int C = best_line_c(L, ELEM_FAST, ELEM_FAST, false, 256);
-    auto s = make_line(P, "stockham_rows", L, C, ELEM_FAST, ELEM_FAST, false);
+    auto s = make_line(P, "stockham_rows", L, ELEM_FAST, ELEM_FAST, false, 256, 0, ov);
     if (!s) return fail(FFT_E_INTERNAL, "no row kernel for L=" + std::to_string(L));
+    const int C = s->k.lines;
     s->a.in_b = s->a.out_b = 0;
     s->a.in_l = s->a.out_l = D;
     s->a.in_e = s->a.out_e = 1;
     s->a.lines = B;
     s->a.tiles_per_batch = (B + C - 1) / C;
     s->grid = dim3((unsigned)s->a.tiles_per_batch);
+    s->a.ntiles = s->grid.x;
     s->first = s->last = true;
     s->inv_scale = (float)(1.0 / (double)N);
     s->src = BUF_IN;
@@ -166,12 +301,10 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   // N2-point FFTs along the rows of Y, stored transposed: X[k1 + N1 k2].
   const int lg = ilog2(N);
   const int N1 = 1 << (lg / 2), N2 = 1 << (lg - lg / 2);
-  const int CA = best_line_c(N1, LINE_FAST, LINE_FAST, true, 16);
-  const int CB = best_line_c(N2, ELEM_FAST, LINE_FAST, false, 16);
-  if (!CA || !CB) return fail(FFT_E_UNSUPPORTED, "no four-step kernels for N=" + std::to_string(N));
-  auto a = make_line(P, "fourstep_columns", N1, CA, LINE_FAST, LINE_FAST, true);
-  auto b = make_line(P, "fourstep_rows_transposed", N2, CB, ELEM_FAST, LINE_FAST, false);
-  if (!a || !b) return fail(FFT_E_INTERNAL, "four-step kernel lookup failed");
+  auto a = make_line(P, "fourstep_columns", N1, LINE_FAST, LINE_FAST, true, 16, 0, ov);
+  auto b = make_line(P, "fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false, 16, 1, ov);
+  if (!a || !b) return fail(FFT_E_UNSUPPORTED, "no four-step kernels for N=" + std::to_string(N));
+  const int CA = a->k.lines, CB = b->k.lines;
   std::vector<std::complex<double>> lo, hi;
   const int shift = (lg + 1) / 2;
   fourstep_tables(N, shift, lo, hi);
@@ -189,6 +322,7 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   a->a.tiles_per_batch = N2 / CA;
   a->a.flags = F_REMAP;
   a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
+  a->a.ntiles = a->grid.x;
   a->first = true;
   a->src = BUF_IN;
   a->dst = BUF_WS;
@@ -203,6 +337,7 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   b->a.tiles_per_batch = N1 / CB;
   b->a.flags = F_REMAP;
   b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
+  b->a.ntiles = b->grid.x;
   b->last = true;
   b->inv_scale = (float)(1.0 / (double)N);
   b->src = BUF_WS;
@@ -216,20 +351,20 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
 
 fft_status_t plan_pow2_2d(dpfft_plan_s *P) {
   const int64_t NY = P->ny, NX = P->nx, B = P->batch, D = P->dist;
-  const int CR = best_line_c((int)NX, ELEM_FAST, ELEM_FAST, false, 256);
-  const int CC = best_line_c((int)NY, LINE_FAST, LINE_FAST, false, 64);
-  if (!CR || !CC) return fail(FFT_E_UNSUPPORTED, "no 2D kernels for this shape");
+  const Override ov = read_override();
   // row pass: in -> out; column pass: in place on out (column tiles read and
   // written by the same workgroup, so no transpose and no workspace)
-  auto r = make_line(P, "rows", (int)NX, CR, ELEM_FAST, ELEM_FAST, false);
-  auto c = make_line(P, "columns", (int)NY, CC, LINE_FAST, LINE_FAST, false);
-  if (!r || !c) return fail(FFT_E_INTERNAL, "2D kernel lookup failed");
+  auto r = make_line(P, "rows", (int)NX, ELEM_FAST, ELEM_FAST, false, 256, 0, ov);
+  auto c = make_line(P, "columns", (int)NY, LINE_FAST, LINE_FAST, false, 64, 1, ov);
+  if (!r || !c) return fail(FFT_E_UNSUPPORTED, "no 2D kernels for this shape");
+  const int CR = r->k.lines, CC = c->k.lines;
   r->a.in_b = r->a.out_b = D;
   r->a.in_l = r->a.out_l = NX;
   r->a.in_e = r->a.out_e = 1;
   r->a.lines = NY;
   r->a.tiles_per_batch = (NY + CR - 1) / CR;
   r->grid = dim3((unsigned)(B * r->a.tiles_per_batch));
+  r->a.ntiles = r->grid.x;
   r->first = true;
   r->src = BUF_IN;
   r->dst = BUF_OUT;
@@ -240,6 +375,7 @@ fft_status_t plan_pow2_2d(dpfft_plan_s *P) {
   c->a.tiles_per_batch = (NX + CC - 1) / CC;
   c->a.flags = F_REMAP;
   c->grid = dim3((unsigned)(B * c->a.tiles_per_batch));
+  c->a.ntiles = c->grid.x;
   c->last = true;
   c->inv_scale = (float)(1.0 / ((double)NX * (double)NY));
   c->src = BUF_OUT;
@@ -247,6 +383,126 @@ fft_status_t plan_pow2_2d(dpfft_plan_s *P) {
   P->steps.push_back(std::move(r));
   P->steps.push_back(std::move(c));
   P->variant = "2d rows+columns";
+  return FFT_OK;
+}
+
+// A runtime-radix step over lines of length L, C lines per workgroup.
+std::unique_ptr<MixedStep> make_mixed(dpfft_plan_s *P, const char *name, int64_t L, int map,
+                                      int omap, bool tw4, int C) {
+  auto s = std::make_unique<MixedStep>();
+  if (!mixed_radices(L, &s->a.mp)) return nullptr;
+  s->a.mp.C = C;
+  s->map = map;
+  s->omap = omap;
+  s->tw4 = tw4;
+  s->name = name;
+  s->threads = C * s->a.mp.T;
+  s->lds_bytes = mixed_lds_bytes(s->a.mp, map, omap);
+  for (int sw = 0; sw < 4; ++sw) s->fn_sw[sw] = mixed_kernel(map, omap, tw4, sw);
+  std::vector<std::complex<double>> lo, hi;
+  fourstep_tables(L, s->a.mp.tw2_shift, lo, hi);
+  lo.insert(lo.end(), hi.begin(), hi.end());
+  s->tw2_off = P->tables.add(lo);
+  s->a.scale = 1.0f;
+  // dynamic LDS above the default 64 KB needs an explicit opt-in per function
+  for (int sw = 0; sw < 4; ++sw)
+    if (s->fn_sw[sw])
+      (void)hipFuncSetAttribute(s->fn_sw[sw], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                s->lds_bytes);
+  return s;
+}
+
+// lines per workgroup: as many as keep the workgroup <= `thr` threads and the
+// LDS within one CU's 160 KB, at least `cmin`
+int mixed_lines(int64_t L, int map, int omap, int thr, int cmin) {
+  MixedPlan mp{};
+  if (!mixed_radices(L, &mp)) return 0;
+  int C = std::max(cmin, thr / mp.T);
+  while (C > 1) {
+    mp.C = C;
+    if (C * mp.T <= 1024 && mixed_lds_bytes(mp, map, omap) <= kLdsBytes) break;
+    --C;
+  }
+  mp.C = C;
+  if (C * mp.T > 1024 || mixed_lds_bytes(mp, map, omap) > kLdsBytes) return 0;
+  return C;
+}
+
+// largest divisor of n that is <= sqrt(n)
+int64_t split_factor(int64_t n) {
+  int64_t best = 1;
+  for (int64_t d = 1; d * d <= n; ++d)
+    if (n % d == 0) best = d;
+  return best;
+}
+
+fft_status_t plan_mixed_1d(dpfft_plan_s *P) {
+  const int64_t N = P->n, B = P->batch, D = P->dist;
+  if (N <= kSinglePassMax) {
+    const int C = mixed_lines(N, ELEM_FAST, ELEM_FAST, 256, 1);
+    auto s = C ? make_mixed(P, "mixed_rows", N, ELEM_FAST, ELEM_FAST, false, C) : nullptr;
+    if (!s) return fail(FFT_E_UNSUPPORTED, "no mixed-radix plan for N=" + std::to_string(N));
+    s->a.in_b = s->a.out_b = 0;
+    s->a.in_l = s->a.out_l = D;
+    s->a.in_e = s->a.out_e = 1;
+    s->a.lines = B;
+    s->a.tiles_per_batch = (B + C - 1) / C;
+    s->grid = dim3((unsigned)s->a.tiles_per_batch);
+    s->first = s->last = true;
+    s->inv_scale = (float)(1.0 / (double)N);
+    P->steps.push_back(std::move(s));
+    P->variant = "mixed single-pass";
+    return FFT_OK;
+  }
+  const int64_t N1 = split_factor(N), N2 = N / N1;
+  if (N2 > kSinglePassMax)
+    return fail(FFT_E_UNSUPPORTED, "no two-factor split of N=" + std::to_string(N));
+  const int CA = mixed_lines(N1, LINE_FAST, LINE_FAST, 1024, 1);
+  const int CB = mixed_lines(N2, ELEM_FAST, LINE_FAST, 1024, 1);
+  auto a = CA ? make_mixed(P, "mixed_fourstep_columns", N1, LINE_FAST, LINE_FAST, true,
+                           std::min(CA, 16))
+              : nullptr;
+  auto b = CB ? make_mixed(P, "mixed_fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false,
+                           std::min(CB, 16))
+              : nullptr;
+  if (!a || !b) return fail(FFT_E_UNSUPPORTED, "no mixed four-step plan for N=" + std::to_string(N));
+  std::vector<std::complex<double>> lo, hi;
+  const int shift = (ilog2(N) + 1) / 2;
+  fourstep_tables(N, shift, lo, hi);
+  a->tw4_lo_off = P->tables.add(lo);
+  a->tw4_hi_off = P->tables.add(hi);
+  a->a.tw4_shift = shift;
+  a->a.in_b = D;
+  a->a.in_l = 1;
+  a->a.in_e = N2;
+  a->a.out_b = N;
+  a->a.out_l = 1;
+  a->a.out_e = N2;
+  a->a.lines = N2;
+  a->a.tiles_per_batch = (N2 + a->a.mp.C - 1) / a->a.mp.C;
+  a->a.flags = F_REMAP;
+  a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
+  a->first = true;
+  a->src = BUF_IN;
+  a->dst = BUF_WS;
+  b->a.in_b = N;
+  b->a.in_l = N2;
+  b->a.in_e = 1;
+  b->a.out_b = D;
+  b->a.out_l = 1;
+  b->a.out_e = N1;
+  b->a.lines = N1;
+  b->a.tiles_per_batch = (N1 + b->a.mp.C - 1) / b->a.mp.C;
+  b->a.flags = F_REMAP;
+  b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
+  b->last = true;
+  b->inv_scale = (float)(1.0 / (double)N);
+  b->src = BUF_WS;
+  b->dst = BUF_OUT;
+  P->steps.push_back(std::move(a));
+  P->steps.push_back(std::move(b));
+  P->ws_bytes = (size_t)B * (size_t)N * sizeof(float2);
+  P->variant = "mixed four-step " + std::to_string(N1) + "x" + std::to_string(N2);
   return FFT_OK;
 }
 
@@ -336,8 +592,7 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
     return fail(FFT_E_UNSUPPORTED, "only FFT_FP32 is implemented for this shape");
 
   if (desc->rank == 1) {
-    if (!is_pow2(P->n)) return fail(FFT_E_UNSUPPORTED, "mixed-radix lengths are not implemented yet");
-    st = plan_pow2_1d(P.get());
+    st = is_pow2(P->n) ? plan_pow2_1d(P.get()) : plan_mixed_1d(P.get());
   } else {
     st = plan_pow2_2d(P.get());
   }
@@ -357,6 +612,8 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
       };
       if (mi >= cap(si) || mo >= cap(di))
         return fail(FFT_E_INTERNAL, "plan bounds check failed in " + s->describe());
+      if (!s->valid())
+        return fail(FFT_E_INTERNAL, "plan layout check failed in " + s->describe());
     }
   }
 
@@ -392,11 +649,14 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
   return FFT_OK;
 }
 
-fft_status_t fft_exec(fft_plan_t plan, const void *in, void *out, int direction, void *workspace,
-                      void *hip_stream) {
+static fft_status_t exec_range(fft_plan_t plan, const void *in, void *out, int direction,
+                               void *workspace, void *hip_stream, int first, int count) {
   if (!plan) return fail(FFT_E_INVALID, "plan is NULL");
   if (direction != FFT_FORWARD && direction != FFT_INVERSE)
     return fail(FFT_E_INVALID, "direction must be FFT_FORWARD or FFT_INVERSE");
+  const int nsteps = (int)plan->steps.size();
+  if (first < 0 || count < 0 || first + count > nsteps)
+    return fail(FFT_E_INVALID, "step range outside the plan");
   if (plan->batch == 0) return FFT_OK;
   if (!in || !out) return fail(FFT_E_INVALID, "in/out is NULL");
   if (((uintptr_t)in | (uintptr_t)out) & 7u) return fail(FFT_E_INVALID, "in/out not 8-byte aligned");
@@ -404,12 +664,25 @@ fft_status_t fft_exec(fft_plan_t plan, const void *in, void *out, int direction,
     return fail(FFT_E_INVALID, "in == out needs FFT_F_INPLACE");
   if (plan->ws_bytes && !workspace) return fail(FFT_E_INVALID, "plan needs a workspace");
   ExecCtx ctx{in, out, workspace, (hipStream_t)hip_stream, direction == FFT_INVERSE};
-  for (auto &s : plan->steps) {
-    hipError_t e = s->launch(ctx);
+  for (int i = first; i < first + count; ++i) {
+    hipError_t e = plan->steps[i]->launch(ctx);
     if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   }
   return FFT_OK;
 }
+
+fft_status_t fft_exec(fft_plan_t plan, const void *in, void *out, int direction, void *workspace,
+                      void *hip_stream) {
+  if (!plan) return fail(FFT_E_INVALID, "plan is NULL");
+  return exec_range(plan, in, out, direction, workspace, hip_stream, 0, (int)plan->steps.size());
+}
+
+fft_status_t fft_exec_steps(fft_plan_t plan, const void *in, void *out, int direction,
+                            void *workspace, void *hip_stream, int first, int count) {
+  return exec_range(plan, in, out, direction, workspace, hip_stream, first, count);
+}
+
+int fft_plan_num_steps(fft_plan_t plan) { return plan ? (int)plan->steps.size() : 0; }
 
 fft_status_t fft_destroy(fft_plan_t plan) {
   delete plan;

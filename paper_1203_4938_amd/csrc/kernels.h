@@ -12,8 +12,6 @@ namespace dpfft {
 enum : int { ELEM_FAST = 0, LINE_FAST = 1 };
 
 enum : uint32_t {
-  F_SWAP_IN = 1u,   // exchange re/im on load (inverse transform)
-  F_SWAP_OUT = 2u,  // exchange re/im on store (inverse transform)
   F_REMAP = 4u,     // XCD-aware workgroup -> tile order
 };
 
@@ -31,19 +29,22 @@ struct LineArgs {
   int32_t tw4_shift;
   float scale;             // applied to every output (1 or 1/N)
   uint32_t flags;
+  const float2 *tw2;       // two-level pass table of w_L: 2^S lo entries, then L/2^S hi
+  int64_t ntiles;          // tiles in the launch (persistent kernels loop over them)
 };
 
 // Radix plan of the power-of-two line kernels, shared by the device code and
-// the host twiddle generator.  E elements per thread, T threads per line,
+// the host twiddle generator.  E elements per thread (EPT, or L if smaller;
+// a multiple of every radix), T threads per line,
 // NP passes: radix 16 first, then one radix 2/4/8 remainder pass.
-template <int L> struct P2 {
+template <int L, int EPT = 16> struct P2 {
   static constexpr int lg() {
     int k = 0;
     while ((1 << k) < L) ++k;
     return k;
   }
   static constexpr int LG = lg();
-  static constexpr int E = L >= 16 ? 16 : L;
+  static constexpr int E = L >= EPT ? EPT : L;
   static constexpr int T = L / E;
   static constexpr int NP = (LG + 3) / 4;
   static constexpr int radix(int p) { return (p < LG / 4) ? 16 : (1 << (LG % 4)); }
@@ -59,6 +60,10 @@ template <int L> struct P2 {
   }
 };
 
+// Split of the two-level pass-twiddle table of a length-L kernel: w_L^e =
+// hi[e >> S] * lo[e & (2^S - 1)] with 2^S lo and L / 2^S hi entries.
+constexpr int tw2_shift(int lg) { return (lg + 1) / 2; }
+
 // Runtime twin of P2<L> for the host.
 inline int pow2_radix(int L, int p) {
   int lg = 0;
@@ -72,17 +77,21 @@ inline int pow2_passes(int L) {
 }
 
 struct KernelInfo {
-  const void *fn = nullptr;
+  const void *fn = nullptr;          // forward instance
+  const void *fn_sw[4] = {};         // by swap mode: 1 = on load, 2 = on store, 3 = both
   int threads = 0;      // workgroup size
   int lines = 0;        // lines per workgroup (C)
   int lds_bytes = 0;    // static LDS of the instance
+  int map = 0, omap = 0;
+  bool persistent = false;  // loops over tiles; launch at most one grid of resident workgroups
 };
 
 // Power-of-two line kernel with compile-time length L and C lines per
 // workgroup.  tw4 = apply the four-step twiddle w_N^{line*i} before the store.
 bool find_line_kernel(int L, int C, int map, int omap, bool tw4, KernelInfo *out);
 
-// Largest C available for (L, map, omap, tw4) with C <= cmax; 0 if none.
-int best_line_c(int L, int map, int omap, bool tw4, int cmax);
+// All compiled instances for (L, map, omap, tw4); returns how many exist and
+// fills up to `max` of them.
+int list_line_kernels(int L, int map, int omap, bool tw4, KernelInfo *out, int max);
 
 }  // namespace dpfft

@@ -25,6 +25,8 @@
 
 namespace dpfft {
 
+constexpr int kPadShift = 4;
+
 // LDS layouts; one padding element every 2^PADSH entries breaks the power-of-
 // two strides of the scatter writes across banks.
 template <int L, int C, int MAP, int PADSH> struct Lds {
@@ -40,52 +42,89 @@ template <int L, int C, int MAP, int PADSH> struct Lds {
   }
 };
 
-template <int L, int C, int MAP, int PADSH, int P>
-__device__ __forceinline__ void stockham_pass(cf (&v)[P2<L>::E], cf *lds,
-                                              const cf *__restrict__ tw, int c, int j) {
-  using G = P2<L>;
+// Exchange through LDS: v[m] goes to slot wpos(m), then v[m] is reloaded from
+// slot rpos(m) (complex pairs).  `TAIL` adds the barrier that protects the
+// buffer against the next writer.
+template <int E, bool TAIL, class WPos, class RPos>
+__device__ __forceinline__ void lds_exchange(cf (&v)[E], cf *lds, WPos wpos, RPos rpos) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) lds[wpos(m)] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = lds[rpos(m)];
+  if constexpr (TAIL) __syncthreads();
+}
+
+// One Stockham pass on the registers of thread (c, j).  Butterfly q of the
+// thread is b = j + T*q; its inputs are v[q + r*QN] and its outputs are left
+// in the same registers, then (unless this is the last pass) exchanged so that
+// v[m] again holds element j + T*m.
+// Pass twiddle sources: TwTable reads the per-pass table from global memory;
+// TwLds2 rebuilds w_{Ns R}^{k r} = w_L^{k r L/(Ns R)} from the two-level table
+// held in LDS (one product, no global load, so nothing waits behind a
+// prefetch).
+struct TwTable {
+  const cf *__restrict__ tw;
+  template <int L, int TWO, int NS, int R>
+  __device__ __forceinline__ cf get(int r, int k) const {
+    return tw[TWO + (r - 1) * NS + k];
+  }
+};
+struct TwLds2 {
+  const cf *lo;
+  const cf *hi;
+  template <int L, int TWO, int NS, int R>
+  __device__ __forceinline__ cf get(int r, int k) const {
+    constexpr int S = tw2_shift(P2<L>::LG);
+    const uint32_t e = (uint32_t)(k * r) * (uint32_t)(L / (NS * R));
+    return cmul(hi[e >> S], lo[e & ((1u << S) - 1u)]);
+  }
+};
+
+template <int L, int EPT, int C, int MAP, int P, class TW>
+__device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
+                                              int j) {
+  using G = P2<L, EPT>;
   constexpr int E = G::E, T = G::T, R = G::radix(P), NS = G::ns(P), QN = E / R;
   constexpr bool LAST = (P == G::NP - 1);
   constexpr int TWO = G::twoff(P);
-  using LD = Lds<L, C, MAP, PADSH>;
+  using LD = Lds<L, C, MAP, kPadShift>;
 #pragma unroll
   for (int q = 0; q < QN; ++q) {
     const int b = j + T * q;
     cf x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = v[q + r * QN];
-    const int k = b & (NS - 1);
     if constexpr (NS > 1) {
+      const int k = b & (NS - 1);
 #pragma unroll
-      for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[TWO + (r - 1) * NS + k]);
+      for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw.template get<L, TWO, NS, R>(r, k));
     }
     Dft<R>::run(x);
-    if constexpr (LAST) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q + r * QN] = x[r];
-    } else {
-      const int base = (b - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[LD::idx(c, base + r * NS)] = x[r];
-    }
+    for (int r = 0; r < R; ++r) v[q + r * QN] = x[r];
   }
   if constexpr (!LAST) {
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = lds[LD::idx(c, j + T * m)];
-    __syncthreads();
+    auto wpos = [&](int m) {
+      const int q = m % QN, r = m / QN;
+      const int b = j + T * q;
+      const int k = b & (NS - 1);
+      return LD::idx(c, (b - k) * R + k + r * NS);
+    };
+    auto rpos = [&](int m) { return LD::idx(c, j + T * m); };
+    lds_exchange<E, true>(v, lds, wpos, rpos);
   }
 }
 
-template <int L, int C, int MAP, int PADSH, int... P>
-__device__ __forceinline__ void all_passes(cf (&v)[P2<L>::E], cf *lds, const cf *__restrict__ tw,
-                                           int c, int j, std::integer_sequence<int, P...>) {
-  (stockham_pass<L, C, MAP, PADSH, P>(v, lds, tw, c, j), ...);
+template <int L, int EPT, int C, int MAP, class TW, int... P>
+__device__ __forceinline__ void all_passes(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
+                                           int j, std::integer_sequence<int, P...>) {
+  (stockham_pass<L, EPT, C, MAP, P>(v, lds, tw, c, j), ...);
 }
 
-template <int L, int C, int MAP>
+template <int L, int EPT, int C, int MAP>
 __device__ __forceinline__ void lane_map(int tid, int &c, int &j) {
-  constexpr int T = P2<L>::T;
+  constexpr int T = P2<L, EPT>::T;
   if constexpr (MAP == ELEM_FAST) {
     c = tid / T;
     j = tid % T;
@@ -95,29 +134,68 @@ __device__ __forceinline__ void lane_map(int tid, int &c, int &j) {
   }
 }
 
-// four-step twiddle w_N^e, e = line * i (< N), from the two-level table
-__device__ __forceinline__ cf tw4_value(const LineArgs &a, int64_t e) {
-  const int64_t lo = e & ((int64_t(1) << a.tw4_shift) - 1);
-  const int64_t hi = e >> a.tw4_shift;
+// w_N^e for 0 <= e < N from the two-level table: hi[e >> s] * lo[e & (2^s-1)]
+__device__ __forceinline__ cf tw4_lookup(const LineArgs &a, uint32_t e) {
+  const uint32_t lo = e & ((1u << a.tw4_shift) - 1u);
+  const uint32_t hi = e >> a.tw4_shift;
   return cmul(a.tw4_hi[hi], a.tw4_lo[lo]);
 }
 
-constexpr int kPadShift = 4;
+// Four-step twiddles w_N^{n2 k1} for the elements k1 = j + T*m (m = 0..E-1)
+// of column n2: with A = w_N^{n2 j} and B = w_N^{n2 T} (two table lookups
+// each), w_N^{n2 (j + T m)} = A * B^m, where B^m comes from a product tree of
+// depth at most 4 (B^2 = B B, B^4 = B^2 B^2, B^8 = B^4 B^4, the others as one
+// product of two of these), so no twiddle carries more than about six
+// roundings.
+template <int E>
+__device__ __forceinline__ void tw4_apply_ab(cf (&v)[E], cf A, cf B) {
+  cf Bm[E];
+  Bm[0] = make_float2(1.0f, 0.0f);
+  if constexpr (E > 1) Bm[1] = B;
+#pragma unroll
+  for (int m = 2; m < E; ++m) {
+    // largest power of two p <= m; B^m = B^p * B^(m-p), or B^(p/2)^2 for m = p
+    int p = 1;
+    while (2 * p <= m) p *= 2;
+    Bm[m] = (m == p) ? cmul(Bm[p / 2], Bm[p / 2]) : cmul(Bm[p], Bm[m - p]);
+  }
+  v[0] = cmul(v[0], A);
+#pragma unroll
+  for (int m = 1; m < E; ++m) v[m] = cmul(v[m], cmul(A, Bm[m]));
+}
 
-template <int L, int C, int MAP, int OMAP, bool TW4>
-__global__ void __launch_bounds__(C * P2<L>::T)
+template <int E>
+__device__ __forceinline__ void tw4_apply(cf (&v)[E], const LineArgs &a, uint32_t n2, int j, int T) {
+  tw4_apply_ab<E>(v, tw4_lookup(a, n2 * (uint32_t)j), tw4_lookup(a, n2 * (uint32_t)T));
+}
+
+// LDS complex elements an instance needs (0 if it never exchanges)
+template <int L, int C, int MAP, int OMAP>
+constexpr int lds_pairs() {
+  constexpr bool need = (P2<L>::NP > 1) || (OMAP != MAP);  // independent of EPT
+  constexpr int a = Lds<L, C, MAP, kPadShift>::SIZE, b = Lds<L, C, OMAP, kPadShift>::SIZE;
+  return need ? (a > b ? a : b) : 0;
+}
+
+// SW bit 0: exchange re/im on load; bit 1: exchange on store (the inverse
+// transform is swap(FFT(swap(x))), so the first launch of an inverse swaps on
+// load and the last one on store).
+//
+// Addressing: an ELEM_FAST side has unit element stride (x_e == 1) and a
+// LINE_FAST side has unit line stride (x_l == 1); the plan guarantees it.
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
+__global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
-  using G = P2<L>;
+  using G = P2<L, EPT>;
+  static_assert(C * G::T <= 1024, "a workgroup holds at most 1024 threads");
   constexpr int E = G::E, T = G::T;
-  constexpr bool NEED_LDS = (G::NP > 1) || (OMAP != MAP);
-  using LI = Lds<L, C, MAP, kPadShift>;
   using LO = Lds<L, C, OMAP, kPadShift>;
-  constexpr int LDS_SZ = NEED_LDS ? (LI::SIZE > LO::SIZE ? LI::SIZE : LO::SIZE) : 1;
-  __shared__ cf lds[LDS_SZ];
+  constexpr int NP = lds_pairs<L, C, MAP, OMAP>();
+  __shared__ __align__(16) cf lds[NP > 0 ? NP : 1];
 
   const int tid = threadIdx.x;
   int c, j;
-  lane_map<L, C, MAP>(tid, c, j);
+  lane_map<L, EPT, C, MAP>(tid, c, j);
   const uint32_t tile = (a.flags & F_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (int64_t)(tile - bb * a.tiles_per_batch) * C;
@@ -126,10 +204,17 @@ __global__ void __launch_bounds__(C * P2<L>::T)
 
   cf v[E];
   if (valid) {
-    const cf *src = in + bb * a.in_b + line * a.in_l;
+    if constexpr (MAP == ELEM_FAST) {
+      const cf *src = in + bb * a.in_b + line * a.in_l + j;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = src[(int64_t)(j + T * m) * a.in_e];
-    if (a.flags & F_SWAP_IN) {
+      for (int m = 0; m < E; ++m) v[m] = src[T * m];
+    } else {
+      const int32_t es = (int32_t)a.in_e;
+      const cf *src = in + bb * a.in_b + line + (int64_t)j * es;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = src[(uint32_t)(T * m * es)];
+    }
+    if constexpr (SW & 1) {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
     }
@@ -138,42 +223,161 @@ __global__ void __launch_bounds__(C * P2<L>::T)
     for (int m = 0; m < E; ++m) v[m] = make_float2(0.0f, 0.0f);
   }
 
-  all_passes<L, C, MAP, kPadShift>(v, lds, a.tw, c, j, std::make_integer_sequence<int, G::NP>{});
+  all_passes<L, EPT, C, MAP>(v, lds, TwTable{a.tw}, c, j,
+                             std::make_integer_sequence<int, G::NP>{});
 
-  // epilogue: four-step twiddle and scale in registers
+  // epilogue in registers: four-step twiddle, inverse scale
+  if constexpr (TW4) tw4_apply<E>(v, a, (uint32_t)line, j, T);
+  if constexpr (SW & 2) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    cf y = v[m];
-    if constexpr (TW4) y = cmul(y, tw4_value(a, line * (int64_t)(j + T * m)));
-    v[m] = cscale(y, a.scale);
+    for (int m = 0; m < E; ++m) v[m] = cscale(v[m], a.scale);
   }
-  const bool swap_out = (a.flags & F_SWAP_OUT) != 0;
-  if constexpr (OMAP == MAP) {
-    if (valid) {
-      cf *dst = out + bb * a.out_b + line * a.out_l;
+  int c2 = c, j2 = j;
+  int64_t line2 = line;
+  if constexpr (OMAP != MAP) {
+    // re-tile through LDS so the store is coalesced in the output layout
+    lane_map<L, EPT, C, OMAP>(tid, c2, j2);
+    line2 = line0 + c2;
+    auto wpos = [&](int m) { return LO::idx(c, j + T * m); };
+    auto rpos = [&](int m) { return LO::idx(c2, j2 + T * m); };
+    lds_exchange<E, false>(v, lds, wpos, rpos);
+  }
+  if (line2 < a.lines) {
+    if constexpr (SW & 2) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        cf y = swap_out ? cswap(v[m]) : v[m];
-        dst[(int64_t)(j + T * m) * a.out_e] = y;
-      }
+      for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
+    }
+    if constexpr (OMAP == ELEM_FAST) {
+      cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[T * m] = v[m];
+    } else {
+      const int32_t es = (int32_t)a.out_e;
+      cf *dst = out + bb * a.out_b + line2 + (int64_t)j2 * es;
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[(uint32_t)(T * m * es)] = v[m];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form for instances whose LDS buffer allows one workgroup per CU.
+// A grid of resident workgroups loops over the tiles; while a tile is being
+// transformed, the next tile's elements (and its four-step twiddle bases) are
+// already in flight into a second register set, so the CU keeps HBM busy
+// through the passes and barriers.  Pass twiddles come from LDS.  Each round
+// of gridDim tiles is split so that every XCD sweeps a contiguous slice.
+// ---------------------------------------------------------------------------
+template <int L, int EPT, int C, int MAP>
+__device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__restrict__ in,
+                                          const LineArgs &a, int64_t tile, int c, int j,
+                                          bool swap) {
+  constexpr int E = P2<L, EPT>::E, T = P2<L, EPT>::T;
+  const int64_t bb = tile / a.tiles_per_batch;
+  const int64_t line = (tile - bb * a.tiles_per_batch) * C + c;
+  if (line < a.lines) {
+    if constexpr (MAP == ELEM_FAST) {
+      const cf *src = in + bb * a.in_b + line * a.in_l + j;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = src[T * m];
+    } else {
+      const int32_t es = (int32_t)a.in_e;
+      const cf *src = in + bb * a.in_b + line + (int64_t)j * es;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = src[(uint32_t)(T * m * es)];
+    }
+    if (swap) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
     }
   } else {
-    // re-tile through LDS so the store is coalesced in the output layout
 #pragma unroll
-    for (int m = 0; m < E; ++m) lds[LO::idx(c, j + T * m)] = v[m];
-    __syncthreads();
-    int c2, j2;
-    lane_map<L, C, OMAP>(tid, c2, j2);
-    const int64_t line2 = line0 + c2;
-    if (line2 < a.lines) {
-      cf *dst = out + bb * a.out_b + line2 * a.out_l;
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        cf y = lds[LO::idx(c2, j2 + T * m)];
-        if (swap_out) y = cswap(y);
-        dst[(int64_t)(j2 + T * m) * a.out_e] = y;
+    for (int m = 0; m < E; ++m) v[m] = make_float2(0.0f, 0.0f);
+  }
+}
+
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
+__global__ void __launch_bounds__(C * (P2<L, EPT>::T))
+    k_lines_pf(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
+  using G = P2<L, EPT>;
+  static_assert(C * G::T <= 1024, "a workgroup holds at most 1024 threads");
+  constexpr int E = G::E, T = G::T, NT = C * G::T;
+  constexpr int S = tw2_shift(G::LG), NLO = 1 << S, NHI = (L >> S) > 0 ? (L >> S) : 1;
+  using LO = Lds<L, C, OMAP, kPadShift>;
+  constexpr int NPR = lds_pairs<L, C, MAP, OMAP>();
+  __shared__ __align__(16) cf lds[NPR > 0 ? NPR : 1];
+  __shared__ cf twl[NLO + NHI];
+  for (int i = threadIdx.x; i < NLO + NHI; i += NT) twl[i] = a.tw2[i];
+  __syncthreads();
+  const TwLds2 tw{twl, twl + NLO};
+
+  const int tid = threadIdx.x;
+  int c, j;
+  lane_map<L, EPT, C, MAP>(tid, c, j);
+  const uint32_t Gd = gridDim.x, bid = blockIdx.x;
+  const uint32_t slot = (Gd % 8u == 0u) ? (bid % 8u) * (Gd / 8u) + bid / 8u : bid;
+  int64_t tile = slot;
+  if (tile >= a.ntiles) return;
+
+  cf v[E], vn[E];
+  load_tile<L, EPT, C, MAP>(v, in, a, tile, c, j, (SW & 1) != 0);
+  cf A = make_float2(1.f, 0.f), B = A, An = A, Bn = A;
+  auto line_of = [&](int64_t t) {
+    const int64_t bb = t / a.tiles_per_batch;
+    return (t - bb * a.tiles_per_batch) * C + c;
+  };
+  if constexpr (TW4) {
+    const uint32_t n2 = (uint32_t)line_of(tile);
+    A = tw4_lookup(a, n2 * (uint32_t)j);
+    B = tw4_lookup(a, n2 * (uint32_t)T);
+  }
+
+  for (; tile < a.ntiles; tile += Gd) {
+    const int64_t next = tile + Gd;
+    if (next < a.ntiles) {
+      load_tile<L, EPT, C, MAP>(vn, in, a, next, c, j, (SW & 1) != 0);
+      if constexpr (TW4) {
+        const uint32_t n2 = (uint32_t)line_of(next);
+        An = tw4_lookup(a, n2 * (uint32_t)j);
+        Bn = tw4_lookup(a, n2 * (uint32_t)T);
       }
     }
+    all_passes<L, EPT, C, MAP>(v, lds, tw, c, j, std::make_integer_sequence<int, G::NP>{});
+    if constexpr (TW4) tw4_apply_ab<E>(v, A, B);
+    if constexpr (SW & 2) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cscale(v[m], a.scale);
+    }
+    const int64_t bb = tile / a.tiles_per_batch;
+    const int64_t line0 = (tile - bb * a.tiles_per_batch) * C;
+    int c2 = c, j2 = j;
+    if constexpr (OMAP != MAP) {
+      lane_map<L, EPT, C, OMAP>(tid, c2, j2);
+      auto wpos = [&](int m) { return LO::idx(c, j + T * m); };
+      auto rpos = [&](int m) { return LO::idx(c2, j2 + T * m); };
+      lds_exchange<E, true>(v, lds, wpos, rpos);
+    }
+    const int64_t line2 = line0 + c2;
+    if (line2 < a.lines) {
+      if constexpr (SW & 2) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
+      }
+      if constexpr (OMAP == ELEM_FAST) {
+        cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
+#pragma unroll
+        for (int m = 0; m < E; ++m) dst[T * m] = v[m];
+      } else {
+        const int32_t es = (int32_t)a.out_e;
+        cf *dst = out + bb * a.out_b + line2 + (int64_t)j2 * es;
+#pragma unroll
+        for (int m = 0; m < E; ++m) dst[(uint32_t)(T * m * es)] = v[m];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = vn[m];
+    A = An;
+    B = Bn;
   }
 }
 
@@ -183,61 +387,109 @@ __global__ void __launch_bounds__(C * P2<L>::T)
 struct LineEntry {
   int L, C, map, omap;
   bool tw4;
-  const void *fn;
+  const void *fn[4];  // by SW; nullptr where not instantiated
   int threads;
   int lds;
+  bool pf;
 };
 
-#define DP_LINE(L_, C_, M_, O_, TW_)                                                  \
-  LineEntry{L_, C_, M_, O_, TW_, (const void *)&k_lines<L_, C_, M_, O_, TW_>,        \
-            C_ * P2<L_>::T,                                                           \
-            (int)sizeof(cf) *                                                         \
-                (((P2<L_>::NP > 1) || (M_ != O_))                                     \
-                     ? (Lds<L_, C_, M_, kPadShift>::SIZE > Lds<L_, C_, O_, kPadShift>::SIZE \
-                            ? Lds<L_, C_, M_, kPadShift>::SIZE                        \
-                            : Lds<L_, C_, O_, kPadShift>::SIZE)                       \
-                     : 1)}
+#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT>
+#define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
+  LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
+            (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
+                (KPF ? (int)sizeof(cf) * ((1 << tw2_shift(P2<L_>::LG)) +            \
+                                          ((L_ >> tw2_shift(P2<L_>::LG)) > 0        \
+                                               ? (L_ >> tw2_shift(P2<L_>::LG))      \
+                                               : 1))                                \
+                     : 0),                                                          \
+            KPF}
 
-#define ROW(L_, C_) DP_LINE(L_, C_, ELEM_FAST, ELEM_FAST, false)
-#define COL(L_, C_) DP_LINE(L_, C_, LINE_FAST, LINE_FAST, false)
-#define COLTW(L_, C_) DP_LINE(L_, C_, LINE_FAST, LINE_FAST, true)
-#define ROWT(L_, C_) DP_LINE(L_, C_, ELEM_FAST, LINE_FAST, false)
+// rows: forward, inverse single pass (swap in+out), 2D row pass inverse (swap in)
+#define ROW(L_, C_)                                                                          \
+  ENTRY(L_, C_, ELEM_FAST, ELEM_FAST, false, KL(L_, C_, ELEM_FAST, ELEM_FAST, false, 0),   \
+        KL(L_, C_, ELEM_FAST, ELEM_FAST, false, 1), nullptr,                                \
+        KL(L_, C_, ELEM_FAST, ELEM_FAST, false, 3))
+// 2D column pass: forward, inverse (swap out)
+#define COL(L_, C_)                                                                          \
+  ENTRY(L_, C_, LINE_FAST, LINE_FAST, false, KL(L_, C_, LINE_FAST, LINE_FAST, false, 0),   \
+        nullptr, KL(L_, C_, LINE_FAST, LINE_FAST, false, 2), nullptr)
+// four-step first pass: forward, inverse (swap in)
+#define COLTW(L_, C_)                                                                        \
+  ENTRY(L_, C_, LINE_FAST, LINE_FAST, true, KL(L_, C_, LINE_FAST, LINE_FAST, true, 0),     \
+        KL(L_, C_, LINE_FAST, LINE_FAST, true, 1), nullptr, nullptr)
+// four-step second pass: forward, inverse (swap out)
+#define ROWT(L_, C_)                                                                         \
+  ENTRY(L_, C_, ELEM_FAST, LINE_FAST, false, KL(L_, C_, ELEM_FAST, LINE_FAST, false, 0),   \
+        nullptr, KL(L_, C_, ELEM_FAST, LINE_FAST, false, 2), nullptr)
 
+#define KFN k_lines
+#define KPF false
+#define KEPT 16
 static const LineEntry kLineTable[] = {
     // batched rows (single-pass transforms, 2D row pass)
     ROW(1, 256), ROW(2, 256), ROW(4, 256), ROW(8, 256), ROW(16, 256), ROW(32, 128),
-    ROW(64, 64), ROW(128, 32), ROW(256, 16), ROW(512, 8), ROW(1024, 4), ROW(2048, 2),
-    ROW(4096, 1), ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
+    ROW(64, 64), ROW(128, 32), ROW(256, 16), ROW(512, 8), ROW(1024, 4), ROW(1024, 8),
+    ROW(2048, 2), ROW(2048, 4), ROW(4096, 1), ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
     // column tiles (2D column pass)
     COL(16, 64), COL(32, 32), COL(64, 16), COL(128, 16), COL(256, 16), COL(512, 16),
-    COL(1024, 16), COL(1024, 8), COL(2048, 8), COL(4096, 4),
+    COL(1024, 16), COL(1024, 8), COL(2048, 4), COL(2048, 8), COL(4096, 4),
     // column tiles with the four-step twiddle (first four-step pass)
     COLTW(64, 16), COLTW(128, 16), COLTW(256, 16), COLTW(256, 32), COLTW(512, 16),
-    COLTW(1024, 16), COLTW(1024, 8), COLTW(2048, 8), COLTW(4096, 4),
+    COLTW(1024, 16), COLTW(1024, 8), COLTW(2048, 4), COLTW(2048, 8), COLTW(4096, 4),
     // rows stored transposed (second four-step pass)
     ROWT(64, 16), ROWT(128, 16), ROWT(256, 16), ROWT(256, 32), ROWT(512, 16),
-    ROWT(1024, 16), ROWT(1024, 8), ROWT(2048, 8), ROWT(4096, 4),
+    ROWT(1024, 16), ROWT(1024, 8), ROWT(2048, 4), ROWT(2048, 8), ROWT(4096, 4),
 };
+#undef KFN
+#undef KPF
+#undef KEPT
+#define KFN k_lines_pf
+#define KPF true
+#define KEPT 16
+// persistent instances, 16 elements per thread (512-thread workgroups)
+static const LineEntry kLineTablePf[] = {
+    ROW(4096, 2), ROW(8192, 1),
+};
+#undef KFN
+#undef KPF
+#undef KEPT
+
+static void fill(const LineEntry &e, KernelInfo *out) {
+  for (int i = 0; i < 4; ++i) out->fn_sw[i] = e.fn[i];
+  out->fn = e.fn[0];
+  out->threads = e.threads;
+  out->lines = e.C;
+  out->lds_bytes = e.lds;
+  out->map = e.map;
+  out->omap = e.omap;
+  out->persistent = e.pf;
+}
+
+template <class F>
+static void for_each_entry(F f) {
+  for (const auto &e : kLineTable) f(e);
+  for (const auto &e : kLineTablePf) f(e);
+}
 
 bool find_line_kernel(int L, int C, int map, int omap, bool tw4, KernelInfo *out) {
   for (const auto &e : kLineTable) {
     if (e.L == L && e.C == C && e.map == map && e.omap == omap && e.tw4 == tw4) {
-      out->fn = e.fn;
-      out->threads = e.threads;
-      out->lines = e.C;
-      out->lds_bytes = e.lds;
+      fill(e, out);
       return true;
     }
   }
   return false;
 }
 
-int best_line_c(int L, int map, int omap, bool tw4, int cmax) {
-  int best = 0;
-  for (const auto &e : kLineTable)
-    if (e.L == L && e.map == map && e.omap == omap && e.tw4 == tw4 && e.C <= cmax && e.C > best)
-      best = e.C;
-  return best;
+int list_line_kernels(int L, int map, int omap, bool tw4, KernelInfo *out, int max) {
+  int n = 0;
+  for_each_entry([&](const LineEntry &e) {
+    if (e.L == L && e.map == map && e.omap == omap && e.tw4 == tw4) {
+      if (n < max) fill(e, &out[n]);
+      ++n;
+    }
+  });
+  return n;
 }
 
 }  // namespace dpfft

@@ -11,6 +11,7 @@
 
 #include "../../include/dpfft.h"
 #include "kernels.h"
+#include "mixed.h"
 
 namespace dpfft {
 
@@ -52,6 +53,8 @@ struct Step {
   virtual std::string describe() const = 0;
   // largest element index read from `src` / written to `dst` (-1 = none)
   virtual void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const = 0;
+  // layout assumptions of the kernel hold and every needed instance exists
+  virtual bool valid() const = 0;
 };
 
 struct LineStep : Step {
@@ -60,7 +63,8 @@ struct LineStep : Step {
   dim3 grid;
   int src = BUF_IN, dst = BUF_OUT;
   LineArgs a{};
-  size_t tw_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
+  size_t tw_off = 0, tw4_lo_off = 0, tw4_hi_off = 0, tw2_off = 0;
+  int resident = 0;  // persistent instances: workgroups resident on the device
   bool has_tw4 = false;
   bool first = false, last = false;  // receive the inverse swap / scale
   float inv_scale = 1.0f;
@@ -69,6 +73,29 @@ struct LineStep : Step {
   hipError_t launch(const ExecCtx &ctx) const override;
   std::string describe() const override;
   void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
+  bool valid() const override;
+  int inverse_sw() const;
+};
+
+struct MixedStep : Step {
+  MixedArgs a{};
+  const void *fn_sw[4] = {};
+  int map = ELEM_FAST, omap = ELEM_FAST;
+  bool tw4 = false;
+  dim3 grid;
+  int threads = 0;
+  int lds_bytes = 0;
+  int src = BUF_IN, dst = BUF_OUT;
+  size_t tw2_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
+  bool first = false, last = false;
+  float inv_scale = 1.0f;
+  std::string name;
+  int inverse_sw() const { return (first ? 1 : 0) | (last ? 2 : 0); }
+  void bind(const float2 *tables) override;
+  hipError_t launch(const ExecCtx &ctx) const override;
+  std::string describe() const override;
+  void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
+  bool valid() const override;
 };
 
 }  // namespace dpfft

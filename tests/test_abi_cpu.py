@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid descriptors before touching the device.
+On a machine without a GPU a valid plan gets as far as the table upload and
+fails there with FFT_E_DEVICE, which shows that validation, factorization,
+kernel choice and the plan's bounds checks all passed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpfft.h")
+
+
+def _dp():
+    import paper_1203_4938_amd as dp
+    return dp
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:fft_status_t|size_t|int|const char \*)\s*(fft_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    dp = _dp()
+    lib = ctypes.CDLL(dp.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) <= set(dp.EXPORTS)
+
+
+def test_status_strings():
+    dp = _dp()
+    assert dp.fft_status_str(dp.FFT_OK) == "FFT_OK"
+    assert dp.fft_status_str(dp.FFT_E_UNSUPPORTED) == "FFT_E_UNSUPPORTED"
+    assert dp.fft_status_str(99) == "FFT_E_UNKNOWN"
+
+
+def _plan_status(**kw):
+    dp = _dp()
+    d, keep = dp.make_desc(**kw)
+    st, h = dp.fft_plan(d)
+    return st, dp.fft_last_error()
+
+
+def _no_gpu():
+    import torch
+    return not torch.cuda.is_available()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=0, batch=4), 1),
+    (dict(n=-5, batch=4), 1),
+    (dict(n=16, batch=-1), 1),
+    (dict(n=16, batch=4, rank=3), 1),
+    (dict(n=16, batch=4, dist=8), 1),
+    (dict(n=16, batch=4, precision=9), 1),
+    (dict(n=16, batch=4, flags=1 << 9), 1),
+    (dict(n=11, batch=4), 2),
+    (dict(n=13 * 64, batch=4), 2),
+    (dict(n=(1 << 24) + 1, batch=1), 2),
+    (dict(n=1 << 25, batch=1), 2),
+    (dict(rank=2, shape=(100, 128), batch=1), 2),
+    (dict(rank=2, shape=(0, 128), batch=1), 1),
+    (dict(ragged_sizes=[64, 0, 16]), 1),
+    (dict(ragged_sizes=[64, 22, 16]), 2),
+])
+def test_invalid_descriptors_rejected_before_device(kw, status):
+    st, msg = _plan_status(**kw)
+    assert st == status, msg
+    assert msg
+
+
+def test_null_arguments():
+    dp = _dp()
+    assert dp._lib.fft_plan(None, None, None) == dp.FFT_E_INVALID
+    h = ctypes.c_void_p()
+    assert dp._lib.fft_plan(ctypes.byref(h), None, None) == dp.FFT_E_INVALID
+    assert dp.fft_exec(0, 0, 0, -1) == dp.FFT_E_INVALID
+    assert dp.fft_destroy(None) == dp.FFT_OK
+    assert dp.fft_workspace_bytes(None) == 0
+    assert dp.fft_plan_num_steps(None) == 0
+    assert dp.fft_plan_describe(None) == ""
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="checks the no-device path")
+@pytest.mark.parametrize("kw", [
+    dict(n=1, batch=3), dict(n=2, batch=3), dict(n=16, batch=1000), dict(n=1024, batch=7),
+    dict(n=4096, batch=64), dict(n=16384, batch=3), dict(n=1 << 15, batch=3),
+    dict(n=1 << 18, batch=2), dict(n=1 << 22, batch=2), dict(n=1 << 24, batch=1),
+    dict(n=2048, batch=5, dist=2100),
+    dict(rank=2, shape=(16, 32), batch=3), dict(rank=2, shape=(2048, 2048), batch=16),
+    dict(rank=2, shape=(128, 4096), batch=2),
+])
+def test_valid_plans_reach_the_device_step(kw):
+    st, msg = _plan_status(**kw)
+    assert st == 4, msg  # FFT_E_DEVICE: the first device call, after every host check
+    assert "hipMalloc" in msg

@@ -151,3 +151,39 @@ def test_exec_rejects_bad_arguments():
     z = torch.empty_like(y)
     st = dp.fft_exec(p4.handle, y.data_ptr(), z.data_ptr(), dp.FFT_FORWARD, 0, 0)
     assert st == dp.FFT_E_INVALID  # workspace required
+
+
+VARIANTS = [
+    (4096, 10, "p0=1"), (8192, 6, "p0=1"), (1024, 37, "c0=8"), (2048, 9, "c0=4"),
+    (4096, 7, "c0=2"), (1 << 22, 1, "c0=4 c1=4"), (1 << 20, 2, "c0=8 c1=8"),
+    (1 << 18, 3, "c0=32 c1=32"),
+]
+
+
+@pytest.mark.parametrize("n,batch,force", VARIANTS, ids=[f"{v[0]}-{v[2]}" for v in VARIANTS])
+def test_forced_variants(n, batch, force, monkeypatch):
+    """Every kernel variant the planner or the tuner may pick matches the oracle."""
+    dp = _dp()
+    monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
+    say(f"[variant] n={n} batch={batch} force={force}")
+    x = synth.uniform_complex(synth.BASE_SEED + 400, n, batch)
+    p = dp.Plan(n, batch)
+    say("   plan:", p.describe().replace("\n", " | "))
+    xd = to_dev(x)
+    for inv in (False, True):
+        y = run_plan(p, xd, inverse=inv).cpu().numpy()
+        e = max_rel(y, oracle.fft_batch(x, inverse=inv))
+        say(f"   inverse={inv} max rel L2 = {e:.3e}")
+        assert e <= TOL_FP32, (n, force, inv, e)
+
+
+@pytest.mark.parametrize("force", ["c1=8", "c1=4"])
+def test_forced_2d_variants(force, monkeypatch):
+    dp = _dp()
+    monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
+    x = synth.images_complex(synth.BASE_SEED + 3, 2, 2048, 2048)
+    p = dp.Plan(shape=(2048, 2048), batch=2, rank=2)
+    xd = to_dev(x)
+    for inv in (False, True):
+        y = run_plan(p, xd, inverse=inv).cpu().numpy()
+        assert max_rel(y, oracle.fft2d(x, inverse=inv)) <= TOL_FP32
