@@ -74,7 +74,9 @@ typedef enum {
 /* Plan flags. */
 #define FFT_F_INPLACE 1u     /* in == out is allowed */
 #define FFT_F_NO_AUTOTUNE 2u /* ignore the autotune cache, use the heuristic plan */
-#define FFT_F_GRAPH 4u       /* ragged plans: replay the launch as a captured HIP graph */
+#define FFT_F_GRAPH 4u       /* ragged plans: replay the launches as a HIP graph */
+#define FFT_F_PER_SIZE 8u    /* ragged plans: one launch per distinct length instead of
+                                the persistent queue (the comparison baseline) */
 
 typedef struct {
   int32_t rank;     /* 1: batched 1D signals; 2: batched images */
@@ -129,6 +131,33 @@ int fft_plan_num_steps(fft_plan_t plan);
  * fft_exec; FFT_E_INVALID if the range is outside [0, fft_plan_num_steps). */
 fft_status_t fft_exec_steps(fft_plan_t plan, const void *in, void *out, int direction,
                             void *workspace, void *hip_stream, int first, int count);
+
+/* Plan without touching the device: validation, factorization, kernel choice
+ * and the bounds checks of fft_plan, then the plan description (as
+ * fft_plan_describe) in buf.  Same status codes as fft_plan except that no
+ * device error can occur. */
+fft_status_t fft_plan_dry(const fft_desc_t *desc, char *buf, size_t len);
+
+/* Autotune: build every compiled kernel variant the planner could use for
+ * *desc (tile widths, persistent form, radix order of non-power-of-two
+ * lengths), time `reps` forward executions of each on `hip_stream` with HIP
+ * events on scratch buffers it allocates and frees, and record the fastest
+ * for (architecture, shape, batch rounded down to a power of two, precision).
+ * Later fft_plan calls for that key use it unless FFT_F_NO_AUTOTUNE is set.
+ * If the environment variable DPFFT_TUNE_CACHE names a file, the record is
+ * also written there as JSON and read back by later processes (a missing or
+ * unreadable file is treated as empty).  A per-candidate report (one line per
+ * candidate, then the choice) goes to `report` (may be NULL).  Synchronizes
+ * the stream.  Ragged plans and MFMA precision forms have nothing to tune
+ * (FFT_OK, report says so). */
+fft_status_t fft_autotune(const fft_desc_t *desc, void *hip_stream, int reps, char *report,
+                          size_t len);
+
+/* Ragged plans (persistent queue): wait for hip_stream, then set *error to 1
+ * if the last execution that used `workspace` gave up waiting on an
+ * unfinished dependency (its output is then not valid), else to 0.  Other
+ * plans set *error to 0 without waiting.  FFT_E_INVALID on NULL arguments. */
+fft_status_t fft_exec_check(fft_plan_t plan, void *workspace, void *hip_stream, int *error);
 
 /* Release a plan and its device tables.  fft_destroy(NULL) returns FFT_OK.
  * The caller must ensure no execution of the plan is still pending. */

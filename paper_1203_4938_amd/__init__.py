@@ -21,12 +21,13 @@ LIB_PATH = os.path.join(_HERE, "libdpfft.so")
 
 FFT_OK, FFT_E_INVALID, FFT_E_UNSUPPORTED, FFT_E_NOMEM, FFT_E_DEVICE, FFT_E_INTERNAL = range(6)
 FFT_FORWARD, FFT_INVERSE = -1, +1
-FFT_F_INPLACE, FFT_F_NO_AUTOTUNE, FFT_F_GRAPH = 1, 2, 4
+FFT_F_INPLACE, FFT_F_NO_AUTOTUNE, FFT_F_GRAPH, FFT_F_PER_SIZE = 1, 2, 4, 8
 PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4, "bf16_split3": 5}
 
 #: names of every C entry point declared in include/dpfft.h
 EXPORTS = ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
-           "fft_last_error", "fft_plan_describe", "fft_plan_num_steps", "fft_exec_steps")
+           "fft_last_error", "fft_plan_describe", "fft_plan_num_steps", "fft_exec_steps",
+           "fft_exec_check", "fft_plan_dry", "fft_autotune")
 
 
 class FftError(RuntimeError):
@@ -66,6 +67,13 @@ def _load() -> ctypes.CDLL:
     lib.fft_plan_num_steps.restype = ctypes.c_int
     lib.fft_exec_steps.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.fft_exec_steps.restype = ctypes.c_int
+    lib.fft_exec_check.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int)]
+    lib.fft_exec_check.restype = ctypes.c_int
+    lib.fft_plan_dry.argtypes = [ctypes.POINTER(FftDesc), ctypes.c_char_p, ctypes.c_size_t]
+    lib.fft_plan_dry.restype = ctypes.c_int
+    lib.fft_autotune.argtypes = [ctypes.POINTER(FftDesc), vp, ctypes.c_int, ctypes.c_char_p,
+                                 ctypes.c_size_t]
+    lib.fft_autotune.restype = ctypes.c_int
     return lib
 
 
@@ -109,6 +117,28 @@ def fft_exec_steps(handle: int, in_ptr: int, out_ptr: int, direction: int, works
     return _lib.fft_exec_steps(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr),
                                ctypes.c_void_p(out_ptr), direction, ctypes.c_void_p(workspace),
                                ctypes.c_void_p(stream), first, count)
+
+
+def fft_exec_check(handle: int, workspace: int, stream: int = 0) -> tuple[int, int]:
+    """Returns (status, error flag) of the last ragged execution on `workspace`."""
+    err = ctypes.c_int(0)
+    st = _lib.fft_exec_check(ctypes.c_void_p(handle), ctypes.c_void_p(workspace),
+                             ctypes.c_void_p(stream), ctypes.byref(err))
+    return st, err.value
+
+
+def fft_plan_dry(desc: FftDesc) -> tuple[int, str]:
+    """Plan on the host only; returns (status, description or error message)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    st = _lib.fft_plan_dry(ctypes.byref(desc), buf, len(buf))
+    return st, (buf.value.decode() if st == FFT_OK else fft_last_error())
+
+
+def fft_autotune(desc: FftDesc, stream: int = 0, reps: int = 10) -> tuple[int, str]:
+    """Time the candidate kernel variants for desc; returns (status, report)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    st = _lib.fft_autotune(ctypes.byref(desc), ctypes.c_void_p(stream), reps, buf, len(buf))
+    return st, (buf.value.decode() if st == FFT_OK else fft_last_error())
 
 
 def fft_destroy(handle: Optional[int]) -> int:
@@ -168,9 +198,10 @@ class Plan:
 
     def __init__(self, n: Optional[int] = None, batch: int = 1, *, rank: int = 1, shape=None,
                  dist: int = 0, ragged_sizes=None, ragged_offsets=None, precision: str = "fp32",
-                 inplace: bool = False, graph: bool = False, autotune: bool = True, stream=None):
+                 inplace: bool = False, graph: bool = False, per_size: bool = False,
+                 autotune: bool = True, stream=None):
         flags = (FFT_F_INPLACE if inplace else 0) | (FFT_F_GRAPH if graph else 0) | \
-                (0 if autotune else FFT_F_NO_AUTOTUNE)
+                (FFT_F_PER_SIZE if per_size else 0) | (0 if autotune else FFT_F_NO_AUTOTUNE)
         self.desc, self._keep = make_desc(n, batch, rank=rank, shape=shape, dist=dist,
                                           ragged_sizes=ragged_sizes, ragged_offsets=ragged_offsets,
                                           precision=precision, flags=flags)
@@ -224,6 +255,15 @@ class Plan:
         if st != FFT_OK:
             raise FftError(st, "fft_exec", fft_last_error())
         return out
+
+    def check(self, stream=None) -> int:
+        """Ragged plans: 1 if the last execution gave up on a dependency wait."""
+        ws = self._ws
+        st, err = fft_exec_check(self.handle, ws.data_ptr() if ws is not None else 0,
+                                 _stream_handle(stream))
+        if st != FFT_OK:
+            raise FftError(st, "fft_exec_check", fft_last_error())
+        return err
 
     def num_steps(self) -> int:
         return fft_plan_num_steps(self.handle)

@@ -8,19 +8,43 @@
 #include <sstream>
 #include <string>
 
+#include "internal.h"
 #include "plan.h"
 #include "twiddle.h"
 
 using namespace dpfft;
 
 namespace {
-
 thread_local std::string g_last_error;
+}
 
+namespace dpfft {
 fft_status_t fail(fft_status_t s, const std::string &msg) {
   g_last_error = msg;
   return s;
 }
+
+int64_t split_factor(int64_t n) {
+  int64_t best = 1;
+  for (int64_t d = 1; d * d <= n; ++d)
+    if (n % d == 0) best = d;
+  return best;
+}
+
+int resident_for(int lds_bytes, int threads) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  int by_lds = lds_bytes ? kLdsBytes / lds_bytes : 8;
+  int by_thr = 2048 / threads;
+  return cus * std::max(1, std::min(by_lds, by_thr));
+}
+}  // namespace dpfft
+
+namespace {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -41,9 +65,6 @@ int64_t largest_prime_factor(int64_t n) {
   return n > 1 ? n : best;
 }
 
-constexpr int64_t kMaxN = int64_t(1) << 24;
-constexpr int kSinglePassMax = 16384;  // largest L of a one-workgroup transform
-constexpr int kLdsBytes = 160 * 1024;
 
 }  // namespace
 
@@ -174,6 +195,48 @@ std::string MixedStep::describe() const {
   return o.str();
 }
 
+// ---- matrix-core steps ----
+void MfmaStep::bind(const float2 *tables) {
+  a.amat = reinterpret_cast<const uint16_t *>(tables + amat_off);
+  a.tw16 = tables + tw16_off;
+  if (tw4) {
+    a.tw4_lo = tables + tw4_lo_off;
+    a.tw4_hi = tables + tw4_hi_off;
+  }
+}
+
+hipError_t MfmaStep::launch(const ExecCtx &ctx) const {
+  MfmaArgs args = a;
+  const void *fn = fn_sw[0];
+  if (ctx.inverse) {
+    fn = fn_sw[inverse_sw()];
+    if (last) args.scale = inv_scale;
+  }
+  const float2 *s = buf_c(ctx, src, 0);
+  float2 *d = buf_m(ctx, dst, 0);
+  void *kargs[] = {(void *)&s, (void *)&d, (void *)&args};
+  return hipLaunchKernel(fn, grid, dim3(kMfmaThreads), kargs, 0, ctx.stream);
+}
+
+void MfmaStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const {
+  const int64_t nb = (int64_t)grid.x / a.tiles_per_batch;
+  const int64_t last_line = std::min<int64_t>(a.lines, a.tiles_per_batch * kMfmaLines) - 1;
+  max_in = (nb - 1) * a.in_b + last_line * a.in_l + 255 * a.in_e;
+  max_out = (nb - 1) * a.out_b + last_line * a.out_l + 255 * a.out_e;
+  src_id = src;
+  dst_id = dst;
+}
+
+bool MfmaStep::valid() const { return fn_sw[0] && fn_sw[inverse_sw()]; }
+
+std::string MfmaStep::describe() const {
+  static const char *names[] = {"fp32", "fp16", "bf16", "fp16_split", "bf16_split", "bf16_split3"};
+  std::ostringstream o;
+  o << name << ": L=256 (DFT-16 x DFT-16 on MFMA, " << names[prec] << ") C=" << kMfmaLines
+    << " threads=" << kMfmaThreads << " grid=" << grid.x << " lds=" << mfma_lds_bytes() << "B";
+  return o.str();
+}
+
 }  // namespace dpfft
 
 dpfft_plan_s::~dpfft_plan_s() {
@@ -185,43 +248,22 @@ dpfft_plan_s::~dpfft_plan_s() {
 // ---------------------------------------------------------------------------
 namespace {
 
-// Per-step tile-width overrides "c<i>=<C>" from DPFFT_FORCE_PLAN (a testing
-// and tuning hook); -1 = no override.
-struct Override {
-  int c[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-  int p[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-};
+// Override in force for a plan being built (see internal.h for the sources).
+thread_local const fft_desc_t *g_building = nullptr;
 
 Override read_override() {
-  Override o;
-  const char *env = getenv("DPFFT_FORCE_PLAN");
-  if (!env) return o;
-  std::istringstream in(env);
-  std::string tok;
-  while (in >> tok) {
-    char kind = 0;
-    int idx = -1, val = -1;
-    if (sscanf(tok.c_str(), "%c%d=%d", &kind, &idx, &val) == 3 && idx >= 0 && idx < 8) {
-      if (kind == 'c') o.c[idx] = val;
-      if (kind == 'p') o.p[idx] = val;
-    }
+  if (const Override *t = tuner_override()) return *t;
+  if (const char *env = getenv("DPFFT_FORCE_PLAN")) return parse_override(env);
+  if (g_building && !(g_building->flags & FFT_F_NO_AUTOTUNE)) {
+    const std::string key = tune_key(g_building);
+    std::string val;
+    if (!key.empty() && tune_cache_lookup(key, &val)) return parse_override(val);
   }
-  return o;
+  return Override{};
 }
 
-// Workgroups of a persistent instance that stay resident on the device: the
-// CU count times what one CU holds by LDS and threads.
-int resident_workgroups(const KernelInfo &k) {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-  }
-  int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 8;
-  int by_thr = 2048 / k.threads;
-  return cus * std::max(1, std::min(by_lds, by_thr));
-}
+// Workgroups of a persistent instance that stay resident on the device.
+int resident_workgroups(const KernelInfo &k) { return resident_for(k.lds_bytes, k.threads); }
 
 // Heuristic choice among the compiled instances of a line kernel: the most
 // resident waves per CU that the 160 KB LDS allows (counted up to 16), then
@@ -244,7 +286,7 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
     int by_thr = 2048 / k.threads;
     int wg = std::min(by_lds, by_thr);
     double waves = wg * (k.threads / 64.0);
-    double tie = map == LINE_FAST ? k.lines : 1.0 / k.lines;
+    double tie = (map == LINE_FAST || omap == LINE_FAST) ? k.lines : 1.0 / k.lines;
     double score = std::min(waves, 16.0) * 1000 + tie;
     if (score > best) {
       best = score;
@@ -390,7 +432,8 @@ fft_status_t plan_pow2_2d(dpfft_plan_s *P) {
 std::unique_ptr<MixedStep> make_mixed(dpfft_plan_s *P, const char *name, int64_t L, int map,
                                       int omap, bool tw4, int C) {
   auto s = std::make_unique<MixedStep>();
-  if (!mixed_radices(L, &s->a.mp)) return nullptr;
+  const Override ov = read_override();
+  if (!mixed_radices(L, &s->a.mp, ov.order > 0 ? ov.order : 0)) return nullptr;
   s->a.mp.C = C;
   s->map = map;
   s->omap = omap;
@@ -428,18 +471,16 @@ int mixed_lines(int64_t L, int map, int omap, int thr, int cmin) {
   return C;
 }
 
-// largest divisor of n that is <= sqrt(n)
-int64_t split_factor(int64_t n) {
-  int64_t best = 1;
-  for (int64_t d = 1; d * d <= n; ++d)
-    if (n % d == 0) best = d;
-  return best;
-}
-
 fft_status_t plan_mixed_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch, D = P->dist;
+  const Override ov = read_override();
   if (N <= kSinglePassMax) {
-    const int C = mixed_lines(N, ELEM_FAST, ELEM_FAST, 256, 1);
+    int C = mixed_lines(N, ELEM_FAST, ELEM_FAST, 256, 1);
+    if (ov.c[0] > 0) {
+      const int cmax = mixed_lines(N, ELEM_FAST, ELEM_FAST, 1024, 1);
+      if (ov.c[0] > cmax) return fail(FFT_E_UNSUPPORTED, "override c0 too large for N");
+      C = ov.c[0];
+    }
     auto s = C ? make_mixed(P, "mixed_rows", N, ELEM_FAST, ELEM_FAST, false, C) : nullptr;
     if (!s) return fail(FFT_E_UNSUPPORTED, "no mixed-radix plan for N=" + std::to_string(N));
     s->a.in_b = s->a.out_b = 0;
@@ -506,6 +547,85 @@ fft_status_t plan_mixed_1d(dpfft_plan_s *P) {
   return FFT_OK;
 }
 
+std::unique_ptr<MfmaStep> make_mfma(dpfft_plan_s *P, const char *name, int prec, int map,
+                                    int omap, bool tw4) {
+  auto s = std::make_unique<MfmaStep>();
+  s->prec = prec;
+  s->name = name;
+  s->tw4 = tw4;
+  for (int sw = 0; sw < 4; ++sw) s->fn_sw[sw] = mfma_kernel(prec, map, omap, tw4, sw);
+  const std::vector<uint16_t> am = mfma_dft16_operands(prec);
+  s->amat_off = P->tables.add_bytes(am.data(), am.size() * sizeof(uint16_t));
+  std::vector<std::complex<double>> t16(256);
+  for (int k1 = 0; k1 < 16; ++k1)
+    for (int n2 = 0; n2 < 16; ++n2) t16[k1 * 16 + n2] = omega(256, (int64_t)n2 * k1);
+  s->tw16_off = P->tables.add(t16);
+  s->a.scale = 1.0f;
+  return s;
+}
+
+// Matrix-core plans: N = 256 (one pass) and N = 65536 (four-step 256 x 256).
+fft_status_t plan_mfma_1d(dpfft_plan_s *P) {
+  const int64_t N = P->n, B = P->batch, D = P->dist;
+  const int prec = P->precision;
+  const int C = kMfmaLines;
+  if (N == 256) {
+    auto s = make_mfma(P, "mfma_rows", prec, ELEM_FAST, ELEM_FAST, false);
+    s->a.in_b = s->a.out_b = 0;
+    s->a.in_l = s->a.out_l = D;
+    s->a.in_e = s->a.out_e = 1;
+    s->a.lines = B;
+    s->a.tiles_per_batch = (B + C - 1) / C;
+    s->grid = dim3((unsigned)s->a.tiles_per_batch);
+    s->first = s->last = true;
+    s->inv_scale = 1.0f / 256.0f;
+    P->steps.push_back(std::move(s));
+    P->variant = "mfma single-pass";
+    return FFT_OK;
+  }
+  if (N != 65536)
+    return fail(FFT_E_UNSUPPORTED, "MFMA precision forms support N = 256 and N = 65536");
+  auto a = make_mfma(P, "mfma_fourstep_columns", prec, LINE_FAST, LINE_FAST, true);
+  auto b = make_mfma(P, "mfma_fourstep_rows_transposed", prec, ELEM_FAST, LINE_FAST, false);
+  std::vector<std::complex<double>> lo, hi;
+  fourstep_tables(N, 8, lo, hi);
+  a->tw4_lo_off = P->tables.add(lo);
+  a->tw4_hi_off = P->tables.add(hi);
+  a->a.tw4_shift = 8;
+  a->a.in_b = D;
+  a->a.in_l = 1;
+  a->a.in_e = 256;
+  a->a.out_b = N;
+  a->a.out_l = 1;
+  a->a.out_e = 256;
+  a->a.lines = 256;
+  a->a.tiles_per_batch = 256 / C;
+  a->a.flags = F_REMAP;
+  a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
+  a->first = true;
+  a->src = BUF_IN;
+  a->dst = BUF_WS;
+  b->a.in_b = N;
+  b->a.in_l = 256;
+  b->a.in_e = 1;
+  b->a.out_b = D;
+  b->a.out_l = 1;
+  b->a.out_e = 256;
+  b->a.lines = 256;
+  b->a.tiles_per_batch = 256 / C;
+  b->a.flags = F_REMAP;
+  b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
+  b->last = true;
+  b->inv_scale = (float)(1.0 / (double)N);
+  b->src = BUF_WS;
+  b->dst = BUF_OUT;
+  P->steps.push_back(std::move(a));
+  P->steps.push_back(std::move(b));
+  P->ws_bytes = (size_t)B * (size_t)N * sizeof(float2);
+  P->variant = "mfma four-step 256x256";
+  return FFT_OK;
+}
+
 fft_status_t validate_desc(const fft_desc_t *d) {
   if (!d) return fail(FFT_E_INVALID, "desc is NULL");
   if (d->rank != 1 && d->rank != 2) return fail(FFT_E_INVALID, "rank must be 1 or 2");
@@ -513,7 +633,7 @@ fft_status_t validate_desc(const fft_desc_t *d) {
   if (d->dist < 0) return fail(FFT_E_INVALID, "dist must be >= 0");
   if (d->precision < FFT_FP32 || d->precision > FFT_BF16_SPLIT3)
     return fail(FFT_E_INVALID, "unknown precision");
-  if (d->flags & ~(FFT_F_INPLACE | FFT_F_NO_AUTOTUNE | FFT_F_GRAPH))
+  if (d->flags & ~(FFT_F_INPLACE | FFT_F_NO_AUTOTUNE | FFT_F_GRAPH | FFT_F_PER_SIZE))
     return fail(FFT_E_INVALID, "unknown flag bits");
   if (d->ragged_offsets && !d->ragged_sizes)
     return fail(FFT_E_INVALID, "ragged_offsets given without ragged_sizes");
@@ -568,9 +688,10 @@ const char *fft_status_str(fft_status_t s) {
 
 const char *fft_last_error(void) { return g_last_error.c_str(); }
 
-fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream) {
-  if (!out) return fail(FFT_E_INVALID, "out is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+// Host part of fft_plan: validation, kernel choice, tables, bounds checks.
+static fft_status_t build_plan(const fft_desc_t *desc, std::unique_ptr<dpfft_plan_s> &out) {
   fft_status_t st = validate_desc(desc);
   if (st != FFT_OK) return st;
   auto P = std::make_unique<dpfft_plan_s>();
@@ -586,22 +707,33 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
     P->nx = desc->n[1];
     P->dist = desc->dist ? desc->dist : desc->n[0] * desc->n[1];
   }
-  if (desc->rank == 1 && desc->ragged_sizes)
-    return fail(FFT_E_UNSUPPORTED, "ragged batches are not implemented yet");
-  if (desc->precision != FFT_FP32)
-    return fail(FFT_E_UNSUPPORTED, "only FFT_FP32 is implemented for this shape");
+  if (desc->precision != FFT_FP32 && desc->rank != 1)
+    return fail(FFT_E_UNSUPPORTED, "MFMA precision forms are rank 1 only");
+  if (desc->rank == 1 && desc->ragged_sizes && desc->precision != FFT_FP32)
+    return fail(FFT_E_UNSUPPORTED, "ragged batches are FFT_FP32 only");
 
-  if (desc->rank == 1) {
-    st = is_pow2(P->n) ? plan_pow2_1d(P.get()) : plan_mixed_1d(P.get());
+  struct Guard {
+    Guard(const fft_desc_t *d) { g_building = d; }
+    ~Guard() { g_building = nullptr; }
+  } guard(desc);
+  const Override ov = read_override();
+  if (desc->rank == 1 && desc->ragged_sizes) {
+    st = plan_ragged(P.get(), desc->ragged_sizes, desc->ragged_offsets);
+  } else if (desc->rank == 1) {
+    if (desc->precision != FFT_FP32)
+      st = plan_mfma_1d(P.get());
+    else
+      st = is_pow2(P->n) ? plan_pow2_1d(P.get()) : plan_mixed_1d(P.get());
   } else {
     st = plan_pow2_2d(P.get());
   }
   if (st != FFT_OK) return st;
 
   // every index a kernel forms must stay inside its buffer
-  P->io_elems = P->batch == 0 ? 0
-                : P->rank == 1 ? (P->batch - 1) * P->dist + P->n
-                               : (P->batch - 1) * P->dist + P->ny * P->nx;
+  if (P->rsizes.empty())
+    P->io_elems = P->batch == 0 ? 0
+                  : P->rank == 1 ? (P->batch - 1) * P->dist + P->n
+                                 : (P->batch - 1) * P->dist + P->ny * P->nx;
   if (P->batch > 0) {
     for (auto &s : P->steps) {
       int64_t mi, mo;
@@ -616,6 +748,43 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
         return fail(FFT_E_INTERNAL, "plan layout check failed in " + s->describe());
     }
   }
+
+  std::ostringstream o;
+  if (!P->rsizes.empty())
+    o << "rank=1 ragged count=" << P->batch;
+  else if (P->rank == 1)
+    o << "rank=1 N=" << P->n << " batch=" << P->batch << " dist=" << P->dist;
+  else
+    o << "rank=2 ny=" << P->ny << " nx=" << P->nx << " batch=" << P->batch << " dist=" << P->dist;
+  o << " variant=" << P->variant << " launches=" << P->steps.size()
+    << " workspace=" << P->ws_bytes << "B tables=" << P->tables.host.size() * sizeof(float2) << "B";
+  if (!ov.empty()) o << " override=\"" << ov.text << "\"";
+  for (auto &s : P->steps) o << "\n  " << s->describe();
+  P->text = o.str();
+  out = std::move(P);
+  return FFT_OK;
+}
+
+extern "C" {
+
+fft_status_t fft_plan_dry(const fft_desc_t *desc, char *buf, size_t len) {
+  std::unique_ptr<dpfft_plan_s> P;
+  fft_status_t st = build_plan(desc, P);
+  if (st != FFT_OK) return st;
+  if (buf && len) {
+    const size_t n = std::min(P->text.size(), len - 1);
+    memcpy(buf, P->text.data(), n);
+    buf[n] = 0;
+  }
+  return FFT_OK;
+}
+
+fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream) {
+  if (!out) return fail(FFT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<dpfft_plan_s> P;
+  fft_status_t st = build_plan(desc, P);
+  if (st != FFT_OK) return st;
 
   // upload every table in one allocation
   hipStream_t stream = (hipStream_t)hip_stream;
@@ -633,17 +802,6 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
       return fail(FFT_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
   }
   for (auto &s : P->steps) s->bind(P->tables.dev);
-
-  std::ostringstream o;
-  if (P->rank == 1)
-    o << "rank=1 N=" << P->n;
-  else
-    o << "rank=2 ny=" << P->ny << " nx=" << P->nx;
-  o << " batch=" << P->batch << " dist=" << P->dist << " variant=" << P->variant
-    << " hbm_passes=" << P->steps.size() << " workspace=" << P->ws_bytes << "B"
-    << " tables=" << bytes << "B";
-  for (auto &s : P->steps) o << "\n  " << s->describe();
-  P->text = o.str();
   if (getenv("DPFFT_LOG")) fprintf(stderr, "[dpfft] plan %s\n", P->text.c_str());
   *out = P.release();
   return FFT_OK;
@@ -683,6 +841,20 @@ fft_status_t fft_exec_steps(fft_plan_t plan, const void *in, void *out, int dire
 }
 
 int fft_plan_num_steps(fft_plan_t plan) { return plan ? (int)plan->steps.size() : 0; }
+
+fft_status_t fft_exec_check(fft_plan_t plan, void *workspace, void *hip_stream, int *error) {
+  if (!plan || !error) return fail(FFT_E_INVALID, "plan/error is NULL");
+  *error = 0;
+  if (plan->rsizes.empty() || (plan->flags & FFT_F_PER_SIZE) || plan->batch == 0) return FFT_OK;
+  if (!workspace) return fail(FFT_E_INVALID, "ragged plans need their workspace");
+  uint32_t flag = 0;
+  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(&flag, (const char *)workspace + sizeof(uint32_t), sizeof(flag), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("fft_exec_check: ") + hipGetErrorString(e));
+  *error = flag ? 1 : 0;
+  return FFT_OK;
+}
 
 fft_status_t fft_destroy(fft_plan_t plan) {
   delete plan;

@@ -1,0 +1,53 @@
+// Helpers shared by the plan builders of the library (host only).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/dpfft.h"
+
+namespace dpfft {
+
+constexpr int64_t kMaxN = int64_t(1) << 24;
+constexpr int kSinglePassMax = 16384;  // longest line one workgroup transforms
+constexpr int kLdsBytes = 160 * 1024;  // LDS of one CU
+
+// Record `msg` as this thread's last error and return `s`.
+fft_status_t fail(fft_status_t s, const std::string &msg);
+
+// Largest divisor of n that is <= sqrt(n).
+int64_t split_factor(int64_t n);
+
+// Workgroups that fit on the device at once for `lds_bytes` and `threads`.
+int resident_for(int lds_bytes, int threads);
+
+// Kernel-choice overrides for the plan builders, per launch step i:
+//   c<i>=<C>   lines (rows or columns) per workgroup
+//   p<i>=0|1   persistent variant off / on
+//   o=0|1      radix order of runtime-radix lengths: powers of two first / odd first
+// Sources, first match wins: the autotuner while it times candidates, the
+// DPFFT_FORCE_PLAN environment variable, the tuning cache entry of the plan.
+struct Override {
+  int c[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int p[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int order = -1;
+  std::string text;
+  bool empty() const { return text.empty(); }
+};
+Override parse_override(const std::string &text);
+
+// Thread-local override installed by the autotuner around candidate plans.
+void set_tuner_override(const Override *o);
+const Override *tuner_override();
+
+// Tuning cache: in-process map, loaded on first use from the JSON file named by
+// DPFFT_TUNE_CACHE (a missing or corrupt file leaves it empty).
+bool tune_cache_lookup(const std::string &key, std::string *value);
+void tune_cache_store(const std::string &key, const std::string &value);
+
+}  // namespace dpfft
+
+struct dpfft_plan_s;
+// key of a plan in the tuning cache ("" = not tunable)
+std::string tune_key(const fft_desc_t *d);
+fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *offsets);

@@ -1,0 +1,273 @@
+// 256-point line transforms with the DFT-16 stages on the matrix cores.
+//
+// A 256-point DFT is split as 16 x 16 (n = n2 + 16 n1, k = k1 + 16 k2):
+//   stage 1: for each n2, a DFT-16 over n1          -> Y1[k1][n2]
+//   twiddle: Y1[k1][n2] *= w_256^{n2 k1}            (FP32, on the vector ALUs)
+//   stage 2: for each k1, a DFT-16 over n2          -> X[k1 + 16 k2]
+// Each stage applies the 16x16 complex DFT matrix W to 16 vectors at once,
+// written as a real product of a 16x32 matrix and a 32x16 matrix:
+//   [Yr] = [Wr -Wi] [Xr]        A_re = [ cos | sin ]   (row i, column k)
+//   [Yi]   [Wi  Wr] [Xi]        A_im = [-sin | cos ],  angle 2 pi i k / 16
+// so a stage is one v_mfma_f32_16x16x32_{f16,bf16} for Yr and one for Yi,
+// accumulating in FP32.  Operand layouts (64-wide wave, 16x16x32 shape):
+//   A: lane l holds row (l & 15), k = 8 (l >> 4) + t, t = 0..7
+//   B: lane l holds column (l & 15), k = 8 (l >> 4) + t
+//   D: lane l holds column (l & 15), rows 4 (l >> 4) + t, t = 0..3
+// (only the pairing of A and B k-slots matters for the sum, and both are
+// built with the same convention).
+//
+// Split forms recover FP32 accuracy from 16-bit products.  With pieces
+// x = xh + 2^-s xl (+ 2^-2s xll) and the same for W, scaled so every piece is
+// a normal-range 16-bit number:
+//   2 pieces: Y = Wh xh + 2^-s (Wh xl + Wl xh)                 (3 products)
+//   3 pieces: Y = Wh xh + 2^-s (Wh xm + Wm xh)
+//                       + 2^-2s (Wh xl + Wm xm + Wl xh)         (6 products)
+// each group in its own FP32 accumulator (Ootomo and Yokota's scaled split for
+// matrix units, SC 2022).  The W pieces are made on the host in FP64; the data
+// pieces are made here with round-to-nearest-even conversions.
+#include "fft_common.h"
+#include "kernels.h"
+#include "mfma.h"
+
+namespace dpfft {
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kPitch = 256 + 16 + 1;  // LDS pitch of a line (pad: one per 16, plus one)
+
+__device__ __forceinline__ int tidx(int c, int pos) { return c * kPitch + pos + (pos >> 4); }
+
+template <int PREC> struct Piece;
+template <> struct Piece<MP_FP16> {
+  typedef f16x8 vec;
+  __device__ static _Float16 cvt(float x) { return (_Float16)x; }
+  __device__ static float back(_Float16 h) { return (float)h; }
+};
+template <> struct Piece<MP_BF16> {
+  typedef bf16x8 vec;
+  __device__ static __bf16 cvt(float x) { return (__bf16)x; }
+  __device__ static float back(__bf16 h) { return (float)h; }
+};
+
+template <int PREC> constexpr int base_of() {
+  return (PREC == MP_FP16 || PREC == MP_FP16_SPLIT) ? MP_FP16 : MP_BF16;
+}
+
+template <int B>
+__device__ __forceinline__ f32x4 mfma(typename Piece<B>::vec a, typename Piece<B>::vec b, f32x4 c) {
+  if constexpr (B == MP_FP16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// split eight FP32 values into NP 16-bit pieces (scaled by 2^s between pieces)
+template <int PREC>
+__device__ __forceinline__ void split8(const float (&x)[8],
+                                       typename Piece<base_of<PREC>()>::vec (&p)[3]) {
+  constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
+  constexpr float up = (float)(1 << mfma_piece_shift(PREC));
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    float r = x[t];
+#pragma unroll
+    for (int q = 0; q < NPC; ++q) {
+      const auto h = Piece<B>::cvt(r);
+      p[q][t] = h;
+      r = (r - Piece<B>::back(h)) * up;  // exact: the remainder has <= 24 - width bits
+    }
+  }
+}
+
+// One DFT-16 stage: D = W X for the 16 vectors held in B layout.
+template <int PREC>
+__device__ __forceinline__ void dft16_stage(const typename Piece<base_of<PREC>()>::vec (&are)[3],
+                                            const typename Piece<base_of<PREC>()>::vec (&aim)[3],
+                                            const float (&xv)[8], f32x4 &dre, f32x4 &dim) {
+  constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
+  constexpr float down = 1.0f / (float)(1 << mfma_piece_shift(PREC));
+  typename Piece<B>::vec xp[3];
+  split8<PREC>(xv, xp);
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  f32x4 r0 = mfma<B>(are[0], xp[0], z);
+  f32x4 i0 = mfma<B>(aim[0], xp[0], z);
+  if constexpr (NPC >= 2) {
+    f32x4 r1 = mfma<B>(are[0], xp[1], z);
+    r1 = mfma<B>(are[1], xp[0], r1);
+    f32x4 i1 = mfma<B>(aim[0], xp[1], z);
+    i1 = mfma<B>(aim[1], xp[0], i1);
+    if constexpr (NPC == 3) {
+      f32x4 r2 = mfma<B>(are[0], xp[2], z);
+      r2 = mfma<B>(are[1], xp[1], r2);
+      r2 = mfma<B>(are[2], xp[0], r2);
+      f32x4 i2 = mfma<B>(aim[0], xp[2], z);
+      i2 = mfma<B>(aim[1], xp[1], i2);
+      i2 = mfma<B>(aim[2], xp[0], i2);
+      r1 = r1 + r2 * down;
+      i1 = i1 + i2 * down;
+    }
+    r0 = r0 + r1 * down;
+    i0 = i0 + i1 * down;
+  }
+  dre = r0;
+  dim = i0;
+}
+
+}  // namespace
+
+// C = 16 lines of 256 points per workgroup of 256 threads (4 waves, 4 lines
+// each).  The tile is loaded coalesced into LDS, each wave runs the two MFMA
+// stages of its lines (the stage-1 result goes through a per-wave LDS scratch
+// to reach the B layout of stage 2), and the tile is stored coalesced.
+template <int PREC, int MAP, int OMAP, bool TW4, int SW>
+__global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__ in,
+                                                          cf *__restrict__ out, MfmaArgs a) {
+  constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
+  constexpr int C = kMfmaLines;
+  __shared__ cf tile[C * kPitch];
+  __shared__ cf scratch[4][16 * 17];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t tileid = (a.flags & F_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t bb = tileid / a.tiles_per_batch;
+  const int64_t line0 = (tileid - bb * a.tiles_per_batch) * C;
+
+  // A operands (DFT-16 matrix pieces) for this lane
+  typename Piece<B>::vec are[3], aim[3];
+#pragma unroll
+  for (int q = 0; q < NPC; ++q) {
+    const uint4 ur = *reinterpret_cast<const uint4 *>(a.amat + ((q * 2 + 0) * 64 + lane) * 8);
+    const uint4 ui = *reinterpret_cast<const uint4 *>(a.amat + ((q * 2 + 1) * 64 + lane) * 8);
+    are[q] = __builtin_bit_cast(typename Piece<B>::vec, ur);
+    aim[q] = __builtin_bit_cast(typename Piece<B>::vec, ui);
+  }
+  const int col = lane & 15, g4 = lane >> 4;
+  // inter-stage twiddles w_256^{n2 k1} for n2 = col, k1 = 4 g4 + t
+  cf tw[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) tw[t] = a.tw16[(4 * g4 + t) * 16 + col];
+
+  // ---- load the tile (C lines x 256) coalesced, into LDS ----
+  {
+    const int c = MAP == ELEM_FAST ? tid >> 4 : tid & 15;
+    const int j = MAP == ELEM_FAST ? tid & 15 : tid >> 4;
+    const int64_t line = line0 + c;
+    if (line < a.lines) {
+      const cf *src = in + bb * a.in_b + line * a.in_l;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        cf v = src[(int64_t)(j + 16 * m) * a.in_e];
+        if (SW & 1) v = cswap(v);
+        tile[tidx(c, j + 16 * m)] = v;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) tile[tidx(c, j + 16 * m)] = make_float2(0.f, 0.f);
+    }
+  }
+  __syncthreads();
+
+  const int part = g4 >> 1, kb = 8 * (g4 & 1);
+  cf *scr = scratch[wave];
+  for (int u = 0; u < C / 4; ++u) {
+    const int c = wave * (C / 4) + u;
+    // stage 1: vector n2 = col, element n1 = kb + t: x[n2 + 16 n1]
+    float xv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const cf v = tile[tidx(c, col + 16 * (kb + t))];
+      xv[t] = part ? v.y : v.x;
+    }
+    f32x4 dre, dim;
+    dft16_stage<PREC>(are, aim, xv, dre, dim);
+    // D: column n2 = col, rows k1 = 4 g4 + t -> twiddle, to scratch[k1][n2]
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const cf y = cmul(make_float2(dre[t], dim[t]), tw[t]);
+      scr[(4 * g4 + t) * 17 + col] = y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // stage 2: vector k1 = col, element n2 = kb + t
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const cf v = scr[col * 17 + kb + t];
+      xv[t] = part ? v.y : v.x;
+    }
+    dft16_stage<PREC>(are, aim, xv, dre, dim);
+    // D: column k1 = col, rows k2 = 4 g4 + t -> X[k1 + 16 k2] back into the line
+    const int64_t line = line0 + c;
+    cf y4[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) y4[t] = make_float2(dre[t], dim[t]);
+    if constexpr (TW4) {
+      // w_N^{line k}, k = col + 16 (4 g4 + t): A = w^{line (col + 64 g4)}, S = w^{16 line}
+      const uint32_t e0 = (uint32_t)line * (uint32_t)(col + 64 * g4);
+      const uint32_t e1 = (uint32_t)line * 16u;
+      const uint32_t m = (1u << a.tw4_shift) - 1u;
+      const cf A = cmul(a.tw4_hi[e0 >> a.tw4_shift], a.tw4_lo[e0 & m]);
+      const cf S = cmul(a.tw4_hi[e1 >> a.tw4_shift], a.tw4_lo[e1 & m]);
+      const cf S2 = cmul(S, S);
+      y4[0] = cmul(y4[0], A);
+      y4[1] = cmul(y4[1], cmul(A, S));
+      y4[2] = cmul(y4[2], cmul(A, S2));
+      y4[3] = cmul(y4[3], cmul(A, cmul(S2, S)));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      cf y = y4[t];
+      if (SW & 2) y = cswap(cscale(y, a.scale));
+      tile[tidx(c, col + 16 * (4 * g4 + t))] = y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+
+  // ---- store the tile coalesced in the output layout ----
+  {
+    const int c = OMAP == ELEM_FAST ? tid >> 4 : tid & 15;
+    const int j = OMAP == ELEM_FAST ? tid & 15 : tid >> 4;
+    const int64_t line = line0 + c;
+    if (line < a.lines) {
+      cf *dst = out + bb * a.out_b + line * a.out_l;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) dst[(int64_t)(j + 16 * m) * a.out_e] = tile[tidx(c, j + 16 * m)];
+    }
+  }
+}
+
+int mfma_lds_bytes() { return (int)sizeof(cf) * (kMfmaLines * kPitch + 4 * 16 * 17); }
+
+const void *mfma_kernel(int prec, int map, int omap, bool tw4, int sw) {
+#define MK2(P)                                                                                 \
+  if (prec == P) {                                                                             \
+    if (map == LINE_FAST && omap == LINE_FAST && tw4 && sw == 0)                               \
+      return (const void *)&k_mfma256<P, LINE_FAST, LINE_FAST, true, 0>;                       \
+    if (map == LINE_FAST && omap == LINE_FAST && tw4 && sw == 1)                               \
+      return (const void *)&k_mfma256<P, LINE_FAST, LINE_FAST, true, 1>;                       \
+    if (map == ELEM_FAST && omap == LINE_FAST && !tw4 && sw == 0)                              \
+      return (const void *)&k_mfma256<P, ELEM_FAST, LINE_FAST, false, 0>;                      \
+    if (map == ELEM_FAST && omap == LINE_FAST && !tw4 && sw == 2)                              \
+      return (const void *)&k_mfma256<P, ELEM_FAST, LINE_FAST, false, 2>;                      \
+    if (map == ELEM_FAST && omap == ELEM_FAST && !tw4 && sw == 0)                              \
+      return (const void *)&k_mfma256<P, ELEM_FAST, ELEM_FAST, false, 0>;                      \
+    if (map == ELEM_FAST && omap == ELEM_FAST && !tw4 && sw == 3)                              \
+      return (const void *)&k_mfma256<P, ELEM_FAST, ELEM_FAST, false, 3>;                      \
+  }
+  MK2(MP_FP16)
+  MK2(MP_BF16)
+  MK2(MP_FP16_SPLIT)
+  MK2(MP_BF16_SPLIT)
+  MK2(MP_BF16_SPLIT3)
+#undef MK2
+  return nullptr;
+}
+
+}  // namespace dpfft

@@ -37,9 +37,10 @@ struct MixedArgs {
   uint32_t flags;
 };
 
-// Host: radix sequence for a 7-smooth L (16s first, then 8/4/2, then 7, 5, 3).
-// Returns false if L has a prime factor above 7 or needs too many passes.
-bool mixed_radices(int64_t L, MixedPlan *mp);
+// Host: radix sequence for a 7-smooth L.  order 0: 16s, then 8/4/2, then 7,
+// 5, 3; order 1: 7, 5, 3 first, then the powers of two.  Returns false if L
+// has a prime factor above 7 or needs too many passes.
+bool mixed_radices(int64_t L, MixedPlan *mp, int order = 0);
 
 // Host: the kernel instance for (map, omap, tw4, swap mode); nullptr if none.
 const void *mixed_kernel(int map, int omap, bool tw4, int sw);

@@ -1,0 +1,173 @@
+// Device building blocks of the runtime-radix transforms, shared by the
+// batched kernels and the ragged persistent kernel.
+#pragma once
+#include "fft_common.h"
+#include "kernels.h"
+#include "mixed.h"
+
+namespace dpfft {
+
+namespace {
+
+__device__ __forceinline__ int midx_elem(int pitch, int c, int pos) {
+  return c * pitch + pos + (pos >> 4);
+}
+__device__ __forceinline__ int midx_line(int C, int c, int pos) {
+  const int u = pos * C + c;
+  return u + (u >> 4);
+}
+
+__device__ __forceinline__ cf tw2_lookup(const cf *__restrict__ t, int shift, uint32_t e) {
+  const cf lo = t[e & ((1u << shift) - 1u)];
+  const cf hi = t[(1u << shift) + (e >> shift)];
+  return cmul(hi, lo);
+}
+
+__device__ __forceinline__ cf tw4_lookup_m(const MixedArgs &a, uint32_t e) {
+  const uint32_t lo = e & ((1u << a.tw4_shift) - 1u);
+  const uint32_t hi = e >> a.tw4_shift;
+  return cmul(a.tw4_hi[hi], a.tw4_lo[lo]);
+}
+
+}  // namespace
+
+// Per-thread and per-line context of a pass, as plain scalars: the pass is a
+// separate (non-inlined) function per radix so that each gets its own
+// register allocation, and scalars travel in registers rather than through
+// the stack.
+struct PassArgs {
+  int L, T, C, pitch, NS, tw2_shift, tw4_shift, c, j;
+  bool valid, first, last;
+  int64_t in_e, out_e, line;
+  float scale;
+};
+
+template <int MAP, int OMAP, bool TW4, int SW, int R>
+__device__ __noinline__ void mixed_pass(const cf *__restrict__ src, cf *__restrict__ dst,
+                                        cf *lds, const cf *__restrict__ tw2,
+                                        const cf *__restrict__ tw4_lo,
+                                        const cf *__restrict__ tw4_hi, int L, int T, int C,
+                                        int pitch, int NS, int tw2_shift, int tw4_shift, int c,
+                                        int j, bool valid, bool first, bool last, int64_t in_e,
+                                        int64_t out_e, int64_t line, float scale) {
+  const int M = L / R;
+  constexpr int QM = (16 + R - 1) / R;  // butterflies per thread (T >= L/16)
+  auto li = [&](int m, int pos) {
+    return m == ELEM_FAST ? midx_elem(pitch, c, pos) : midx_line(C, c, pos);
+  };
+  cf v[QM][R];
+  bool act[QM];
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    const int b = j + T * q;
+    act[q] = valid && b < M;
+    if (!act[q]) continue;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pos = b + r * M;
+      cf y;
+      if (first) {
+        y = src[(int64_t)pos * in_e];
+        if (SW & 1) y = cswap(y);
+      } else {
+        y = lds[li(MAP, pos)];
+      }
+      v[q][r] = y;
+    }
+    if (NS > 1) {
+      const int k = b % NS;
+      const uint32_t step = (uint32_t)(L / (NS * R));
+#pragma unroll
+      for (int r = 1; r < R; ++r)
+        v[q][r] = cmul(v[q][r], tw2_lookup(tw2, tw2_shift, (uint32_t)(k * r) * step));
+    }
+    Dft<R>::run(v[q]);
+  }
+  if (!first) __syncthreads();  // every read of this pass precedes the in-place writes
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    if (!act[q]) continue;
+    const int b = j + T * q;
+    const int k = b % NS;
+    const int base = (b - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pos = base + r * NS;
+      cf y = v[q][r];
+      if (last) {
+        if (TW4) {
+          const uint32_t e = (uint32_t)(line * pos);
+          y = cmul(y, cmul(tw4_hi[e >> tw4_shift], tw4_lo[e & ((1u << tw4_shift) - 1u)]));
+        }
+        if (SW & 2) y = cswap(cscale(y, scale));
+        if (OMAP == MAP) {
+          dst[(int64_t)pos * out_e] = y;
+          continue;
+        }
+        lds[li(OMAP, pos)] = y;
+      } else {
+        lds[li(MAP, pos)] = y;
+      }
+    }
+  }
+  if (!last || OMAP != MAP) __syncthreads();
+}
+
+// One tile (up to C lines of length L) through every pass.  Thread (c, j)
+// works on line c; src/dst are its line's base pointers.  With OMAP != MAP the
+// last pass leaves the tile in LDS and thread (c2, j2) stores line c2 through
+// dst2, coalesced in the output layout.
+struct TileLine {
+  const cf *src;
+  cf *dst;
+  int64_t in_e, out_e, line;
+  int c, j;
+  bool valid;
+  cf *dst2;      // staged store: output base of line c2
+  int c2, j2;
+  bool valid2;
+};
+
+struct LineShape {
+  int L, T, C, pitch, P, tw2_shift;
+  uint64_t codes;
+  const cf *tw2;
+  const cf *tw4_lo, *tw4_hi;
+  int tw4_shift;
+  float scale;
+};
+
+template <int MAP, int OMAP, bool TW4, int SW>
+__device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &t, cf *lds) {
+  if (sh.P == 0) {  // length 1: the transform is the identity (both swaps cancel)
+    if (t.valid && t.j == 0) t.dst[0] = t.src[0];
+    return;
+  }
+  int ns = 1;
+  for (int p = 0; p < sh.P; ++p) {
+    const bool first = p == 0, last = p == sh.P - 1;
+    const int R = (int)((sh.codes >> (5 * p)) & 31u);
+#define PASS(RR)                                                                                 \
+  mixed_pass<MAP, OMAP, TW4, SW, RR>(t.src, t.dst, lds, sh.tw2, sh.tw4_lo, sh.tw4_hi, sh.L, sh.T, \
+                                     sh.C, sh.pitch, ns, sh.tw2_shift, sh.tw4_shift, t.c, t.j,    \
+                                     t.valid, first, last, t.in_e, t.out_e, t.line, sh.scale)
+    switch (R) {
+      case 2: PASS(2); break;
+      case 3: PASS(3); break;
+      case 4: PASS(4); break;
+      case 5: PASS(5); break;
+      case 7: PASS(7); break;
+      case 8: PASS(8); break;
+      default: PASS(16); break;
+    }
+#undef PASS
+    ns *= R;
+  }
+  if (OMAP != MAP && t.valid2) {
+    for (int i = t.j2; i < sh.L; i += sh.T)
+      t.dst2[(int64_t)i * t.out_e] =
+          lds[OMAP == ELEM_FAST ? midx_elem(sh.pitch, t.c2, i) : midx_line(sh.C, t.c2, i)];
+  }
+}
+
+}  // namespace dpfft

@@ -12,6 +12,7 @@
 #include "../../include/dpfft.h"
 #include "kernels.h"
 #include "mixed.h"
+#include "mfma.h"
 
 namespace dpfft {
 
@@ -87,6 +88,25 @@ struct MixedStep : Step {
   int lds_bytes = 0;
   int src = BUF_IN, dst = BUF_OUT;
   size_t tw2_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
+  bool first = false, last = false;
+  float inv_scale = 1.0f;
+  std::string name;
+  int inverse_sw() const { return (first ? 1 : 0) | (last ? 2 : 0); }
+  void bind(const float2 *tables) override;
+  hipError_t launch(const ExecCtx &ctx) const override;
+  std::string describe() const override;
+  void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
+  bool valid() const override;
+};
+
+struct MfmaStep : Step {
+  MfmaArgs a{};
+  int prec = 0;
+  const void *fn_sw[4] = {};
+  dim3 grid;
+  int src = BUF_IN, dst = BUF_OUT;
+  size_t amat_off = 0, tw16_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
+  bool tw4 = false;
   bool first = false, last = false;
   float inv_scale = 1.0f;
   std::string name;

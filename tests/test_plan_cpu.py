@@ -1,0 +1,119 @@
+"""Host-side planning (no GPU): factorization and variant choice seen through
+fft_plan_dry, the override hook, and the tuning-cache file (valid entry used,
+corrupt file ignored, FFT_F_NO_AUTOTUNE honoured)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _dp():
+    import paper_1203_4938_amd as dp
+    return dp
+
+
+def _dry(**kw):
+    dp = _dp()
+    d, keep = dp.make_desc(**kw)
+    st, text = dp.fft_plan_dry(d)
+    assert st == dp.FFT_OK, text
+    return text
+
+
+@pytest.mark.parametrize("n,variant,launches", [
+    (1, "single-pass", 1), (4096, "single-pass", 1), (16384, "single-pass", 1),
+    (1 << 15, "four-step 128x256", 2), (1 << 18, "four-step 512x512", 2),
+    (1 << 22, "four-step 2048x2048", 2), (1 << 24, "four-step 4096x4096", 2),
+    (1000, "mixed single-pass", 1), (15625, "mixed single-pass", 1),
+    (78125, "mixed four-step 125x625", 2), (3 ** 15, "mixed four-step 2187x6561", 2),
+])
+def test_variant_by_length(n, variant, launches):
+    t = _dry(n=n, batch=3)
+    assert f"variant={variant} " in t, t
+    assert f"launches={launches}" in t
+
+
+def test_radix_plans_of_mixed_lengths():
+    assert "radices=8x5x5x5" in _dry(n=1000, batch=1)
+    assert "radices=16x7x3" in _dry(n=336, batch=1)
+    assert "radices=7x7x7x7" in _dry(n=2401, batch=1)
+    assert "mixed four-step 49x343" in _dry(n=16807, batch=1)
+
+
+def test_workspace_sizes():
+    dp = _dp()
+    for n, b, ws in ((4096, 64, 0), (1 << 18, 4, (1 << 18) * 4 * 8)):
+        t = _dry(n=n, batch=b)
+        assert f"workspace={ws}B" in t
+
+
+def test_mfma_forms_plan():
+    t = _dry(n=65536, batch=4096, precision="bf16_split3")
+    assert "mfma four-step 256x256" in t and "bf16_split3" in t
+
+
+def test_ragged_plan_counts():
+    import synth
+    sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
+    t = _dry(ragged_sizes=sizes.tolist(), flags=4)
+    assert "10000 signals" in t and "HIP graph" in t and "persistent queue" in t
+    t2 = _dry(ragged_sizes=sizes.tolist(), flags=8)
+    assert "one launch per length" in t2
+
+
+def _run(code, env_extra):
+    env = dict(os.environ)
+    env.update(env_extra)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       env=env, timeout=120)
+    assert r.returncode == 0, r.stderr
+    return r.stdout
+
+
+CODE = """
+import paper_1203_4938_amd as dp
+d, k = dp.make_desc(4096, 64, flags={flags})
+print(dp.fft_plan_dry(d)[1])
+"""
+
+
+def test_override_env_changes_the_kernel():
+    out = _run(CODE.format(flags=0), {"DPFFT_FORCE_PLAN": "c0=2"})
+    assert "C=2" in out and 'override="c0=2"' in out
+
+
+def test_tune_cache_file_is_used(tmp_path):
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"dpfft_tune_cache": 1,
+                                "entries": {"gfx950|r1|n=4096|b=2^6|fp32": "c0=2 p0=0"}}))
+    out = _run(CODE.format(flags=0), {"DPFFT_TUNE_CACHE": str(path)})
+    assert "C=2" in out
+    # FFT_F_NO_AUTOTUNE ignores the cache
+    out = _run(CODE.format(flags=2), {"DPFFT_TUNE_CACHE": str(path)})
+    assert "C=1" in out and "override" not in out
+
+
+@pytest.mark.parametrize("content", ["not json at all", '{"dpfft_tune_cache": 1, "entries": {"k": ',
+                                     "", '{"other": 2}'])
+def test_corrupt_tune_cache_falls_back_to_heuristic(tmp_path, content):
+    path = tmp_path / "tune.json"
+    path.write_text(content)
+    out = _run(CODE.format(flags=0), {"DPFFT_TUNE_CACHE": str(path)})
+    assert "C=1" in out and "override" not in out
+
+
+def test_autotune_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("checks the no-device path")
+    dp = _dp()
+    d, k = dp.make_desc(4096, 64)
+    st, msg = dp.fft_autotune(d)
+    assert st in (dp.FFT_E_DEVICE, dp.FFT_E_INTERNAL)
+    d, k = dp.make_desc(65536, 8, precision="fp16")
+    st, msg = dp.fft_autotune(d)
+    assert st == dp.FFT_OK and "nothing to tune" in msg
