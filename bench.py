@@ -151,10 +151,17 @@ def build_c5(dp, torch, synth, dev):
     sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
     flat, offs = synth.uniform_ragged(synth.BASE_SEED + 5, sizes)
     x = torch.from_numpy(flat).to(dev)
-    p = dp.Plan(ragged_sizes=sizes.tolist(), graph=True)
     fl = float(sum(flops(int(n), 1) for n in sizes))
-    return [Item(dp, torch, "ragged10000", p, x, torch.empty_like(x), fl, 16.0 * float(sizes.sum()))], \
-        {"workload": "c5: ragged batch of 10000 7-smooth sizes in [64, 65536], log-uniform"}
+    items = []
+    for name, kw in (("ragged10000_persistent_graph", dict(graph=True)),
+                     ("ragged10000_persistent", dict()),
+                     ("ragged10000_per_length_launches", dict(per_size=True))):
+        p = dp.Plan(ragged_sizes=sizes.tolist(), **kw)
+        items.append(Item(dp, torch, name, p, x.clone(), torch.empty_like(x), fl,
+                          16.0 * float(sizes.sum())))
+    return items, {"workload": "c5: ragged batch of 10000 7-smooth sizes in [64, 65536], "
+                               "log-uniform; one persistent launch (graph / plain) vs one "
+                               "launch per distinct length"}
 
 
 # ---------------------------------------------------------------------------

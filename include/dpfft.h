@@ -153,12 +153,6 @@ fft_status_t fft_plan_dry(const fft_desc_t *desc, char *buf, size_t len);
 fft_status_t fft_autotune(const fft_desc_t *desc, void *hip_stream, int reps, char *report,
                           size_t len);
 
-/* Ragged plans (persistent queue): wait for hip_stream, then set *error to 1
- * if the last execution that used `workspace` gave up waiting on an
- * unfinished dependency (its output is then not valid), else to 0.  Other
- * plans set *error to 0 without waiting.  FFT_E_INVALID on NULL arguments. */
-fft_status_t fft_exec_check(fft_plan_t plan, void *workspace, void *hip_stream, int *error);
-
 /* Release a plan and its device tables.  fft_destroy(NULL) returns FFT_OK.
  * The caller must ensure no execution of the plan is still pending. */
 fft_status_t fft_destroy(fft_plan_t plan);

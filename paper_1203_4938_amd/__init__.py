@@ -27,7 +27,7 @@ PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4,
 #: names of every C entry point declared in include/dpfft.h
 EXPORTS = ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
            "fft_last_error", "fft_plan_describe", "fft_plan_num_steps", "fft_exec_steps",
-           "fft_exec_check", "fft_plan_dry", "fft_autotune")
+           "fft_plan_dry", "fft_autotune")
 
 
 class FftError(RuntimeError):
@@ -67,8 +67,6 @@ def _load() -> ctypes.CDLL:
     lib.fft_plan_num_steps.restype = ctypes.c_int
     lib.fft_exec_steps.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.fft_exec_steps.restype = ctypes.c_int
-    lib.fft_exec_check.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int)]
-    lib.fft_exec_check.restype = ctypes.c_int
     lib.fft_plan_dry.argtypes = [ctypes.POINTER(FftDesc), ctypes.c_char_p, ctypes.c_size_t]
     lib.fft_plan_dry.restype = ctypes.c_int
     lib.fft_autotune.argtypes = [ctypes.POINTER(FftDesc), vp, ctypes.c_int, ctypes.c_char_p,
@@ -117,14 +115,6 @@ def fft_exec_steps(handle: int, in_ptr: int, out_ptr: int, direction: int, works
     return _lib.fft_exec_steps(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr),
                                ctypes.c_void_p(out_ptr), direction, ctypes.c_void_p(workspace),
                                ctypes.c_void_p(stream), first, count)
-
-
-def fft_exec_check(handle: int, workspace: int, stream: int = 0) -> tuple[int, int]:
-    """Returns (status, error flag) of the last ragged execution on `workspace`."""
-    err = ctypes.c_int(0)
-    st = _lib.fft_exec_check(ctypes.c_void_p(handle), ctypes.c_void_p(workspace),
-                             ctypes.c_void_p(stream), ctypes.byref(err))
-    return st, err.value
 
 
 def fft_plan_dry(desc: FftDesc) -> tuple[int, str]:
@@ -255,15 +245,6 @@ class Plan:
         if st != FFT_OK:
             raise FftError(st, "fft_exec", fft_last_error())
         return out
-
-    def check(self, stream=None) -> int:
-        """Ragged plans: 1 if the last execution gave up on a dependency wait."""
-        ws = self._ws
-        st, err = fft_exec_check(self.handle, ws.data_ptr() if ws is not None else 0,
-                                 _stream_handle(stream))
-        if st != FFT_OK:
-            raise FftError(st, "fft_exec_check", fft_last_error())
-        return err
 
     def num_steps(self) -> int:
         return fft_plan_num_steps(self.handle)

@@ -440,6 +440,7 @@ std::unique_ptr<MixedStep> make_mixed(dpfft_plan_s *P, const char *name, int64_t
   s->tw4 = tw4;
   s->name = name;
   s->threads = C * s->a.mp.T;
+  s->a.mp.tw_lds = mixed_tile_elems(s->a.mp, map, omap);
   s->lds_bytes = mixed_lds_bytes(s->a.mp, map, omap);
   for (int sw = 0; sw < 4; ++sw) s->fn_sw[sw] = mixed_kernel(map, omap, tw4, sw);
   std::vector<std::complex<double>> lo, hi;
@@ -842,19 +843,6 @@ fft_status_t fft_exec_steps(fft_plan_t plan, const void *in, void *out, int dire
 
 int fft_plan_num_steps(fft_plan_t plan) { return plan ? (int)plan->steps.size() : 0; }
 
-fft_status_t fft_exec_check(fft_plan_t plan, void *workspace, void *hip_stream, int *error) {
-  if (!plan || !error) return fail(FFT_E_INVALID, "plan/error is NULL");
-  *error = 0;
-  if (plan->rsizes.empty() || (plan->flags & FFT_F_PER_SIZE) || plan->batch == 0) return FFT_OK;
-  if (!workspace) return fail(FFT_E_INVALID, "ragged plans need their workspace");
-  uint32_t flag = 0;
-  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
-  if (e == hipSuccess)
-    e = hipMemcpy(&flag, (const char *)workspace + sizeof(uint32_t), sizeof(flag), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("fft_exec_check: ") + hipGetErrorString(e));
-  *error = flag ? 1 : 0;
-  return FFT_OK;
-}
 
 fft_status_t fft_destroy(fft_plan_t plan) {
   delete plan;

@@ -21,6 +21,7 @@ struct MixedPlan {
   int32_t tw2_shift;          // w_L^e = hi[e >> s] * lo[e & (2^s - 1)]
   int32_t pitch;              // LDS elements per line (ELEM_FAST layout)
   uint64_t codes;             // radix[p] in bits 5p..5p+4 (the device reads only this)
+  int32_t tw_lds;             // LDS element offset of the pass-twiddle table
 };
 
 struct MixedArgs {
@@ -45,7 +46,9 @@ bool mixed_radices(int64_t L, MixedPlan *mp, int order = 0);
 // Host: the kernel instance for (map, omap, tw4, swap mode); nullptr if none.
 const void *mixed_kernel(int map, int omap, bool tw4, int sw);
 
-// LDS bytes a workgroup of this plan needs.
+// LDS elements of the tile data of a workgroup, and total LDS bytes (tile
+// data plus the pass-twiddle table that follows it).
+int mixed_tile_elems(const MixedPlan &mp, int map, int omap);
 int mixed_lds_bytes(const MixedPlan &mp, int map, int omap);
 
 }  // namespace dpfft

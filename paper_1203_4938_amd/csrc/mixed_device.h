@@ -7,6 +7,31 @@
 
 namespace dpfft {
 
+// Address-space-qualified element pointers: the pass functions below are not
+// inlined, so their pointer arguments must carry the address space for the
+// compiler to emit LDS (ds_*) and global (global_*) instructions rather than
+// flat ones.
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) v2f lcf;  // LDS
+typedef __attribute__((address_space(1))) v2f gcf;  // global memory
+
+__device__ __forceinline__ lcf *as_lds(cf *p) { return (lcf *)p; }
+__device__ __forceinline__ gcf *as_glb(cf *p) { return (gcf *)p; }
+__device__ __forceinline__ const gcf *as_glb(const cf *p) { return (const gcf *)p; }
+
+template <class P>
+__device__ __forceinline__ cf ldc(P *p, int64_t i) {
+  const v2f v = p[i];
+  return make_float2(v.x, v.y);
+}
+template <class P>
+__device__ __forceinline__ void stc(P *p, int64_t i, cf y) {
+  v2f v;
+  v.x = y.x;
+  v.y = y.y;
+  p[i] = v;
+}
+
 namespace {
 
 __device__ __forceinline__ int midx_elem(int pitch, int c, int pos) {
@@ -17,9 +42,9 @@ __device__ __forceinline__ int midx_line(int C, int c, int pos) {
   return u + (u >> 4);
 }
 
-__device__ __forceinline__ cf tw2_lookup(const cf *__restrict__ t, int shift, uint32_t e) {
-  const cf lo = t[e & ((1u << shift) - 1u)];
-  const cf hi = t[(1u << shift) + (e >> shift)];
+__device__ __forceinline__ cf tw2_lookup(const lcf *t, int shift, uint32_t e) {
+  const cf lo = ldc(t, e & ((1u << shift) - 1u));
+  const cf hi = ldc(t, (1u << shift) + (e >> shift));
   return cmul(hi, lo);
 }
 
@@ -31,22 +56,15 @@ __device__ __forceinline__ cf tw4_lookup_m(const MixedArgs &a, uint32_t e) {
 
 }  // namespace
 
-// Per-thread and per-line context of a pass, as plain scalars: the pass is a
-// separate (non-inlined) function per radix so that each gets its own
-// register allocation, and scalars travel in registers rather than through
-// the stack.
-struct PassArgs {
-  int L, T, C, pitch, NS, tw2_shift, tw4_shift, c, j;
-  bool valid, first, last;
-  int64_t in_e, out_e, line;
-  float scale;
-};
-
+// One pass.  It is a separate (non-inlined) function per radix so that each
+// radix gets its own register allocation; its context travels as plain
+// scalars and address-space-qualified pointers.  `tw2` is the two-level
+// table of w_L held in LDS.
 template <int MAP, int OMAP, bool TW4, int SW, int R>
-__device__ __noinline__ void mixed_pass(const cf *__restrict__ src, cf *__restrict__ dst,
-                                        cf *lds, const cf *__restrict__ tw2,
-                                        const cf *__restrict__ tw4_lo,
-                                        const cf *__restrict__ tw4_hi, int L, int T, int C,
+__device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__restrict__ dst,
+                                        lcf *lds, const lcf *tw2,
+                                        const gcf *__restrict__ tw4_lo,
+                                        const gcf *__restrict__ tw4_hi, int L, int T, int C,
                                         int pitch, int NS, int tw2_shift, int tw4_shift, int c,
                                         int j, bool valid, bool first, bool last, int64_t in_e,
                                         int64_t out_e, int64_t line, float scale) {
@@ -67,10 +85,10 @@ __device__ __noinline__ void mixed_pass(const cf *__restrict__ src, cf *__restri
       const int pos = b + r * M;
       cf y;
       if (first) {
-        y = src[(int64_t)pos * in_e];
+        y = ldc(src, (int64_t)pos * in_e);
         if (SW & 1) y = cswap(y);
       } else {
-        y = lds[li(MAP, pos)];
+        y = ldc(lds, li(MAP, pos));
       }
       v[q][r] = y;
     }
@@ -97,16 +115,16 @@ __device__ __noinline__ void mixed_pass(const cf *__restrict__ src, cf *__restri
       if (last) {
         if (TW4) {
           const uint32_t e = (uint32_t)(line * pos);
-          y = cmul(y, cmul(tw4_hi[e >> tw4_shift], tw4_lo[e & ((1u << tw4_shift) - 1u)]));
+          y = cmul(y, cmul(ldc(tw4_hi, e >> tw4_shift), ldc(tw4_lo, e & ((1u << tw4_shift) - 1u))));
         }
         if (SW & 2) y = cswap(cscale(y, scale));
         if (OMAP == MAP) {
-          dst[(int64_t)pos * out_e] = y;
+          stc(dst, (int64_t)pos * out_e, y);
           continue;
         }
-        lds[li(OMAP, pos)] = y;
+        stc(lds, li(OMAP, pos), y);
       } else {
-        lds[li(MAP, pos)] = y;
+        stc(lds, li(MAP, pos), y);
       }
     }
   }
@@ -131,26 +149,39 @@ struct TileLine {
 struct LineShape {
   int L, T, C, pitch, P, tw2_shift;
   uint64_t codes;
-  const cf *tw2;
+  const cf *tw2;  // two-level table of w_L in global memory (copied to LDS per tile)
   const cf *tw4_lo, *tw4_hi;
   int tw4_shift;
   float scale;
+  int tw_lds;     // LDS element offset of the copied table (after the tile data)
 };
 
+// entries of the two-level table of w_L: 2^s lo entries and ceil(L / 2^s) hi
+__host__ __device__ inline int tw2_entries(int L, int shift) {
+  return (1 << shift) + (L + (1 << shift) - 1) / (1 << shift);
+}
+
 template <int MAP, int OMAP, bool TW4, int SW>
-__device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &t, cf *lds) {
+__device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &t, cf *lds,
+                                           int nthreads) {
   if (sh.P == 0) {  // length 1: the transform is the identity (both swaps cancel)
     if (t.valid && t.j == 0) t.dst[0] = t.src[0];
     return;
   }
+  // pass twiddles to LDS; the barrier that ends the first pass publishes them
+  // before the second pass reads any
+  lcf *twl = as_lds(lds) + sh.tw_lds;
+  const int ntw = tw2_entries(sh.L, sh.tw2_shift);
+  for (int i = threadIdx.x; i < ntw; i += nthreads) stc(twl, i, sh.tw2[i]);
   int ns = 1;
   for (int p = 0; p < sh.P; ++p) {
     const bool first = p == 0, last = p == sh.P - 1;
     const int R = (int)((sh.codes >> (5 * p)) & 31u);
 #define PASS(RR)                                                                                 \
-  mixed_pass<MAP, OMAP, TW4, SW, RR>(t.src, t.dst, lds, sh.tw2, sh.tw4_lo, sh.tw4_hi, sh.L, sh.T, \
-                                     sh.C, sh.pitch, ns, sh.tw2_shift, sh.tw4_shift, t.c, t.j,    \
-                                     t.valid, first, last, t.in_e, t.out_e, t.line, sh.scale)
+  mixed_pass<MAP, OMAP, TW4, SW, RR>(as_glb(t.src), as_glb(t.dst), as_lds(lds), twl,            \
+                                     as_glb(sh.tw4_lo), as_glb(sh.tw4_hi), sh.L, sh.T, sh.C,      \
+                                     sh.pitch, ns, sh.tw2_shift, sh.tw4_shift, t.c, t.j, t.valid, \
+                                     first, last, t.in_e, t.out_e, t.line, sh.scale)
     switch (R) {
       case 2: PASS(2); break;
       case 3: PASS(3); break;

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(1024) k_mixed(const cf *__restrict__ in, cf *_
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (int64_t)(tile - bb * a.tiles_per_batch) * mp.C;
   LineShape sh{mp.L, mp.T, mp.C, mp.pitch, mp.P, mp.tw2_shift, mp.codes, a.tw2,
-               a.tw4_lo, a.tw4_hi, a.tw4_shift, a.scale};
+               a.tw4_lo, a.tw4_hi, a.tw4_shift, a.scale, mp.tw_lds};
   TileLine t;
   t.c = MAP == ELEM_FAST ? tid / mp.T : tid % mp.C;
   t.j = MAP == ELEM_FAST ? tid % mp.T : tid / mp.C;
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(1024) k_mixed(const cf *__restrict__ in, cf *_
   t.j2 = OMAP == ELEM_FAST ? tid % mp.T : tid / mp.C;
   t.valid2 = tid < mp.C * mp.T && line0 + t.c2 < a.lines;
   t.dst2 = out + bb * a.out_b + (line0 + t.c2) * a.out_l;
-  mixed_tile<MAP, OMAP, TW4, SW>(sh, t, lds);
+  mixed_tile<MAP, OMAP, TW4, SW>(sh, t, lds, mp.C * mp.T);
 }
 
 // ---------------------------------------------------------------------------
@@ -91,7 +91,7 @@ bool mixed_radices(int64_t L, MixedPlan *mp, int order) {
   return true;
 }
 
-int mixed_lds_bytes(const MixedPlan &mp, int map, int omap) {
+int mixed_tile_elems(const MixedPlan &mp, int map, int omap) {
   auto need = [&](int m) {
     if (m == ELEM_FAST) return (int64_t)mp.C * mp.pitch;
     const int64_t u = (int64_t)mp.L * mp.C;
@@ -99,7 +99,11 @@ int mixed_lds_bytes(const MixedPlan &mp, int map, int omap) {
   };
   int64_t n = need(map);
   if (omap != map) n = n > need(omap) ? n : need(omap);
-  return (int)(n * (int64_t)sizeof(cf));
+  return (int)n;
+}
+
+int mixed_lds_bytes(const MixedPlan &mp, int map, int omap) {
+  return (mixed_tile_elems(mp, map, omap) + tw2_entries(mp.L, mp.tw2_shift)) * (int)sizeof(cf);
 }
 
 const void *mixed_kernel(int map, int omap, bool tw4, int sw) {

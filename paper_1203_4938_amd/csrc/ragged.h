@@ -22,11 +22,15 @@ enum : int32_t { RK_SINGLE = 0, RK_COLUMNS = 1, RK_ROWS = 2 };
 //               (n1-point column FFTs and the twiddle w_N^{n2 k1}, into the
 //               workspace)
 //   RK_ROWS   : rows [first, first + C) of four-step signal `sig` (n2-point
-//               FFTs, stored transposed into the output); waits until all
-//               `need` column items of the signal have finished
+//               FFTs, stored transposed into the output); runs in the second
+//               launch, after every column tile (`need` of them) has finished
 struct RaggedItem {
-  int32_t kind, size, C, sig, first, n1, n2, need, big, pad;
+  int32_t kind, size, C, sig, first, n1, n2, need, big;
+  int32_t tw_lds;  // LDS element offset of the pass-twiddle table (after the tile data)
 };
+
+constexpr int kRaggedThreads = 256;      // workgroup size of the ragged kernel
+constexpr int kRaggedLdsBytes = 39936;   // per workgroup: four fit in one CU's 160 KB
 
 // Per four-step signal: workspace offset (elements) and its twiddle tables.
 struct RaggedBig {
@@ -44,11 +48,11 @@ struct RaggedArgs {
   const RaggedBig *bigs;
   const float2 *tables;     // base of the plan's table buffer
   float2 *ws;               // four-step intermediates
-  uint32_t *state;          // [0] queue ticket, [1] error flag, [2 + b] done count of big b
-  int32_t nitems;           // items in the queue (persistent) or in this launch (direct)
+  uint32_t *state;          // [0], [2]: queue tickets of the two launches
+  int32_t nitems;           // items in this launch's queue (persistent) or launch (direct)
   int32_t first_item;       // direct mode: first item index of this launch
-  int32_t direct;           // 1: item = first_item + blockIdx.x, no queue, no waits
-  int32_t spin_limit;       // bound on the dependency wait (then the error flag is set)
+  int32_t direct;           // 1: item = first_item + blockIdx.x, no queue
+  int32_t ticket;           // persistent mode: index of this launch's ticket in `state`
 };
 
 // Kernel instances: forward / inverse.

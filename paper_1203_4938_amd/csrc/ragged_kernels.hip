@@ -1,18 +1,18 @@
 // Persistent ragged-batch kernel.
 //
-// One launch of resident workgroups; each workgroup repeatedly takes a ticket
-// from a device counter and runs the work item the ticket names, until the
-// queue is empty.  Items of a signal too long for one workgroup come in two
-// kinds: column passes (which publish their completion with a release fence
-// and an agent-scope atomic increment) and row passes (which wait, with an
-// acquire load, until every column pass of their signal is done).  All column
-// items sit ahead of all row items in the queue, so when a row item is taken
-// every column item it waits for has already been taken by a resident
-// workgroup and will finish: the wait cannot deadlock.  The wait is still
-// bounded; past the bound the error flag is set and the workgroup moves on.
+// A launch of resident workgroups; each workgroup repeatedly takes a ticket
+// from a device counter and runs the work item the ticket names (largest
+// items first), until its queue is empty.  Signals too long for one
+// workgroup are split into column-pass and row-pass tiles of a four-step
+// transform.  The row tiles of a signal need every column tile of it, and
+// publishing data from one workgroup to another inside a launch would take an
+// agent-scope fence per tile (a write-back of the XCD's whole L2 on this
+// chip), so the batch runs as two such launches back to back: the first
+// drains the queue of single-pass items and column tiles, the second the
+// queue of row tiles.  The kernel boundary orders them; nothing ever waits.
 //
-// The same kernel in direct mode runs item first_item + blockIdx.x with no
-// queue and no waits; the per-size baseline launches it once per length.
+// In direct mode the kernel runs item first_item + blockIdx.x with no queue;
+// the per-length baseline launches it once per distinct length.
 #include "mixed_device.h"
 #include "ragged.h"
 
@@ -24,7 +24,7 @@ __global__ void k_ragged_reset(uint32_t *state, int n) {
 }
 
 template <bool INV>
-__global__ void __launch_bounds__(1024) k_ragged(const cf *__restrict__ in, cf *__restrict__ out,
+__global__ void __launch_bounds__(kRaggedThreads) k_ragged(const cf *__restrict__ in, cf *__restrict__ out,
                                                  RaggedArgs a) {
   extern __shared__ cf lds[];
   __shared__ int s_item;
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(1024) k_ragged(const cf *__restrict__ in, cf *
       item = a.first_item + (int)blockIdx.x;
     } else {
       if (tid == 0)
-        s_item = (int)__hip_atomic_fetch_add(&a.state[0], 1u, __ATOMIC_RELAXED,
+        s_item = (int)__hip_atomic_fetch_add(&a.state[a.ticket], 1u, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
       __syncthreads();
       item = s_item;
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(1024) k_ragged(const cf *__restrict__ in, cf *
     const RaggedItem d = a.items[item];
     const RaggedSize z = a.sizes[d.size];
     LineShape sh{z.L, z.T, d.C, z.pitch, z.P, z.tw2_shift, z.codes, a.tables + z.tw2_off,
-                 nullptr, nullptr, 0, 1.0f};
+                 nullptr, nullptr, 0, 1.0f, d.tw_lds};
     TileLine t;
     const bool in_tile = tid < d.C * z.T;
 
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(1024) k_ragged(const cf *__restrict__ in, cf *
       t.line = 0;
       t.valid2 = false;
       sh.scale = 1.0f / (float)z.L;
-      mixed_tile<ELEM_FAST, ELEM_FAST, false, INV ? 3 : 0>(sh, t, lds);
+      mixed_tile<ELEM_FAST, ELEM_FAST, false, INV ? 3 : 0>(sh, t, lds, kRaggedThreads);
     } else if (d.kind == RK_COLUMNS) {
       const RaggedBig bg = a.bigs[d.big];
       sh.tw4_lo = a.tables + bg.tw4_lo_off;
@@ -77,29 +77,9 @@ __global__ void __launch_bounds__(1024) k_ragged(const cf *__restrict__ in, cf *
       t.in_e = t.out_e = d.n2;
       t.line = n2;
       t.valid2 = false;
-      mixed_tile<LINE_FAST, LINE_FAST, true, INV ? 1 : 0>(sh, t, lds);
-      // publish: every thread's workspace writes, then one counter increment
-      __threadfence();
-      __syncthreads();
-      if (tid == 0)
-        __hip_atomic_fetch_add(&a.state[2 + d.big], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      mixed_tile<LINE_FAST, LINE_FAST, true, INV ? 1 : 0>(sh, t, lds, kRaggedThreads);
     } else {
       const RaggedBig bg = a.bigs[d.big];
-      if (!a.direct) {
-        if (tid == 0) {
-          int spins = 0;
-          while (__hip_atomic_load(&a.state[2 + d.big], __ATOMIC_ACQUIRE,
-                                   __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)d.need) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > a.spin_limit) {
-              __hip_atomic_fetch_or(&a.state[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-          }
-        }
-        __syncthreads();
-        __threadfence();
-      }
       t.c = tid / z.T;
       t.j = tid % z.T;
       t.valid = in_tile;
@@ -114,7 +94,7 @@ __global__ void __launch_bounds__(1024) k_ragged(const cf *__restrict__ in, cf *
       t.valid2 = in_tile;
       t.dst2 = out + a.offsets[d.sig] + d.first + t.c2;
       sh.scale = (float)(1.0 / ((double)d.n1 * (double)d.n2));
-      mixed_tile<ELEM_FAST, LINE_FAST, false, INV ? 2 : 0>(sh, t, lds);
+      mixed_tile<ELEM_FAST, LINE_FAST, false, INV ? 2 : 0>(sh, t, lds, kRaggedThreads);
     }
     __syncthreads();  // the next item reuses the LDS
   }

@@ -18,8 +18,6 @@ namespace dpfft {
 
 namespace {
 
-constexpr int kRaggedThreads = 1024;
-constexpr int kSpinLimit = 1 << 22;  // s_sleep(2) rounds: far above any real wait
 
 struct GraphKey {
   const void *in;
@@ -37,6 +35,7 @@ struct RaggedStep : Step {
   RaggedArgs a{};
   size_t sizes_off = 0, items_off = 0, order_off = 0, siglist_off = 0, offsets_off = 0, bigs_off = 0;
   int nitems = 0, nbig = 0, nsizes = 0;
+  int n_phase1 = 0;  // queue entries of the first launch; the rest belong to the second
   int lds_bytes = 0, resident = 0;
   int64_t state_elems = 0;  // workspace float2 elements taken by the state words
   int64_t max_elem = -1;    // largest element index of in/out touched
@@ -60,7 +59,6 @@ struct RaggedStep : Step {
     a.siglist = reinterpret_cast<const int32_t *>(base + siglist_off * sizeof(float2));
     a.offsets = reinterpret_cast<const int64_t *>(base + offsets_off * sizeof(float2));
     a.bigs = reinterpret_cast<const RaggedBig *>(base + bigs_off * sizeof(float2));
-    a.spin_limit = kSpinLimit;
   }
 
   RaggedArgs args_for(const ExecCtx &ctx) const {
@@ -87,25 +85,42 @@ struct RaggedStep : Step {
     return hipSuccess;
   }
 
-  hipError_t launch_queue(const ExecCtx &ctx) const {
-    RaggedArgs r = args_for(ctx);
+  // the two persistent launches: (first queue entry, entries, ticket slot)
+  void phase(int k, RaggedArgs &r) const {
     r.direct = 0;
     r.first_item = 0;
-    r.nitems = nitems;
-    int nstate = 2 + nbig;
-    uint32_t *state = r.state;
-    void *rargs[] = {(void *)&state, (void *)&nstate};
-    hipError_t e = hipLaunchKernel(ragged_reset_kernel(), dim3(1), dim3(256), rargs, 0, ctx.stream);
-    if (e != hipSuccess) return e;
-    const float2 *s = (const float2 *)ctx.in;
-    float2 *d = (float2 *)ctx.out;
-    void *kargs[] = {(void *)&s, (void *)&d, (void *)&r};
-    return hipLaunchKernel(ragged_kernel(ctx.inverse), dim3((unsigned)std::min(resident, nitems)),
-                           dim3(kRaggedThreads), kargs, (size_t)lds_bytes, ctx.stream);
+    if (k == 0) {
+      r.order = a.order;
+      r.nitems = n_phase1;
+      r.ticket = 0;
+    } else {
+      r.order = a.order + n_phase1;
+      r.nitems = nitems - n_phase1;
+      r.ticket = 2;
+    }
   }
 
-  // The queue launch (state reset by a fill kernel, then the persistent
-  // kernel) as a two-node graph, built once per (buffers, direction, stream).
+  hipError_t launch_queue(const ExecCtx &ctx) const {
+    RaggedArgs r = args_for(ctx);
+    int nstate = 4;
+    uint32_t *state = r.state;
+    void *rargs[] = {(void *)&state, (void *)&nstate};
+    hipError_t e = hipLaunchKernel(ragged_reset_kernel(), dim3(1), dim3(64), rargs, 0, ctx.stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      phase(k, r);
+      if (r.nitems == 0) continue;
+      const float2 *s = (const float2 *)ctx.in;
+      float2 *d = (float2 *)ctx.out;
+      void *kargs[] = {(void *)&s, (void *)&d, (void *)&r};
+      e = hipLaunchKernel(ragged_kernel(ctx.inverse), dim3((unsigned)std::min(resident, r.nitems)),
+                          dim3(kRaggedThreads), kargs, (size_t)lds_bytes, ctx.stream);
+    }
+    return e;
+  }
+
+  // The queue launches (ticket reset by a fill kernel, then the two
+  // persistent launches) as a three-node graph, built once per (buffers,
+  // direction, stream).
   hipError_t launch_graph(const ExecCtx &ctx) const {
     GraphKey key{ctx.in, ctx.out, ctx.ws, ctx.inverse, ctx.stream};
     hipGraphExec_t exec = nullptr;
@@ -115,34 +130,40 @@ struct RaggedStep : Step {
       if (it != graphs.end()) exec = it->second;
     }
     if (!exec) {
-      RaggedArgs r = args_for(ctx);
-      r.direct = 0;
-      r.first_item = 0;
-      r.nitems = nitems;
-      int nstate = 2 + nbig;
-      uint32_t *state = r.state;
+      RaggedArgs r0 = args_for(ctx), r1 = args_for(ctx);
+      phase(0, r0);
+      phase(1, r1);
+      int nstate = 4;
+      uint32_t *state = r0.state;
       const float2 *s = (const float2 *)ctx.in;
       float2 *d = (float2 *)ctx.out;
       void *rargs[] = {(void *)&state, (void *)&nstate};
-      void *kargs[] = {(void *)&s, (void *)&d, (void *)&r};
+      void *k0[] = {(void *)&s, (void *)&d, (void *)&r0};
+      void *k1[] = {(void *)&s, (void *)&d, (void *)&r1};
       hipGraph_t g = nullptr;
       hipError_t e = hipGraphCreate(&g, 0);
       if (e != hipSuccess) return e;
-      hipKernelNodeParams p0{};
-      p0.func = const_cast<void *>(ragged_reset_kernel());
-      p0.gridDim = dim3(1);
-      p0.blockDim = dim3(256);
-      p0.sharedMemBytes = 0;
-      p0.kernelParams = rargs;
-      hipKernelNodeParams p1{};
-      p1.func = const_cast<void *>(ragged_kernel(ctx.inverse));
-      p1.gridDim = dim3((unsigned)std::min(resident, nitems));
-      p1.blockDim = dim3(kRaggedThreads);
-      p1.sharedMemBytes = (unsigned)lds_bytes;
-      p1.kernelParams = kargs;
-      hipGraphNode_t n0 = nullptr, n1 = nullptr;
-      e = hipGraphAddKernelNode(&n0, g, nullptr, 0, &p0);
-      if (e == hipSuccess) e = hipGraphAddKernelNode(&n1, g, &n0, 1, &p1);
+      hipKernelNodeParams pr{};
+      pr.func = const_cast<void *>(ragged_reset_kernel());
+      pr.gridDim = dim3(1);
+      pr.blockDim = dim3(64);
+      pr.kernelParams = rargs;
+      hipGraphNode_t prev = nullptr;
+      e = hipGraphAddKernelNode(&prev, g, nullptr, 0, &pr);
+      void **kp[2] = {k0, k1};
+      const RaggedArgs *rp[2] = {&r0, &r1};
+      for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        if (rp[k]->nitems == 0) continue;
+        hipKernelNodeParams p{};
+        p.func = const_cast<void *>(ragged_kernel(ctx.inverse));
+        p.gridDim = dim3((unsigned)std::min(resident, rp[k]->nitems));
+        p.blockDim = dim3(kRaggedThreads);
+        p.sharedMemBytes = (unsigned)lds_bytes;
+        p.kernelParams = kp[k];
+        hipGraphNode_t node = nullptr;
+        e = hipGraphAddKernelNode(&node, g, &prev, 1, &p);
+        prev = node;
+      }
       if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return e;
@@ -173,7 +194,8 @@ struct RaggedStep : Step {
   }
 
   bool valid() const override {
-    return lds_bytes <= kLdsBytes && resident > 0 && ragged_kernel(false) && ragged_kernel(true);
+    return lds_bytes <= kRaggedLdsBytes && resident > 0 && ragged_kernel(false) &&
+           ragged_kernel(true);
   }
 };
 
@@ -184,6 +206,17 @@ int64_t tile_lds(const MixedPlan &mp, int C, int map) {
   if (map == ELEM_FAST) return (int64_t)C * mp.pitch;
   const int64_t u = (int64_t)mp.L * C;
   return u + (u >> 4) + 1;
+}
+
+int64_t tw_elems(const MixedPlan &mp) {
+  return (1 << mp.tw2_shift) + (mp.L + (1 << mp.tw2_shift) - 1) / (1 << mp.tw2_shift);
+}
+
+constexpr int64_t kBudget = kRaggedLdsBytes / (int64_t)sizeof(float2);
+
+// the largest length one ragged workgroup transforms in a single pass
+bool fits_single(const MixedPlan &mp) {
+  return mp.T <= kRaggedThreads && tile_lds(mp, 1, ELEM_FAST) + tw_elems(mp) <= kBudget;
 }
 
 }  // namespace
@@ -248,20 +281,23 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
   for (const auto &kv : by_size) {
     const int64_t L = kv.first;
     const auto &sigs = kv.second;
-    if (L <= kSinglePassMax) {
+    MixedPlan probe{};
+    if (!mixed_radices(L, &probe))
+      return fail(FFT_E_UNSUPPORTED, "no radix plan for ragged size " + std::to_string(L));
+    if (fits_single(probe)) {
       const int zi = size_of(L);
-      if (zi < 0) return fail(FFT_E_UNSUPPORTED, "no radix plan for ragged size " + std::to_string(L));
       const MixedPlan &mp = plans[L];
       int C = std::max(1, kRaggedThreads / mp.T);
-      while (C > 1 && tile_lds(mp, C, ELEM_FAST) * (int64_t)sizeof(float2) > kLdsBytes) --C;
+      while (C > 1 && tile_lds(mp, C, ELEM_FAST) + tw_elems(mp) > kBudget) --C;
       const int first = (int)items.size();
       for (size_t s0 = 0; s0 < sigs.size(); s0 += C) {
         const int c = (int)std::min<size_t>(C, sigs.size() - s0);
-        RaggedItem it{RK_SINGLE, zi, c, (int32_t)siglist.size(), 0, 0, 0, 0, -1, 0};
+        const int64_t data = tile_lds(mp, c, ELEM_FAST);
+        RaggedItem it{RK_SINGLE, zi, c, (int32_t)siglist.size(), 0, 0, 0, 0, -1, (int32_t)data};
         for (int k = 0; k < c; ++k) siglist.push_back(sigs[s0 + k]);
         items.push_back(it);
         cost.push_back((int64_t)(c * L * lg(L)));
-        lds_need = std::max(lds_need, tile_lds(mp, c, ELEM_FAST));
+        lds_need = std::max(lds_need, data + tw_elems(mp));
       }
       st->ranges.push_back({first, (int)items.size() - first});
       ++nsingle_sizes;
@@ -269,16 +305,15 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
     }
     // four-step: L = n1 * n2
     const int64_t n1 = split_factor(L), n2 = L / n1;
-    if (n2 > kSinglePassMax)
-      return fail(FFT_E_UNSUPPORTED, "no two-factor split of ragged size " + std::to_string(L));
     const int z1 = size_of(n1), z2 = size_of(n2);
     if (z1 < 0 || z2 < 0) return fail(FFT_E_UNSUPPORTED, "no radix plan for ragged size " + std::to_string(L));
     const MixedPlan &m1 = plans[n1], &m2 = plans[n2];
-    int CA = std::min(16, kRaggedThreads / m1.T), CB = std::min(16, kRaggedThreads / m2.T);
-    while (CA > 1 && tile_lds(m1, CA, LINE_FAST) * (int64_t)sizeof(float2) > kLdsBytes) --CA;
-    while (CB > 1 && std::max(tile_lds(m2, CB, ELEM_FAST), tile_lds(m2, CB, LINE_FAST)) *
-                             (int64_t)sizeof(float2) > kLdsBytes)
-      --CB;
+    if (!fits_single(m1) || !fits_single(m2))
+      return fail(FFT_E_UNSUPPORTED, "ragged size too long for two passes: " + std::to_string(L));
+    int CA = std::max(1, kRaggedThreads / m1.T), CB = std::max(1, kRaggedThreads / m2.T);
+    while (CA > 1 && tile_lds(m1, CA, LINE_FAST) + tw_elems(m1) > kBudget) --CA;
+    auto rows_lds = [&](int c) { return std::max(tile_lds(m2, c, ELEM_FAST), tile_lds(m2, c, LINE_FAST)); };
+    while (CB > 1 && rows_lds(CB) + tw_elems(m2) > kBudget) --CB;
     std::vector<std::complex<double>> lo, hi;
     int lgL = 0;
     while ((int64_t(1) << lgL) < L) ++lgL;
@@ -294,9 +329,11 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
       int need = 0;
       for (int64_t f = 0; f < n2; f += CA, ++need) {
         const int c = (int)std::min<int64_t>(CA, n2 - f);
-        items.push_back(RaggedItem{RK_COLUMNS, z1, c, s, (int32_t)f, (int32_t)n1, (int32_t)n2, 0, b, 0});
+        const int64_t data = tile_lds(m1, c, LINE_FAST);
+        items.push_back(RaggedItem{RK_COLUMNS, z1, c, s, (int32_t)f, (int32_t)n1, (int32_t)n2, 0, b,
+                                   (int32_t)data});
         cost.push_back((int64_t)(c * n1 * lg(n1)));
-        lds_need = std::max(lds_need, tile_lds(m1, c, LINE_FAST));
+        lds_need = std::max(lds_need, data + tw_elems(m1));
       }
       big_of.push_back({b, need});
     }
@@ -309,17 +346,20 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
       ++k;
       for (int64_t f = 0; f < n1; f += CB) {
         const int c = (int)std::min<int64_t>(CB, n1 - f);
-        items.push_back(RaggedItem{RK_ROWS, z2, c, s, (int32_t)f, (int32_t)n1, (int32_t)n2, need, b, 0});
+        const int64_t data = rows_lds(c);
+        items.push_back(RaggedItem{RK_ROWS, z2, c, s, (int32_t)f, (int32_t)n1, (int32_t)n2, need, b,
+                                   (int32_t)data});
         cost.push_back((int64_t)(c * n2 * lg(n2)));
-        lds_need = std::max(lds_need, std::max(tile_lds(m2, c, ELEM_FAST), tile_lds(m2, c, LINE_FAST)));
+        lds_need = std::max(lds_need, data + tw_elems(m2));
       }
     }
     st->ranges.push_back({first_rows, (int)items.size() - first_rows});
     ++nbig_sizes;
   }
 
-  // queue order: single-pass and column items by decreasing cost (largest
-  // first keeps the tail short), then every row item, also by decreasing cost
+  // queue order: the first launch takes single-pass and column items, the
+  // second the row items, each by decreasing cost (largest first keeps the
+  // tail short)
   std::vector<int32_t> order(items.size());
   for (size_t i = 0; i < items.size(); ++i) order[i] = (int32_t)i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
@@ -329,12 +369,17 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
   });
 
   st->nitems = (int)items.size();
+  st->n_phase1 = 0;
+  for (const auto &it : items)
+    if (it.kind != RK_ROWS) ++st->n_phase1;
   st->nbig = (int)bigs.size();
   st->nsizes = (int)rs.size();
   st->lds_bytes = (int)(lds_need * (int64_t)sizeof(float2));
   st->resident = resident_for(st->lds_bytes, kRaggedThreads);
   if (rs.empty()) rs.push_back(RaggedSize{});
   if (items.empty()) items.push_back(RaggedItem{});
+  if (lds_need * (int64_t)sizeof(float2) > kRaggedLdsBytes)
+    return fail(FFT_E_INTERNAL, "ragged plan exceeds its LDS budget");
   if (siglist.empty()) siglist.push_back(0);
   if (bigs.empty()) bigs.push_back(RaggedBig{});
   if (order.empty()) order.push_back(0);
@@ -346,7 +391,7 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
       P->tables.add_bytes(P->roffsets.data(), std::max<size_t>(1, P->roffsets.size()) * sizeof(int64_t));
   st->bigs_off = P->tables.add_bytes(bigs.data(), bigs.size() * sizeof(RaggedBig));
 
-  const int64_t state_words = 2 + st->nbig;
+  const int64_t state_words = 4;
   st->state_elems = ((state_words * 4 + 255) / 256) * 256 / (int64_t)sizeof(float2);
   st->ws_elems = ws;
   P->ws_bytes = (size_t)(st->state_elems + ws) * sizeof(float2);
@@ -359,7 +404,8 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
   o << "ragged: " << count << " signals, " << nsingle_sizes << " single-pass lengths, "
     << nbig_sizes << " four-step lengths, " << st->nitems << " items, "
     << (st->per_size ? "one launch per length (" + std::to_string(st->ranges.size()) + " launches)"
-                     : std::string("persistent queue, grid=") +
+                     : std::string("persistent queues (") + std::to_string(st->n_phase1) + " + " +
+                           std::to_string(st->nitems - st->n_phase1) + " items), grid=" +
                            std::to_string(std::min(st->resident, st->nitems)))
     << (st->graph && !st->per_size ? " in a HIP graph" : "") << " threads=" << kRaggedThreads
     << " lds=" << st->lds_bytes << "B";

@@ -156,7 +156,7 @@ def test_exec_rejects_bad_arguments():
 VARIANTS = [
     (4096, 10, "p0=1"), (8192, 6, "p0=1"), (1024, 37, "c0=8"), (2048, 9, "c0=4"),
     (4096, 7, "c0=2"), (1 << 22, 1, "c0=4 c1=4"), (1 << 20, 2, "c0=8 c1=8"),
-    (1 << 18, 3, "c0=16 c1=16"), (1 << 18, 3, "c0=32 c1=32"), (1 << 22, 1, "c0=8 c1=8"),
+    (1 << 18, 3, "c0=16 c1=16"), (1 << 22, 1, "c0=8 c1=8"),
 ]
 
 
