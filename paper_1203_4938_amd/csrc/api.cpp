@@ -120,8 +120,8 @@ hipError_t LineStep::launch(const ExecCtx &ctx) const {
     fn = k.fn_sw[inverse_sw()];
     if (last) args.scale = inv_scale;
   }
-  const float2 *s = buf_c(ctx, src, 0);
-  float2 *d = buf_m(ctx, dst, 0);
+  const float2 *s = buf_c(ctx, src, src_off);
+  float2 *d = buf_m(ctx, dst, dst_off);
   void *kargs[] = {(void *)&s, (void *)&d, (void *)&args};
   return hipLaunchKernel(fn, g, dim3(k.threads), kargs, 0, ctx.stream);
 }
@@ -129,8 +129,8 @@ hipError_t LineStep::launch(const ExecCtx &ctx) const {
 void LineStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const {
   const int64_t nb = (int64_t)grid.x / a.tiles_per_batch;  // batch items covered by the grid
   const int64_t last_line = std::min<int64_t>(a.lines, a.tiles_per_batch * k.lines) - 1;
-  max_in = (nb - 1) * a.in_b + last_line * a.in_l + (int64_t)(L - 1) * a.in_e;
-  max_out = (nb - 1) * a.out_b + last_line * a.out_l + (int64_t)(L - 1) * a.out_e;
+  max_in = src_off + (nb - 1) * a.in_b + last_line * a.in_l + (int64_t)(L - 1) * a.in_e;
+  max_out = dst_off + (nb - 1) * a.out_b + last_line * a.out_l + (int64_t)(L - 1) * a.out_e;
   src_id = src;
   dst_id = dst;
 }
@@ -315,6 +315,39 @@ std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, in
   return s;
 }
 
+// Two-pass plans over B transforms, `per` elements apart in the caller's
+// buffers: run the pair of launches chunk by chunk, `k` transforms at a time,
+// so the intermediate of a chunk (k transforms, reused by every chunk) can be
+// read back from the memory-side cache instead of HBM.  Pass a reads from the
+// input at chunk offset and writes the workspace (or the output, in place
+// passes); pass b finishes into the output at chunk offset.
+void push_chunked(dpfft_plan_s *P, std::unique_ptr<LineStep> a, std::unique_ptr<LineStep> b,
+                  int64_t B, int64_t k, int64_t per) {
+  if (k <= 0 || k >= B) {
+    P->steps.push_back(std::move(a));
+    P->steps.push_back(std::move(b));
+    return;
+  }
+  for (int64_t c0 = 0; c0 < B; c0 += k) {
+    const int64_t nb = std::min(k, B - c0);
+    auto ac = std::make_unique<LineStep>(*a);
+    auto bc = std::make_unique<LineStep>(*b);
+    ac->grid = dim3((unsigned)(nb * ac->a.tiles_per_batch));
+    ac->a.ntiles = ac->grid.x;
+    bc->grid = dim3((unsigned)(nb * bc->a.tiles_per_batch));
+    bc->a.ntiles = bc->grid.x;
+    ac->src_off = c0 * per;
+    if (ac->dst != BUF_WS) ac->dst_off = c0 * per;
+    if (bc->src != BUF_WS) bc->src_off = c0 * per;
+    bc->dst_off = c0 * per;
+    P->steps.push_back(std::move(ac));
+    P->steps.push_back(std::move(bc));
+  }
+}
+
+// transforms per chunk: the override, else the whole batch at once
+int64_t chunk_of(const Override &ov) { return ov.chunk > 0 ? ov.chunk : 0; }
+
 fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch, D = P->dist;
   const Override ov = read_override();
@@ -384,10 +417,11 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   b->inv_scale = (float)(1.0 / (double)N);
   b->src = BUF_WS;
   b->dst = BUF_OUT;
-  P->steps.push_back(std::move(a));
-  P->steps.push_back(std::move(b));
-  P->ws_bytes = (size_t)B * (size_t)N * sizeof(float2);
-  P->variant = "four-step " + std::to_string(N1) + "x" + std::to_string(N2);
+  const int64_t k = chunk_of(ov);
+  push_chunked(P, std::move(a), std::move(b), B, k, D);
+  P->ws_bytes = (size_t)(k > 0 && k < B ? k : B) * (size_t)N * sizeof(float2);
+  P->variant = "four-step " + std::to_string(N1) + "x" + std::to_string(N2) +
+               (k > 0 && k < B ? " in chunks of " + std::to_string(k) : "");
   return FFT_OK;
 }
 
@@ -422,9 +456,10 @@ fft_status_t plan_pow2_2d(dpfft_plan_s *P) {
   c->inv_scale = (float)(1.0 / ((double)NX * (double)NY));
   c->src = BUF_OUT;
   c->dst = BUF_OUT;
-  P->steps.push_back(std::move(r));
-  P->steps.push_back(std::move(c));
-  P->variant = "2d rows+columns";
+  const int64_t k = chunk_of(ov);
+  push_chunked(P, std::move(r), std::move(c), B, k, D);
+  P->variant = std::string("2d rows+columns") +
+               (k > 0 && k < B ? " in chunks of " + std::to_string(k) : "");
   return FFT_OK;
 }
 

@@ -2,7 +2,8 @@
 // remembers the fastest per (architecture, shape, batch bucket, precision).
 //
 // Candidates are expressed as overrides of the planner's choices (tile width
-// per launch, persistent variant, radix order of runtime-radix lengths); each
+// per launch, persistent variant, radix order of runtime-radix lengths, chunk
+// size of two-pass plans); each
 // is built by the normal plan builder, so every candidate passes the same
 // validation and bounds checks as a default plan.  Results live in an
 // in-process map, optionally persisted as JSON in the file named by
@@ -36,6 +37,8 @@ Override parse_override(const std::string &text) {
     int idx = -1, val = -1;
     if (sscanf(tok.c_str(), "o=%d", &val) == 1) {
       o.order = val;
+    } else if (sscanf(tok.c_str(), "k=%d", &val) == 1) {
+      o.chunk = val;
     } else if (sscanf(tok.c_str(), "%c%d=%d", &kind, &idx, &val) == 3 && idx >= 0 && idx < 8) {
       if (kind == 'c') o.c[idx] = val;
       if (kind == 'p') o.p[idx] = val;
@@ -169,10 +172,19 @@ std::vector<std::string> candidates(const fft_desc_t *d) {
     return "c" + std::to_string(step) + "=" + std::to_string(c) + " p" + std::to_string(step) + "=" +
            std::to_string(p);
   };
+  // two-pass plans: chunk sizes keeping one chunk's intermediate within 64,
+  // 128 or 256 MiB (the memory-side cache holds 256 MB)
+  auto chunks = [&](int64_t per_bytes) {
+    for (int64_t mib : {64, 128, 256}) {
+      const int64_t k = std::max<int64_t>(1, (mib << 20) / per_bytes);
+      if (k < d->batch) out.push_back("k=" + std::to_string(k));
+    }
+  };
   if (d->rank == 2) {
     for (const auto &r : cs((int)d->n[1], ELEM_FAST, ELEM_FAST, false, ks))
       for (const auto &c : cs((int)d->n[0], LINE_FAST, LINE_FAST, false, kb))
         out.push_back(enc(0, r) + " " + enc(1, c));
+    chunks(d->n[0] * d->n[1] * 8);
     return out;
   }
   const int64_t N = d->n[0];
@@ -186,6 +198,7 @@ std::vector<std::string> candidates(const fft_desc_t *d) {
       for (const auto &a : cs(N1, LINE_FAST, LINE_FAST, true, ks))
         for (const auto &b : cs(N2, ELEM_FAST, LINE_FAST, false, kb))
           out.push_back(enc(0, a) + " " + enc(1, b));
+      chunks(N * 8);
     }
     return out;
   }

@@ -25,12 +25,14 @@ int resident_for(int lds_bytes, int threads);
 //   c<i>=<C>   lines (rows or columns) per workgroup
 //   p<i>=0|1   persistent variant off / on
 //   o=0|1      radix order of runtime-radix lengths: powers of two first / odd first
+//   k=<n>      two-pass plans: transforms per chunk (0 = the whole batch at once)
 // Sources, first match wins: the autotuner while it times candidates, the
 // DPFFT_FORCE_PLAN environment variable, the tuning cache entry of the plan.
 struct Override {
   int c[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int p[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int order = -1;
+  int chunk = -1;
   std::string text;
   bool empty() const { return text.empty(); }
 };

@@ -63,6 +63,7 @@ struct LineStep : Step {
   int L = 0;
   dim3 grid;
   int src = BUF_IN, dst = BUF_OUT;
+  int64_t src_off = 0, dst_off = 0;  // element offsets into the buffers (chunked plans)
   LineArgs a{};
   size_t tw_off = 0, tw4_lo_off = 0, tw4_hi_off = 0, tw2_off = 0;
   int resident = 0;  // persistent instances: workgroups resident on the device

@@ -157,6 +157,8 @@ VARIANTS = [
     (4096, 10, "p0=1"), (8192, 6, "p0=1"), (1024, 37, "c0=8"), (2048, 9, "c0=4"),
     (4096, 7, "c0=2"), (1 << 22, 1, "c0=4 c1=4"), (1 << 20, 2, "c0=8 c1=8"),
     (1 << 18, 3, "c0=16 c1=16"), (1 << 22, 1, "c0=8 c1=8"),
+    # chunked four-step: the batch in groups of k signals, with a short last group
+    (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
 ]
 
 
@@ -177,7 +179,7 @@ def test_forced_variants(n, batch, force, monkeypatch):
         assert e <= TOL_FP32, (n, force, inv, e)
 
 
-@pytest.mark.parametrize("force", ["c1=8", "c1=4"])
+@pytest.mark.parametrize("force", ["c1=8", "c1=4", "k=1"])
 def test_forced_2d_variants(force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
