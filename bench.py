@@ -78,8 +78,9 @@ def load_traffic(kernel_key: str):
 class Item:
     """One planned transform of the workload: a plan and its device buffers."""
 
-    def __init__(self, dp, torch, name, plan, x, y, flop, alg_bytes_per_transform):
+    def __init__(self, dp, torch, name, plan, x, y, flop, alg_bytes_per_transform, compare=False):
         self.name, self.plan, self.x, self.y = name, plan, x, y
+        self.compare = compare  # timed after the step, for comparison only
         self.flop = flop
         self.alg_bytes = alg_bytes_per_transform
         self.nsteps = plan.num_steps()
@@ -153,15 +154,16 @@ def build_c5(dp, torch, synth, dev):
     x = torch.from_numpy(flat).to(dev)
     fl = float(sum(flops(int(n), 1) for n in sizes))
     items = []
-    for name, kw in (("ragged10000_persistent_graph", dict(graph=True)),
-                     ("ragged10000_persistent", dict()),
-                     ("ragged10000_per_length_launches", dict(per_size=True))):
+    for name, kw, cmp in (("ragged10000_persistent_graph", dict(graph=True), False),
+                          ("ragged10000_persistent", dict(), True),
+                          ("ragged10000_per_length_launches", dict(per_size=True), True)):
         p = dp.Plan(ragged_sizes=sizes.tolist(), **kw)
         items.append(Item(dp, torch, name, p, x.clone(), torch.empty_like(x), fl,
-                          16.0 * float(sizes.sum())))
+                          16.0 * float(sizes.sum()), compare=cmp))
     return items, {"workload": "c5: ragged batch of 10000 7-smooth sizes in [64, 65536], "
-                               "log-uniform; one persistent launch (graph / plain) vs one "
-                               "launch per distinct length"}
+                               "log-uniform; the step is the persistent two-launch queue in a HIP "
+                               "graph; the same queue without the graph and one launch per "
+                               "distinct length are timed after it for comparison"}
 
 
 # ---------------------------------------------------------------------------
@@ -243,6 +245,7 @@ def main():
 
     probe = copy_probe(torch, dev) if args.copy_probe else None
 
+    step_items = [it for it in items if not it.compare]
     for _ in range(args.warmup):
         for it in items:
             it.run()
@@ -251,17 +254,23 @@ def main():
     events = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        for it in items:
+        for it in step_items:
             it.run(events)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    # comparison items: same number of steps, outside the timed step
+    for _ in range(args.steps):
+        for it in items:
+            if it.compare:
+                it.run(events)
+    torch.cuda.synchronize()
 
     # per-kernel durations from the events of the timed region
     kern = {}
     for name, s, e0, e1 in events:
         kern.setdefault((name, s), []).append(e0.elapsed_time(e1))
-    step_flop = sum(2 * it.flop for it in items)
+    step_flop = sum(2 * it.flop for it in step_items)
     value = step_flop / (ms_step * 1e-3) / 1e9
     breakdown = {}
     for it in items:
@@ -274,8 +283,12 @@ def main():
                         for s in range(it.nsteps)],
             "plan": it.plan.describe().splitlines()[0],
         }
+        if it.compare:
+            breakdown[it.name]["comparison_only"] = True
     # dominant kernel: largest total time over the step
-    (dn, ds), dur = max(kern.items(), key=lambda kv: sum(kv[1]))
+    step_names = {it.name for it in step_items}
+    (dn, ds), dur = max(((k, v) for k, v in kern.items() if k[0] in step_names),
+                        key=lambda kv: sum(kv[1]))
     dit = next(it for it in items if it.name == dn)
     avg_ms = sum(dur) / len(dur)
     alg_per_launch = dit.alg_bytes / dit.nsteps  # the transform's 16 B/pt split over its launches

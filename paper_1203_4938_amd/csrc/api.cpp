@@ -145,8 +145,12 @@ bool LineStep::valid() const {
 
 std::string LineStep::describe() const {
   std::ostringstream o;
-  o << name << ": L=" << L << " C=" << k.lines << " threads=" << k.threads
-    << " grid=" << grid.x << " lds=" << k.lds_bytes << "B";
+  o << name << ": L=" << L << " C=" << k.lines << " threads=" << k.threads;
+  if (k.persistent)
+    o << " persistent tiles=" << a.ntiles << " grid<=" << resident;
+  else
+    o << " grid=" << grid.x;
+  o << " lds=" << k.lds_bytes << "B";
   return o.str();
 }
 
@@ -268,7 +272,10 @@ int resident_workgroups(const KernelInfo &k) { return resident_for(k.lds_bytes, 
 // Heuristic choice among the compiled instances of a line kernel: the most
 // resident waves per CU that the 160 KB LDS allows (counted up to 16), then
 // for row tiles the smaller tile (more workgroups to overlap), for column
-// tiles the wider tile (longer contiguous segments).
+// tiles the wider tile (longer contiguous segments).  Persistent instances are
+// taken by default only where a single 1024-thread workgroup fills the CU's
+// LDS (rows of 16384 points): there the prefetch of the next tile is the only
+// overlap of memory and compute the CU gets.  Elsewhere they are opt-in.
 bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const Override &ov,
                  KernelInfo *out) {
   KernelInfo cand[32];
@@ -280,14 +287,16 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
     if (ov.c[step] >= 0 && k.lines != ov.c[step]) continue;
     if (ov.c[step] < 0 && k.lines > cmax) continue;
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
-    if (ov.p[step] < 0 && k.persistent) continue;  // opt-in until measured
+    const bool pf_default = k.persistent && k.threads == 1024 && map == ELEM_FAST &&
+                            omap == ELEM_FAST;
+    if (ov.p[step] < 0 && k.persistent && !pf_default) continue;
     if (k.threads > 1024) continue;
     int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 64;
     int by_thr = 2048 / k.threads;
     int wg = std::min(by_lds, by_thr);
     double waves = wg * (k.threads / 64.0);
     double tie = (map == LINE_FAST || omap == LINE_FAST) ? k.lines : 1.0 / k.lines;
-    double score = std::min(waves, 16.0) * 1000 + tie;
+    double score = std::min(waves, 16.0) * 1000 + tie * 10 + (pf_default ? 1 : 0);
     if (score > best) {
       best = score;
       *out = k;

@@ -159,6 +159,8 @@ VARIANTS = [
     (1 << 18, 3, "c0=16 c1=16"), (1 << 22, 1, "c0=8 c1=8"),
     # chunked four-step: the batch in groups of k signals, with a short last group
     (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
+    # persistent 1024-thread instances
+    (16384, 300, "p0=1"), (1 << 22, 2, "p0=1 p1=1"), (1 << 20, 3, "p0=1 p1=1"),
 ]
 
 
