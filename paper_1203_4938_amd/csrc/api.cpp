@@ -139,7 +139,11 @@ bool LineStep::valid() const {
   // unit strides the kernel assumes, 32-bit in-line offsets, instances present
   const bool in_ok = k.map == ELEM_FAST ? a.in_e == 1 : a.in_l == 1;
   const bool out_ok = k.omap == ELEM_FAST ? a.out_e == 1 : a.out_l == 1;
-  const bool off_ok = (int64_t)(L - 1) * std::max(a.in_e, a.out_e) < (int64_t(1) << 31);
+  // a tile's elements lie within 2^29 elements (4 GiB) of its first line
+  const int64_t C = k.lines;
+  const int64_t span_in = (C - 1) * a.in_l + (int64_t)(L - 1) * a.in_e;
+  const int64_t span_out = (C - 1) * a.out_l + (int64_t)(L - 1) * a.out_e;
+  const bool off_ok = span_in < (int64_t(1) << 29) && span_out < (int64_t(1) << 29);
   return in_ok && out_ok && off_ok && k.fn_sw[0] && k.fn_sw[inverse_sw()];
 }
 
@@ -287,6 +291,7 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
     if (ov.c[step] >= 0 && k.lines != ov.c[step]) continue;
     if (ov.c[step] < 0 && k.lines > cmax) continue;
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
+    if (ov.t[step] >= 0 && k.threads != ov.t[step]) continue;
     const bool pf_default = k.persistent && k.threads == 1024 && map == ELEM_FAST &&
                             omap == ELEM_FAST;
     if (ov.p[step] < 0 && k.persistent && !pf_default) continue;

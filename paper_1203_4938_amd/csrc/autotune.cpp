@@ -42,6 +42,7 @@ Override parse_override(const std::string &text) {
     } else if (sscanf(tok.c_str(), "%c%d=%d", &kind, &idx, &val) == 3 && idx >= 0 && idx < 8) {
       if (kind == 'c') o.c[idx] = val;
       if (kind == 'p') o.p[idx] = val;
+      if (kind == 't') o.t[idx] = val;
     }
   }
   o.text = text;

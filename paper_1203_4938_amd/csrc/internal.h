@@ -24,6 +24,7 @@ int resident_for(int lds_bytes, int threads);
 // Kernel-choice overrides for the plan builders, per launch step i:
 //   c<i>=<C>   lines (rows or columns) per workgroup
 //   p<i>=0|1   persistent variant off / on
+//   t<i>=<T>   threads per workgroup (instances differing in elements per thread)
 //   o=0|1      radix order of runtime-radix lengths: powers of two first / odd first
 //   k=<n>      two-pass plans: transforms per chunk (0 = the whole batch at once)
 // Sources, first match wins: the autotuner while it times candidates, the
@@ -31,6 +32,7 @@ int resident_for(int lds_bytes, int threads);
 struct Override {
   int c[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int p[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int t[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int order = -1;
   int chunk = -1;
   std::string text;

@@ -20,6 +20,8 @@
 // Twiddles of pass p >= 1 are read from a per-length table built on the host
 // in FP64: entry (r-1)*Ns + k holds w_{Ns R}^{k r}, consecutive k for
 // consecutive lanes.
+#include <type_traits>
+
 #include "fft_common.h"
 #include "kernels.h"
 
@@ -55,6 +57,25 @@ __device__ __forceinline__ void lds_exchange(cf (&v)[E], cf *lds, WPos wpos, RPo
   if constexpr (TAIL) __syncthreads();
 }
 
+// The same exchange through a buffer of floats half the size: real parts
+// first, then imaginary parts, so the LDS of a tile is halved (at the price of
+// two more barriers per exchange).
+template <int E, bool TAIL, class WPos, class RPos>
+__device__ __forceinline__ void lds_exchange(cf (&v)[E], float *lds, WPos wpos, RPos rpos) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) lds[wpos(m)] = v[m].x;
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m].x = lds[rpos(m)];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) lds[wpos(m)] = v[m].y;
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m].y = lds[rpos(m)];
+  if constexpr (TAIL) __syncthreads();
+}
+
 // One Stockham pass on the registers of thread (c, j).  Butterfly q of the
 // thread is b = j + T*q; its inputs are v[q + r*QN] and its outputs are left
 // in the same registers, then (unless this is the last pass) exchanged so that
@@ -67,7 +88,7 @@ struct TwTable {
   const cf *__restrict__ tw;
   template <int L, int TWO, int NS, int R>
   __device__ __forceinline__ cf get(int r, int k) const {
-    return tw[TWO + (r - 1) * NS + k];
+    return *(const cf *)((const char *)tw + ((uint32_t)(TWO + (r - 1) * NS + k) << 3));
   }
 };
 struct TwLds2 {
@@ -81,8 +102,8 @@ struct TwLds2 {
   }
 };
 
-template <int L, int EPT, int C, int MAP, int P, class TW>
-__device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
+template <int L, int EPT, int C, int MAP, int P, class TW, class LT>
+__device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], LT *lds, const TW &tw, int c,
                                               int j) {
   using G = P2<L, EPT>;
   constexpr int E = G::E, T = G::T, R = G::radix(P), NS = G::ns(P), QN = E / R;
@@ -103,6 +124,9 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds,
     Dft<R>::run(x);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q + r * QN] = x[r];
+    // with several butterflies per thread, keep the scheduler from hoisting
+    // every butterfly's twiddle loads to the top of the pass
+    if constexpr (QN > 1 && E > 16) __builtin_amdgcn_sched_barrier(0);
   }
   if constexpr (!LAST) {
     auto wpos = [&](int m) {
@@ -116,8 +140,8 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds,
   }
 }
 
-template <int L, int EPT, int C, int MAP, class TW, int... P>
-__device__ __forceinline__ void all_passes(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
+template <int L, int EPT, int C, int MAP, class TW, class LT, int... P>
+__device__ __forceinline__ void all_passes(cf (&v)[(P2<L, EPT>::E)], LT *lds, const TW &tw, int c,
                                            int j, std::integer_sequence<int, P...>) {
   (stockham_pass<L, EPT, C, MAP, P>(v, lds, tw, c, j), ...);
 }
@@ -143,30 +167,60 @@ __device__ __forceinline__ cf tw4_lookup(const LineArgs &a, uint32_t e) {
 
 // Four-step twiddles w_N^{n2 k1} for the elements k1 = j + T*m (m = 0..E-1)
 // of column n2: with A = w_N^{n2 j} and B = w_N^{n2 T} (two table lookups
-// each), w_N^{n2 (j + T m)} = A * B^m, where B^m comes from a product tree of
-// depth at most 4 (B^2 = B B, B^4 = B^2 B^2, B^8 = B^4 B^4, the others as one
-// product of two of these), so no twiddle carries more than about six
-// roundings.
+// each), w_N^{n2 (j + T m)} = A * B^m.  Writing m = 4s + l, the factor is
+// (A B^l) * B^{4s}: the four A B^l come from B, B^2 = B B and B^3 = B^2 B, and
+// B^{4s} is the product of the repeated squares B^4, B^8, B^16, ... picked by
+// the bits of s.  No twiddle carries more than about seven roundings, and only
+// a handful of complex values stay live next to the data.
 template <int E>
 __device__ __forceinline__ void tw4_apply_ab(cf (&v)[E], cf A, cf B) {
-  cf Bm[E];
-  Bm[0] = make_float2(1.0f, 0.0f);
-  if constexpr (E > 1) Bm[1] = B;
+  if constexpr (E % 4 != 0) {
+    cf w = A;
 #pragma unroll
-  for (int m = 2; m < E; ++m) {
-    // largest power of two p <= m; B^m = B^p * B^(m-p), or B^(p/2)^2 for m = p
-    int p = 1;
-    while (2 * p <= m) p *= 2;
-    Bm[m] = (m == p) ? cmul(Bm[p / 2], Bm[p / 2]) : cmul(Bm[p], Bm[m - p]);
+    for (int m = 0; m < E; ++m) {
+      v[m] = cmul(v[m], w);
+      if (m + 1 < E) w = cmul(w, B);
+    }
+  } else {
+    constexpr int NG = E / 4;
+    constexpr int NB = NG <= 1 ? 1 : (NG <= 2 ? 1 : (NG <= 4 ? 2 : (NG <= 8 ? 3 : 4)));
+    const cf B2 = cmul(B, B);
+    const cf Al[4] = {A, cmul(A, B), cmul(A, B2), cmul(A, cmul(B2, B))};
+    cf Pw[NB];  // Pw[k] = B^(4 * 2^k)
+    Pw[0] = cmul(B2, B2);
+#pragma unroll
+    for (int k = 1; k < NB; ++k) Pw[k] = cmul(Pw[k - 1], Pw[k - 1]);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      cf Q = make_float2(1.0f, 0.0f);
+      bool have = false;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if ((g >> k) & 1) {
+          Q = have ? cmul(Q, Pw[k]) : Pw[k];
+          have = true;
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < 4; ++l) v[4 * g + l] = cmul(v[4 * g + l], have ? cmul(Al[l], Q) : Al[l]);
+    }
   }
-  v[0] = cmul(v[0], A);
-#pragma unroll
-  for (int m = 1; m < E; ++m) v[m] = cmul(v[m], cmul(A, Bm[m]));
 }
 
 template <int E>
 __device__ __forceinline__ void tw4_apply(cf (&v)[E], const LineArgs &a, uint32_t n2, int j, int T) {
   tw4_apply_ab<E>(v, tw4_lookup(a, n2 * (uint32_t)j), tw4_lookup(a, n2 * (uint32_t)T));
+}
+
+// Global accesses of a tile: a base address that is the same for the whole
+// workgroup plus a 32-bit byte offset per lane (the plan keeps every tile's
+// span below 4 GiB), so the loads and stores take the scalar-base form with a
+// single offset VGPR each.
+__device__ __forceinline__ cf ldg(const cf *base, uint32_t idx) {
+  return *(const cf *)((const char *)base + (idx << 3));
+}
+__device__ __forceinline__ void stg(cf *base, uint32_t idx, cf v) {
+  *(cf *)((char *)base + (idx << 3)) = v;
 }
 
 // LDS complex elements an instance needs (0 if it never exchanges)
@@ -183,15 +237,21 @@ constexpr int lds_pairs() {
 //
 // Addressing: an ELEM_FAST side has unit element stride (x_e == 1) and a
 // LINE_FAST side has unit line stride (x_l == 1); the plan guarantees it.
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
-__global__ void __launch_bounds__(C * (P2<L, EPT>::T))
+//
+// XS: exchange real and imaginary parts separately through a float buffer of
+// half the size (see lds_exchange).
+// The split instances ask for at least four waves per SIMD (at most 128 VGPRs),
+// which two 512-thread workgroups on one CU need.
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, bool XS>
+__global__ void __launch_bounds__(C * (P2<L, EPT>::T), XS ? 4 : 1)
     k_lines(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
   static_assert(C * G::T <= 1024, "a workgroup holds at most 1024 threads");
   constexpr int E = G::E, T = G::T;
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NP = lds_pairs<L, C, MAP, OMAP>();
-  __shared__ __align__(16) cf lds[NP > 0 ? NP : 1];
+  using LT = std::conditional_t<XS, float, cf>;
+  __shared__ __align__(16) LT lds[NP > 0 ? NP : 1];
 
   const int tid = threadIdx.x;
   int c, j;
@@ -204,15 +264,16 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 
   cf v[E];
   if (valid) {
+    const cf *tin = in + bb * a.in_b + line0 * a.in_l;
     if constexpr (MAP == ELEM_FAST) {
-      const cf *src = in + bb * a.in_b + line * a.in_l + j;
+      const uint32_t o = (uint32_t)c * (uint32_t)a.in_l + (uint32_t)j;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = src[T * m];
+      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m));
     } else {
-      const int32_t es = (int32_t)a.in_e;
-      const cf *src = in + bb * a.in_b + line + (int64_t)j * es;
+      const uint32_t es = (uint32_t)a.in_e;
+      const uint32_t o = (uint32_t)c + (uint32_t)j * es;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = src[(uint32_t)(T * m * es)];
+      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m) * es);
     }
     if constexpr (SW & 1) {
 #pragma unroll
@@ -247,15 +308,16 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
     }
+    cf *tout = out + bb * a.out_b + line0 * a.out_l;
     if constexpr (OMAP == ELEM_FAST) {
-      cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
+      const uint32_t o = (uint32_t)c2 * (uint32_t)a.out_l + (uint32_t)j2;
 #pragma unroll
-      for (int m = 0; m < E; ++m) dst[T * m] = v[m];
+      for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m), v[m]);
     } else {
-      const int32_t es = (int32_t)a.out_e;
-      cf *dst = out + bb * a.out_b + line2 + (int64_t)j2 * es;
+      const uint32_t es = (uint32_t)a.out_e;
+      const uint32_t o = (uint32_t)c2 + (uint32_t)j2 * es;
 #pragma unroll
-      for (int m = 0; m < E; ++m) dst[(uint32_t)(T * m * es)] = v[m];
+      for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m) * es, v[m]);
     }
   }
 }
@@ -274,17 +336,18 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
                                           bool swap) {
   constexpr int E = P2<L, EPT>::E, T = P2<L, EPT>::T;
   const int64_t bb = tile / a.tiles_per_batch;
-  const int64_t line = (tile - bb * a.tiles_per_batch) * C + c;
-  if (line < a.lines) {
+  const int64_t line0 = (tile - bb * a.tiles_per_batch) * C;
+  if (line0 + c < a.lines) {
+    const cf *tin = in + bb * a.in_b + line0 * a.in_l;
     if constexpr (MAP == ELEM_FAST) {
-      const cf *src = in + bb * a.in_b + line * a.in_l + j;
+      const uint32_t o = (uint32_t)c * (uint32_t)a.in_l + (uint32_t)j;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = src[T * m];
+      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m));
     } else {
-      const int32_t es = (int32_t)a.in_e;
-      const cf *src = in + bb * a.in_b + line + (int64_t)j * es;
+      const uint32_t es = (uint32_t)a.in_e;
+      const uint32_t o = (uint32_t)c + (uint32_t)j * es;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = src[(uint32_t)(T * m * es)];
+      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m) * es);
     }
     if (swap) {
 #pragma unroll
@@ -296,7 +359,7 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
   }
 }
 
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, bool XS>
 __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines_pf(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
@@ -305,7 +368,8 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   constexpr int S = tw2_shift(G::LG), NLO = 1 << S, NHI = (L >> S) > 0 ? (L >> S) : 1;
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NPR = lds_pairs<L, C, MAP, OMAP>();
-  __shared__ __align__(16) cf lds[NPR > 0 ? NPR : 1];
+  using LT = std::conditional_t<XS, float, cf>;
+  __shared__ __align__(16) LT lds[NPR > 0 ? NPR : 1];
   __shared__ cf twl[NLO + NHI];
   for (int i = threadIdx.x; i < NLO + NHI; i += NT) twl[i] = a.tw2[i];
   __syncthreads();
@@ -367,15 +431,16 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
       }
+      cf *tout = out + bb * a.out_b + line0 * a.out_l;
       if constexpr (OMAP == ELEM_FAST) {
-        cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
+        const uint32_t o = (uint32_t)c2 * (uint32_t)a.out_l + (uint32_t)j2;
 #pragma unroll
-        for (int m = 0; m < E; ++m) dst[T * m] = v[m];
+        for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m), v[m]);
       } else {
-        const int32_t es = (int32_t)a.out_e;
-        cf *dst = out + bb * a.out_b + line2 + (int64_t)j2 * es;
+        const uint32_t es = (uint32_t)a.out_e;
+        const uint32_t o = (uint32_t)c2 + (uint32_t)j2 * es;
 #pragma unroll
-        for (int m = 0; m < E; ++m) dst[(uint32_t)(T * m * es)] = v[m];
+        for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m) * es, v[m]);
       }
     }
 #pragma unroll
@@ -397,10 +462,10 @@ struct LineEntry {
   bool pf;
 };
 
-#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT>
+#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT, KXS>
 #define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
-            (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
+            (KXS ? 4 : 8) * lds_pairs<L_, C_, M_, O_>() +                           \
                 (KPF ? (int)sizeof(cf) * ((1 << tw2_shift(P2<L_>::LG)) +            \
                                           ((L_ >> tw2_shift(P2<L_>::LG)) > 0        \
                                                ? (L_ >> tw2_shift(P2<L_>::LG))      \
@@ -429,6 +494,7 @@ struct LineEntry {
 #define KFN k_lines
 #define KPF false
 #define KEPT 16
+#define KXS false
 static const LineEntry kLineTable[] = {
     // batched rows (single-pass transforms, 2D row pass)
     ROW(1, 256), ROW(2, 256), ROW(4, 256), ROW(8, 256), ROW(16, 256), ROW(32, 128),
@@ -444,12 +510,25 @@ static const LineEntry kLineTable[] = {
     ROWT(64, 16), ROWT(128, 16), ROWT(256, 16), ROWT(256, 32), ROWT(512, 16),
     ROWT(1024, 16), ROWT(1024, 8), ROWT(2048, 4), ROWT(2048, 8), ROWT(4096, 4),
 };
+#undef KEPT
+#undef KXS
+#define KEPT 32
+#define KXS true
+// 32 elements per thread and half-size LDS: 512-thread workgroups of the
+// tiles that otherwise need 1024 threads and most of the CU's LDS, so that two
+// workgroups share a CU
+static const LineEntry kLineTableXs[] = {
+    ROW(16384, 1), COL(2048, 8), COLTW(2048, 8), ROWT(2048, 8),
+    COLTW(1024, 16), ROWT(1024, 16), COL(1024, 16),
+};
 #undef KFN
 #undef KPF
 #undef KEPT
+#undef KXS
 #define KFN k_lines_pf
 #define KPF true
 #define KEPT 16
+#define KXS false
 // persistent instances, 16 elements per thread.  Column and transposed-row
 // tiles have none: with the four-step twiddle or the strided addressing the
 // two register sets do not fit the 1024-thread budget without spills.
@@ -459,6 +538,7 @@ static const LineEntry kLineTablePf[] = {
 #undef KFN
 #undef KPF
 #undef KEPT
+#undef KXS
 
 static void fill(const LineEntry &e, KernelInfo *out) {
   for (int i = 0; i < 4; ++i) out->fn_sw[i] = e.fn[i];
@@ -474,6 +554,7 @@ static void fill(const LineEntry &e, KernelInfo *out) {
 template <class F>
 static void for_each_entry(F f) {
   for (const auto &e : kLineTable) f(e);
+  for (const auto &e : kLineTableXs) f(e);
   for (const auto &e : kLineTablePf) f(e);
 }
 

@@ -160,7 +160,9 @@ VARIANTS = [
     # chunked four-step: the batch in groups of k signals, with a short last group
     (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
     # persistent 1024-thread instances
-    (16384, 300, "p0=1"), (1 << 22, 2, "p0=1 p1=1"), (1 << 20, 3, "p0=1 p1=1"),
+    (16384, 300, "p0=1"),
+    # 512-thread instances, 32 elements per thread, re/im split exchanges
+    (16384, 9, "t0=512"), (1 << 22, 1, "t0=512 t1=512"), (1 << 20, 2, "t0=512 t1=512"),
 ]
 
 
@@ -181,7 +183,7 @@ def test_forced_variants(n, batch, force, monkeypatch):
         assert e <= TOL_FP32, (n, force, inv, e)
 
 
-@pytest.mark.parametrize("force", ["c1=8", "c1=4", "k=1"])
+@pytest.mark.parametrize("force", ["c1=8", "c1=4", "k=1", "t1=512"])
 def test_forced_2d_variants(force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
