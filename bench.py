@@ -49,14 +49,21 @@ def parse():
 
 
 # ---------------------------------------------------------------------------
+# Sources of the power-of-two line kernels and of the planner that picks them:
+# the kernels of the c2 workload.  A change to any of them voids the stored
+# counter profile.
+TRAFFIC_SOURCES = ("line_kernels.hip", "kernels.h", "fft_common.h", "api.cpp", "plan.h",
+                   "internal.h", "twiddle.cpp", "twiddle.h")
+
+
 def src_digest() -> str:
-    """Hash of the kernel sources; a stored counter profile is valid only for it."""
+    """Hash of the line-kernel and planner sources; a stored counter profile is
+    valid only for it."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1203_4938_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 

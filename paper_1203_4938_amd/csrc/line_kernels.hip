@@ -20,8 +20,6 @@
 // Twiddles of pass p >= 1 are read from a per-length table built on the host
 // in FP64: entry (r-1)*Ns + k holds w_{Ns R}^{k r}, consecutive k for
 // consecutive lanes.
-#include <type_traits>
-
 #include "fft_common.h"
 #include "kernels.h"
 
@@ -57,25 +55,6 @@ __device__ __forceinline__ void lds_exchange(cf (&v)[E], cf *lds, WPos wpos, RPo
   if constexpr (TAIL) __syncthreads();
 }
 
-// The same exchange through a buffer of floats half the size: real parts
-// first, then imaginary parts, so the LDS of a tile is halved (at the price of
-// two more barriers per exchange).
-template <int E, bool TAIL, class WPos, class RPos>
-__device__ __forceinline__ void lds_exchange(cf (&v)[E], float *lds, WPos wpos, RPos rpos) {
-#pragma unroll
-  for (int m = 0; m < E; ++m) lds[wpos(m)] = v[m].x;
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < E; ++m) v[m].x = lds[rpos(m)];
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < E; ++m) lds[wpos(m)] = v[m].y;
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < E; ++m) v[m].y = lds[rpos(m)];
-  if constexpr (TAIL) __syncthreads();
-}
-
 // One Stockham pass on the registers of thread (c, j).  Butterfly q of the
 // thread is b = j + T*q; its inputs are v[q + r*QN] and its outputs are left
 // in the same registers, then (unless this is the last pass) exchanged so that
@@ -102,8 +81,8 @@ struct TwLds2 {
   }
 };
 
-template <int L, int EPT, int C, int MAP, int P, class TW, class LT>
-__device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], LT *lds, const TW &tw, int c,
+template <int L, int EPT, int C, int MAP, int P, class TW>
+__device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
                                               int j) {
   using G = P2<L, EPT>;
   constexpr int E = G::E, T = G::T, R = G::radix(P), NS = G::ns(P), QN = E / R;
@@ -124,9 +103,6 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], LT *lds,
     Dft<R>::run(x);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q + r * QN] = x[r];
-    // with several butterflies per thread, keep the scheduler from hoisting
-    // every butterfly's twiddle loads to the top of the pass
-    if constexpr (QN > 1 && E > 16) __builtin_amdgcn_sched_barrier(0);
   }
   if constexpr (!LAST) {
     auto wpos = [&](int m) {
@@ -140,8 +116,8 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], LT *lds,
   }
 }
 
-template <int L, int EPT, int C, int MAP, class TW, class LT, int... P>
-__device__ __forceinline__ void all_passes(cf (&v)[(P2<L, EPT>::E)], LT *lds, const TW &tw, int c,
+template <int L, int EPT, int C, int MAP, class TW, int... P>
+__device__ __forceinline__ void all_passes(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
                                            int j, std::integer_sequence<int, P...>) {
   (stockham_pass<L, EPT, C, MAP, P>(v, lds, tw, c, j), ...);
 }
@@ -237,21 +213,15 @@ constexpr int lds_pairs() {
 //
 // Addressing: an ELEM_FAST side has unit element stride (x_e == 1) and a
 // LINE_FAST side has unit line stride (x_l == 1); the plan guarantees it.
-//
-// XS: exchange real and imaginary parts separately through a float buffer of
-// half the size (see lds_exchange).
-// The split instances ask for at least four waves per SIMD (at most 128 VGPRs),
-// which two 512-thread workgroups on one CU need.
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, bool XS>
-__global__ void __launch_bounds__(C * (P2<L, EPT>::T), XS ? 4 : 1)
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
+__global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
   static_assert(C * G::T <= 1024, "a workgroup holds at most 1024 threads");
   constexpr int E = G::E, T = G::T;
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NP = lds_pairs<L, C, MAP, OMAP>();
-  using LT = std::conditional_t<XS, float, cf>;
-  __shared__ __align__(16) LT lds[NP > 0 ? NP : 1];
+  __shared__ __align__(16) cf lds[NP > 0 ? NP : 1];
 
   const int tid = threadIdx.x;
   int c, j;
@@ -359,7 +329,7 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
   }
 }
 
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, bool XS>
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
 __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines_pf(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
@@ -368,8 +338,7 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   constexpr int S = tw2_shift(G::LG), NLO = 1 << S, NHI = (L >> S) > 0 ? (L >> S) : 1;
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NPR = lds_pairs<L, C, MAP, OMAP>();
-  using LT = std::conditional_t<XS, float, cf>;
-  __shared__ __align__(16) LT lds[NPR > 0 ? NPR : 1];
+  __shared__ __align__(16) cf lds[NPR > 0 ? NPR : 1];
   __shared__ cf twl[NLO + NHI];
   for (int i = threadIdx.x; i < NLO + NHI; i += NT) twl[i] = a.tw2[i];
   __syncthreads();
@@ -462,10 +431,10 @@ struct LineEntry {
   bool pf;
 };
 
-#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT, KXS>
+#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT>
 #define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
-            (KXS ? 4 : 8) * lds_pairs<L_, C_, M_, O_>() +                           \
+            (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
                 (KPF ? (int)sizeof(cf) * ((1 << tw2_shift(P2<L_>::LG)) +            \
                                           ((L_ >> tw2_shift(P2<L_>::LG)) > 0        \
                                                ? (L_ >> tw2_shift(P2<L_>::LG))      \
@@ -494,7 +463,6 @@ struct LineEntry {
 #define KFN k_lines
 #define KPF false
 #define KEPT 16
-#define KXS false
 static const LineEntry kLineTable[] = {
     // batched rows (single-pass transforms, 2D row pass)
     ROW(1, 256), ROW(2, 256), ROW(4, 256), ROW(8, 256), ROW(16, 256), ROW(32, 128),
@@ -510,25 +478,12 @@ static const LineEntry kLineTable[] = {
     ROWT(64, 16), ROWT(128, 16), ROWT(256, 16), ROWT(256, 32), ROWT(512, 16),
     ROWT(1024, 16), ROWT(1024, 8), ROWT(2048, 4), ROWT(2048, 8), ROWT(4096, 4),
 };
-#undef KEPT
-#undef KXS
-#define KEPT 32
-#define KXS true
-// 32 elements per thread and half-size LDS: 512-thread workgroups of the
-// tiles that otherwise need 1024 threads and most of the CU's LDS, so that two
-// workgroups share a CU
-static const LineEntry kLineTableXs[] = {
-    ROW(16384, 1), COL(2048, 8), COLTW(2048, 8), ROWT(2048, 8),
-    COLTW(1024, 16), ROWT(1024, 16), COL(1024, 16),
-};
 #undef KFN
 #undef KPF
 #undef KEPT
-#undef KXS
 #define KFN k_lines_pf
 #define KPF true
 #define KEPT 16
-#define KXS false
 // persistent instances, 16 elements per thread.  Column and transposed-row
 // tiles have none: with the four-step twiddle or the strided addressing the
 // two register sets do not fit the 1024-thread budget without spills.
@@ -538,7 +493,6 @@ static const LineEntry kLineTablePf[] = {
 #undef KFN
 #undef KPF
 #undef KEPT
-#undef KXS
 
 static void fill(const LineEntry &e, KernelInfo *out) {
   for (int i = 0; i < 4; ++i) out->fn_sw[i] = e.fn[i];
@@ -554,7 +508,6 @@ static void fill(const LineEntry &e, KernelInfo *out) {
 template <class F>
 static void for_each_entry(F f) {
   for (const auto &e : kLineTable) f(e);
-  for (const auto &e : kLineTableXs) f(e);
   for (const auto &e : kLineTablePf) f(e);
 }
 

@@ -160,9 +160,7 @@ VARIANTS = [
     # chunked four-step: the batch in groups of k signals, with a short last group
     (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
     # persistent 1024-thread instances
-    (16384, 300, "p0=1"),
-    # 512-thread instances, 32 elements per thread, re/im split exchanges
-    (16384, 9, "t0=512"), (1 << 22, 1, "t0=512 t1=512"), (1 << 20, 2, "t0=512 t1=512"),
+    (16384, 300, "p0=1"), (16384, 7, "p0=0"), (4096, 9, "c0=2 p0=0"),
 ]
 
 
@@ -183,7 +181,7 @@ def test_forced_variants(n, batch, force, monkeypatch):
         assert e <= TOL_FP32, (n, force, inv, e)
 
 
-@pytest.mark.parametrize("force", ["c1=8", "c1=4", "k=1", "t1=512"])
+@pytest.mark.parametrize("force", ["c1=8", "c1=4", "k=1"])
 def test_forced_2d_variants(force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)

@@ -1,5 +1,5 @@
 """GPU parity of ragged batches (packed signals of mixed 7-smooth lengths)
-against the FP64 oracle: the persistent queue launch, the same launch replayed
+against the FP64 oracle: the two persistent launches, the same launches replayed
 from a HIP graph (several replays with eager work between them, each checked),
 and the one-launch-per-length baseline; forward and inverse; lengths from 1 to
 65536 including four-step lengths above 16384; and the full 10,000-signal
@@ -82,7 +82,7 @@ def test_ragged_with_gaps_and_explicit_offsets():
 
 def test_c5_full_workload_every_signal():
     """The 10,000-signal workload in the launch configuration the benchmark
-    times (persistent queue in a HIP graph), every signal against the oracle."""
+    times (persistent launches in a HIP graph), every signal against the oracle."""
     import paper_1203_4938_amd as dp
     w = synth.workloads()["c5_ragged_10000"]
     sizes = synth.ragged_sizes(w.seed, w.count)

@@ -60,7 +60,7 @@ def test_ragged_plan_counts():
     import synth
     sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
     t = _dry(ragged_sizes=sizes.tolist(), flags=4)
-    assert "10000 signals" in t and "HIP graph" in t and "persistent queue" in t
+    assert "10000 signals" in t and "HIP graph" in t and "two persistent launches" in t
     t2 = _dry(ragged_sizes=sizes.tolist(), flags=8)
     assert "one launch per length" in t2
 
