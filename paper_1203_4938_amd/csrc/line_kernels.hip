@@ -366,10 +366,9 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   }
 
   for (; tile < a.ntiles; tile += Gd) {
-    // At 1024 threads a lane has 128 VGPRs: keep the compiler from hoisting
-    // every pass's LDS addresses and twiddles out of the tile loop, which
-    // would not fit next to the two register sets.
-    if constexpr (NT > 512) asm volatile("" : "+v"(c), "+v"(j));
+    // Keep the compiler from hoisting every pass's LDS addresses and twiddles
+    // out of the tile loop: they would not fit next to the two register sets.
+    asm volatile("" : "+v"(c), "+v"(j));
     const int64_t next = tile + Gd;
     if (next < a.ntiles) {
       load_tile<L, EPT, C, MAP>(vn, in, a, next, c, j, (SW & 1) != 0);
@@ -484,11 +483,12 @@ static const LineEntry kLineTable[] = {
 #define KFN k_lines_pf
 #define KPF true
 #define KEPT 16
-// persistent instances, 16 elements per thread.  Column and transposed-row
-// tiles have none: with the four-step twiddle or the strided addressing the
-// two register sets do not fit the 1024-thread budget without spills.
+// persistent instances, 16 elements per thread.  Transposed-row tiles have
+// none (with the re-tiling exchange the two register sets do not fit the
+// 1024-thread budget without spills), nor do the 2048-point column tiles,
+// whose persistent form measured slower than the plain one.
 static const LineEntry kLineTablePf[] = {
-    ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
+    ROW(4096, 2), ROW(8192, 1), ROW(16384, 1), COL(1024, 16), COLTW(1024, 16),
 };
 #undef KFN
 #undef KPF

@@ -48,6 +48,29 @@ __device__ __forceinline__ cf tw2_lookup(const lcf *t, int shift, uint32_t e) {
   return cmul(hi, lo);
 }
 
+// Pass twiddles w_L^{e1 r}, r = 1..R-1, into x[1..R-1] (multiplied in).  For
+// R = 8 and 16 only r = 1, 2, 3 and the multiples of 4 are looked up; the
+// others are products w^{4s} w^{l}, which halves the table reads.
+template <int R>
+__device__ __forceinline__ void apply_pass_twiddles(cf *x, const lcf *t, int shift, uint32_t e1) {
+  if constexpr (R == 8 || R == 16) {
+    cf wl[4], w4[R / 4];
+#pragma unroll
+    for (int l = 1; l < 4; ++l) wl[l] = tw2_lookup(t, shift, e1 * (uint32_t)l);
+#pragma unroll
+    for (int s = 1; s < R / 4; ++s) w4[s] = tw2_lookup(t, shift, e1 * (uint32_t)(4 * s));
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const int s = r / 4, l = r % 4;
+      const cf w = s == 0 ? wl[l] : (l == 0 ? w4[s] : cmul(w4[s], wl[l]));
+      x[r] = cmul(x[r], w);
+    }
+  } else {
+#pragma unroll
+    for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw2_lookup(t, shift, e1 * (uint32_t)r));
+  }
+}
+
 __device__ __forceinline__ cf tw4_lookup_m(const MixedArgs &a, uint32_t e) {
   const uint32_t lo = e & ((1u << a.tw4_shift) - 1u);
   const uint32_t hi = e >> a.tw4_shift;
@@ -75,10 +98,12 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
   };
   cf v[QM][R];
   bool act[QM];
+  int kq[QM];
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
     const int b = j + T * q;
     act[q] = valid && b < M;
+    kq[q] = NS > 1 ? b % NS : 0;
     if (!act[q]) continue;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -93,11 +118,8 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
       v[q][r] = y;
     }
     if (NS > 1) {
-      const int k = b % NS;
       const uint32_t step = (uint32_t)(L / (NS * R));
-#pragma unroll
-      for (int r = 1; r < R; ++r)
-        v[q][r] = cmul(v[q][r], tw2_lookup(tw2, tw2_shift, (uint32_t)(k * r) * step));
+      apply_pass_twiddles<R>(v[q], tw2, tw2_shift, (uint32_t)kq[q] * step);
     }
     Dft<R>::run(v[q]);
   }
@@ -106,7 +128,7 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
   for (int q = 0; q < QM; ++q) {
     if (!act[q]) continue;
     const int b = j + T * q;
-    const int k = b % NS;
+    const int k = kq[q];
     const int base = (b - k) * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -161,6 +161,7 @@ VARIANTS = [
     (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
     # persistent 1024-thread instances
     (16384, 300, "p0=1"), (16384, 7, "p0=0"), (4096, 9, "c0=2 p0=0"),
+    (1 << 20, 3, "p0=1"),
 ]
 
 
@@ -181,12 +182,12 @@ def test_forced_variants(n, batch, force, monkeypatch):
         assert e <= TOL_FP32, (n, force, inv, e)
 
 
-@pytest.mark.parametrize("force", ["c1=8", "c1=4", "k=1"])
-def test_forced_2d_variants(force, monkeypatch):
+@pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1")])
+def test_forced_2d_variants(n, force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
-    x = synth.images_complex(synth.BASE_SEED + 3, 2, 2048, 2048)
-    p = dp.Plan(shape=(2048, 2048), batch=2, rank=2)
+    x = synth.images_complex(synth.BASE_SEED + 3, 2, n, n)
+    p = dp.Plan(shape=(n, n), batch=2, rank=2)
     xd = to_dev(x)
     for inv in (False, True):
         y = run_plan(p, xd, inverse=inv).cpu().numpy()
