@@ -20,6 +20,8 @@
 // Twiddles of pass p >= 1 are read from a per-length table built on the host
 // in FP64: entry (r-1)*Ns + k holds w_{Ns R}^{k r}, consecutive k for
 // consecutive lanes.
+#include <type_traits>
+
 #include "fft_common.h"
 #include "kernels.h"
 
@@ -68,6 +70,14 @@ struct TwTable {
   template <int L, int TWO, int NS, int R>
   __device__ __forceinline__ cf get(int r, int k) const {
     return *(const cf *)((const char *)tw + ((uint32_t)(TWO + (r - 1) * NS + k) << 3));
+  }
+};
+// TwLdsTable: the per-pass table itself, copied to LDS (one read per twiddle)
+struct TwLdsTable {
+  const cf *t;
+  template <int L, int TWO, int NS, int R>
+  __device__ __forceinline__ cf get(int r, int k) const {
+    return t[TWO + (r - 1) * NS + k];
   }
 };
 struct TwLds2 {
@@ -302,8 +312,7 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 // ---------------------------------------------------------------------------
 template <int L, int EPT, int C, int MAP>
 __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__restrict__ in,
-                                          const LineArgs &a, int64_t tile, int c, int j,
-                                          bool swap) {
+                                          const LineArgs &a, int64_t tile, int c, int j) {
   constexpr int E = P2<L, EPT>::E, T = P2<L, EPT>::T;
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (tile - bb * a.tiles_per_batch) * C;
@@ -319,13 +328,26 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m) * es);
     }
-    if (swap) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
-    }
   } else {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = make_float2(0.0f, 0.0f);
+  }
+}
+
+// Pass twiddles of a persistent instance: the whole per-pass table when it
+// fits in LDS next to the tile, else the two-level table (one more product per
+// twiddle).  Returns the LDS entries taken.
+template <int L, int C, int MAP, int OMAP>
+constexpr bool pf_direct_tw() {
+  return (lds_pairs<L, C, MAP, OMAP>() + P2<L>::twoff(P2<L>::NP)) * 8 <= 160 * 1024;
+}
+template <int L, int C, int MAP, int OMAP>
+constexpr int pf_tw_entries() {
+  if constexpr (pf_direct_tw<L, C, MAP, OMAP>()) {
+    return P2<L>::twoff(P2<L>::NP) > 0 ? P2<L>::twoff(P2<L>::NP) : 1;
+  } else {
+    return (1 << tw2_shift(P2<L>::LG)) +
+           ((L >> tw2_shift(P2<L>::LG)) > 0 ? (L >> tw2_shift(P2<L>::LG)) : 1);
   }
 }
 
@@ -339,10 +361,19 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NPR = lds_pairs<L, C, MAP, OMAP>();
   __shared__ __align__(16) cf lds[NPR > 0 ? NPR : 1];
-  __shared__ cf twl[NLO + NHI];
-  for (int i = threadIdx.x; i < NLO + NHI; i += NT) twl[i] = a.tw2[i];
+  constexpr bool DIRECT = pf_direct_tw<L, C, MAP, OMAP>();
+  constexpr int NTW = pf_tw_entries<L, C, MAP, OMAP>();
+  __shared__ cf twl[NTW];
+  const cf *tsrc = DIRECT ? a.tw : a.tw2;
+  for (int i = threadIdx.x; i < NTW; i += NT) twl[i] = tsrc[i];
   __syncthreads();
-  const TwLds2 tw{twl, twl + NLO};
+  using TWS = std::conditional_t<DIRECT, TwLdsTable, TwLds2>;
+  TWS tw;
+  if constexpr (DIRECT) {
+    tw = TwLdsTable{twl};
+  } else {
+    tw = TwLds2{twl, twl + NLO};
+  }
 
   const int tid = threadIdx.x;
   int c, j;
@@ -352,9 +383,13 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   int64_t tile = slot;
   if (tile >= a.ntiles) return;
 
+  // The prefetched tile is swapped (inverse) only when it becomes current, and
+  // the four-step twiddle inputs of the next tile are loaded before its data:
+  // every wait for an older load then leaves the prefetch in flight.
   cf v[E], vn[E];
-  load_tile<L, EPT, C, MAP>(v, in, a, tile, c, j, (SW & 1) != 0);
-  cf A = make_float2(1.f, 0.f), B = A, An = A, Bn = A;
+  load_tile<L, EPT, C, MAP>(v, in, a, tile, c, j);
+  cf A = make_float2(1.f, 0.f), B = A;
+  cf nAh = A, nAl = A, nBh = A, nBl = A;  // tw4 table entries of the next tile
   auto line_of = [&](int64_t t) {
     const int64_t bb = t / a.tiles_per_batch;
     return (t - bb * a.tiles_per_batch) * C + c;
@@ -371,12 +406,20 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     asm volatile("" : "+v"(c), "+v"(j));
     const int64_t next = tile + Gd;
     if (next < a.ntiles) {
-      load_tile<L, EPT, C, MAP>(vn, in, a, next, c, j, (SW & 1) != 0);
       if constexpr (TW4) {
         const uint32_t n2 = (uint32_t)line_of(next);
-        An = tw4_lookup(a, n2 * (uint32_t)j);
-        Bn = tw4_lookup(a, n2 * (uint32_t)T);
+        const uint32_t eA = n2 * (uint32_t)j, eB = n2 * (uint32_t)T;
+        const uint32_t msk = (1u << a.tw4_shift) - 1u;
+        nAh = a.tw4_hi[eA >> a.tw4_shift];
+        nAl = a.tw4_lo[eA & msk];
+        nBh = a.tw4_hi[eB >> a.tw4_shift];
+        nBl = a.tw4_lo[eB & msk];
       }
+      load_tile<L, EPT, C, MAP>(vn, in, a, next, c, j);
+    }
+    if constexpr (SW & 1) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
     }
     all_passes<L, EPT, C, MAP>(v, lds, tw, c, j, std::make_integer_sequence<int, G::NP>{});
     if constexpr (TW4) tw4_apply_ab<E>(v, A, B);
@@ -413,8 +456,10 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = vn[m];
-    A = An;
-    B = Bn;
+    if constexpr (TW4) {
+      A = cmul(nAh, nAl);
+      B = cmul(nBh, nBl);
+    }
   }
 }
 
@@ -434,11 +479,7 @@ struct LineEntry {
 #define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
             (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
-                (KPF ? (int)sizeof(cf) * ((1 << tw2_shift(P2<L_>::LG)) +            \
-                                          ((L_ >> tw2_shift(P2<L_>::LG)) > 0        \
-                                               ? (L_ >> tw2_shift(P2<L_>::LG))      \
-                                               : 1))                                \
-                     : 0),                                                          \
+                (KPF ? (int)sizeof(cf) * pf_tw_entries<L_, C_, M_, O_>() : 0),      \
             KPF}
 
 // rows: forward, inverse single pass (swap in+out), 2D row pass inverse (swap in)
@@ -489,6 +530,7 @@ static const LineEntry kLineTable[] = {
 // whose persistent form measured slower than the plain one.
 static const LineEntry kLineTablePf[] = {
     ROW(4096, 2), ROW(8192, 1), ROW(16384, 1), COL(1024, 16), COLTW(1024, 16),
+    COL(2048, 8), COLTW(2048, 8), ROWT(2048, 8), ROWT(1024, 16),
 };
 #undef KFN
 #undef KPF
