@@ -190,8 +190,10 @@ void MixedStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_
 }
 
 bool MixedStep::valid() const {
+  // element strides travel to the passes as 32-bit values
   return fn_sw[0] && fn_sw[inverse_sw()] && threads > 0 && threads <= 1024 &&
-         threads == a.mp.C * a.mp.T && lds_bytes <= kLdsBytes && a.mp.T * 16 >= a.mp.L;
+         threads == a.mp.C * a.mp.T && lds_bytes <= kLdsBytes && a.mp.T * 16 >= a.mp.L &&
+         a.in_e < (int64_t(1) << 31) && a.out_e < (int64_t(1) << 31);
 }
 
 std::string MixedStep::describe() const {
@@ -277,9 +279,10 @@ int resident_workgroups(const KernelInfo &k) { return resident_for(k.lds_bytes, 
 // resident waves per CU that the 160 KB LDS allows (counted up to 16), then
 // for row tiles the smaller tile (more workgroups to overlap), for column
 // tiles the wider tile (longer contiguous segments).  Persistent instances are
-// taken by default only where a single 1024-thread workgroup fills the CU's
-// LDS (rows of 16384 points): there the prefetch of the next tile is the only
-// overlap of memory and compute the CU gets.  Elsewhere they are opt-in.
+// taken by default where a single 1024-thread workgroup fills the CU's LDS
+// (rows of 16384 points, 1024-point column tiles): there the prefetch of the
+// next tile is the only overlap of memory and compute the CU gets.  Elsewhere
+// they are opt-in.
 bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const Override &ov,
                  KernelInfo *out) {
   KernelInfo cand[32];
@@ -292,8 +295,7 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
     if (ov.c[step] < 0 && k.lines > cmax) continue;
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
     if (ov.t[step] >= 0 && k.threads != ov.t[step]) continue;
-    const bool pf_default = k.persistent && k.threads == 1024 && map == ELEM_FAST &&
-                            omap == ELEM_FAST;
+    const bool pf_default = k.persistent && k.threads == 1024 && map == omap;
     if (ov.p[step] < 0 && k.persistent && !pf_default) continue;
     if (k.threads > 1024) continue;
     int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 64;
@@ -389,7 +391,8 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   // (stride N2) and twiddle w_N^{n2 k1} into the workspace Y[k1][n2]; pass B:
   // N2-point FFTs along the rows of Y, stored transposed: X[k1 + N1 k2].
   const int lg = ilog2(N);
-  const int N1 = 1 << (lg / 2), N2 = 1 << (lg - lg / 2);
+  const int lg1 = (ov.split > 0 && ov.split < lg) ? ov.split : lg / 2;
+  const int N1 = 1 << lg1, N2 = 1 << (lg - lg1);
   auto a = make_line(P, "fourstep_columns", N1, LINE_FAST, LINE_FAST, true, 16, 0, ov);
   auto b = make_line(P, "fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false, 16, 1, ov);
   if (!a || !b) return fail(FFT_E_UNSUPPORTED, "no four-step kernels for N=" + std::to_string(N));

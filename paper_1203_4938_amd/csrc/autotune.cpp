@@ -39,6 +39,8 @@ Override parse_override(const std::string &text) {
       o.order = val;
     } else if (sscanf(tok.c_str(), "k=%d", &val) == 1) {
       o.chunk = val;
+    } else if (sscanf(tok.c_str(), "s=%d", &val) == 1) {
+      o.split = val;
     } else if (sscanf(tok.c_str(), "%c%d=%d", &kind, &idx, &val) == 3 && idx >= 0 && idx < 8) {
       if (kind == 'c') o.c[idx] = val;
       if (kind == 'p') o.p[idx] = val;

@@ -27,6 +27,7 @@ int resident_for(int lds_bytes, int threads);
 //   t<i>=<T>   threads per workgroup (instances differing in elements per thread)
 //   o=0|1      radix order of runtime-radix lengths: powers of two first / odd first
 //   k=<n>      two-pass plans: transforms per chunk (0 = the whole batch at once)
+//   s=<n>      power-of-two four-step: log2 of the column length N1
 // Sources, first match wins: the autotuner while it times candidates, the
 // DPFFT_FORCE_PLAN environment variable, the tuning cache entry of the plan.
 struct Override {
@@ -35,6 +36,7 @@ struct Override {
   int t[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int order = -1;
   int chunk = -1;
+  int split = -1;
   std::string text;
   bool empty() const { return text.empty(); }
 };

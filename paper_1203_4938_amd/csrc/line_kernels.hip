@@ -530,7 +530,6 @@ static const LineEntry kLineTable[] = {
 // whose persistent form measured slower than the plain one.
 static const LineEntry kLineTablePf[] = {
     ROW(4096, 2), ROW(8192, 1), ROW(16384, 1), COL(1024, 16), COLTW(1024, 16),
-    COL(2048, 8), COLTW(2048, 8), ROWT(2048, 8), ROWT(1024, 16),
 };
 #undef KFN
 #undef KPF

@@ -91,6 +91,21 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
                                         int pitch, int NS, int tw2_shift, int tw4_shift, int c,
                                         int j, bool valid, bool first, bool last, int64_t in_e,
                                         int64_t out_e, int64_t line, float scale) {
+  // The shape arguments arrive in VGPRs (this is a call); they are the same in
+  // every lane, so move them to SGPRs: the divisions and branches on them then
+  // run once per wave on the scalar unit instead of on the VALU.
+  L = __builtin_amdgcn_readfirstlane(L);
+  T = __builtin_amdgcn_readfirstlane(T);
+  C = __builtin_amdgcn_readfirstlane(C);
+  pitch = __builtin_amdgcn_readfirstlane(pitch);
+  NS = __builtin_amdgcn_readfirstlane(NS);
+  tw2_shift = __builtin_amdgcn_readfirstlane(tw2_shift);
+  tw4_shift = __builtin_amdgcn_readfirstlane(tw4_shift);
+  first = __builtin_amdgcn_readfirstlane((int)first) != 0;
+  last = __builtin_amdgcn_readfirstlane((int)last) != 0;
+  in_e = (int64_t)__builtin_amdgcn_readfirstlane((int)in_e);
+  out_e = (int64_t)__builtin_amdgcn_readfirstlane((int)out_e);
+  scale = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(scale)));
   const int M = L / R;
   constexpr int QM = (16 + R - 1) / R;  // butterflies per thread (T >= L/16)
   auto li = [&](int m, int pos) {

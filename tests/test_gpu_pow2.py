@@ -161,7 +161,9 @@ VARIANTS = [
     (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
     # persistent 1024-thread instances
     (16384, 300, "p0=1"), (16384, 7, "p0=0"), (4096, 9, "c0=2 p0=0"),
-    (1 << 20, 3, "p0=1"), (1 << 20, 3, "p1=1"), (1 << 22, 2, "p0=1 p1=1"),
+    (1 << 20, 3, "p0=1"), (1 << 20, 3, "p0=0"),
+    # other four-step splits of 2^22 (1024 x 4096, 4096 x 1024)
+    (1 << 22, 1, "s=10"), (1 << 22, 1, "s=12"),
 ]
 
 
@@ -182,7 +184,7 @@ def test_forced_variants(n, batch, force, monkeypatch):
         assert e <= TOL_FP32, (n, force, inv, e)
 
 
-@pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (2048, "p1=1")])
+@pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (1024, "p1=0")])
 def test_forced_2d_variants(n, force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
