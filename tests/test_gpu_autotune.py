@@ -55,8 +55,8 @@ def _child(code, env):
 @pytest.mark.parametrize("kw", [
     dict(n=4096, batch=64),
     dict(n=1 << 18, batch=8),
-    dict(rank=2, shape=(512, 512), batch=4),
-], ids=["n4096", "n2^18", "2d512"])
+    dict(rank=2, shape=(1024, 1024), batch=2),
+], ids=["n4096", "n2^18", "2d1024"])
 def test_autotune_then_plan(kw, tmp_path):
     env = dict(os.environ)
     env["DPFFT_TUNE_CACHE"] = str(tmp_path / "tune.json")
