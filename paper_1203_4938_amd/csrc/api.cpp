@@ -160,7 +160,7 @@ std::string LineStep::describe() const {
 
 // ---- runtime-radix steps ----
 void MixedStep::bind(const float2 *tables) {
-  a.twp = tables + twp_off;
+  a.tw2 = tables + tw2_off;
   if (tw4) {
     a.tw4_lo = tables + tw4_lo_off;
     a.tw4_hi = tables + tw4_hi_off;
@@ -492,9 +492,13 @@ std::unique_ptr<MixedStep> make_mixed(dpfft_plan_s *P, const char *name, int64_t
   s->tw4 = tw4;
   s->name = name;
   s->threads = C * s->a.mp.T;
+  s->a.mp.tw_lds = mixed_tile_elems(s->a.mp, map, omap);
   s->lds_bytes = mixed_lds_bytes(s->a.mp, map, omap);
   for (int sw = 0; sw < 4; ++sw) s->fn_sw[sw] = mixed_kernel(map, omap, tw4, sw);
-  s->twp_off = P->tables.add(stockham_table(s->a.mp.radix, s->a.mp.P));
+  std::vector<std::complex<double>> lo, hi;
+  fourstep_tables(L, s->a.mp.tw2_shift, lo, hi);
+  lo.insert(lo.end(), hi.begin(), hi.end());
+  s->tw2_off = P->tables.add(lo);
   s->a.scale = 1.0f;
   // dynamic LDS above the default 64 KB needs an explicit opt-in per function
   for (int sw = 0; sw < 4; ++sw)

@@ -18,8 +18,10 @@ struct MixedPlan {
   int32_t C;                  // lines per workgroup
   int32_t radix[kMaxPasses];
   int32_t ns[kMaxPasses];     // product of the earlier radices
+  int32_t tw2_shift;          // w_L^e = hi[e >> s] * lo[e & (2^s - 1)]
   int32_t pitch;              // LDS elements per line (ELEM_FAST layout)
   uint64_t codes;             // radix[p] in bits 5p..5p+4 (the device reads only this)
+  int32_t tw_lds;             // LDS element offset of the pass-twiddle table
 };
 
 struct MixedArgs {
@@ -28,8 +30,7 @@ struct MixedArgs {
   int64_t out_b, out_l, out_e;
   int64_t lines;             // lines per batch item
   int64_t tiles_per_batch;   // ceil(lines / C)
-  const float2 *twp;         // pass table: passes p >= 1 concatenated, entry
-                             // (r-1)*Ns + k = w_{Ns R}^{k r}
+  const float2 *tw2;         // 2^s lo entries, then ceil(L / 2^s) hi entries
   const float2 *tw4_lo;      // four-step twiddles of N (two-level)
   const float2 *tw4_hi;
   int32_t tw4_shift;
@@ -45,7 +46,8 @@ bool mixed_radices(int64_t L, MixedPlan *mp, int order = 0);
 // Host: the kernel instance for (map, omap, tw4, swap mode); nullptr if none.
 const void *mixed_kernel(int map, int omap, bool tw4, int sw);
 
-// LDS elements of the tile data of a workgroup, and its LDS bytes.
+// LDS elements of the tile data of a workgroup, and total LDS bytes (tile
+// data plus the pass-twiddle table that follows it).
 int mixed_tile_elems(const MixedPlan &mp, int map, int omap);
 int mixed_lds_bytes(const MixedPlan &mp, int map, int omap);
 

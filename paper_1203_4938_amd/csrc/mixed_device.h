@@ -42,12 +42,33 @@ __device__ __forceinline__ int midx_line(int C, int c, int pos) {
   return u + (u >> 4);
 }
 
-// Pass twiddles w_{Ns R}^{k r}, r = 1..R-1, multiplied into x[1..R-1]; `t`
-// points at this pass's part of the table (entry (r-1)*Ns + k).
+__device__ __forceinline__ cf tw2_lookup(const lcf *t, int shift, uint32_t e) {
+  const cf lo = ldc(t, e & ((1u << shift) - 1u));
+  const cf hi = ldc(t, (1u << shift) + (e >> shift));
+  return cmul(hi, lo);
+}
+
+// Pass twiddles w_L^{e1 r}, r = 1..R-1, into x[1..R-1] (multiplied in).  For
+// R = 8 and 16 only r = 1, 2, 3 and the multiples of 4 are looked up; the
+// others are products w^{4s} w^{l}, which halves the table reads.
 template <int R>
-__device__ __forceinline__ void apply_pass_twiddles(cf *x, const gcf *t, int NS, int k) {
+__device__ __forceinline__ void apply_pass_twiddles(cf *x, const lcf *t, int shift, uint32_t e1) {
+  if constexpr (R == 8 || R == 16) {
+    cf wl[4], w4[R / 4];
 #pragma unroll
-  for (int r = 1; r < R; ++r) x[r] = cmul(x[r], ldc(t, (r - 1) * NS + k));
+    for (int l = 1; l < 4; ++l) wl[l] = tw2_lookup(t, shift, e1 * (uint32_t)l);
+#pragma unroll
+    for (int s = 1; s < R / 4; ++s) w4[s] = tw2_lookup(t, shift, e1 * (uint32_t)(4 * s));
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const int s = r / 4, l = r % 4;
+      const cf w = s == 0 ? wl[l] : (l == 0 ? w4[s] : cmul(w4[s], wl[l]));
+      x[r] = cmul(x[r], w);
+    }
+  } else {
+#pragma unroll
+    for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw2_lookup(t, shift, e1 * (uint32_t)r));
+  }
 }
 
 __device__ __forceinline__ cf tw4_lookup_m(const MixedArgs &a, uint32_t e) {
@@ -60,14 +81,14 @@ __device__ __forceinline__ cf tw4_lookup_m(const MixedArgs &a, uint32_t e) {
 
 // One pass.  It is a separate (non-inlined) function per radix so that each
 // radix gets its own register allocation; its context travels as plain
-// scalars and address-space-qualified pointers.  `twp` is this pass's part of
-// the pass-twiddle table.
+// scalars and address-space-qualified pointers.  `tw2` is the two-level
+// table of w_L held in LDS.
 template <int MAP, int OMAP, bool TW4, int SW, int R>
 __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__restrict__ dst,
-                                        lcf *lds, const gcf *__restrict__ twp,
+                                        lcf *lds, const lcf *tw2,
                                         const gcf *__restrict__ tw4_lo,
                                         const gcf *__restrict__ tw4_hi, int L, int T, int C,
-                                        int pitch, int NS, int tw4_shift, int c,
+                                        int pitch, int NS, int tw2_shift, int tw4_shift, int c,
                                         int j, bool valid, bool first, bool last, int64_t in_e,
                                         int64_t out_e, int64_t line, float scale) {
   // The shape arguments arrive in VGPRs (this is a call); they are the same in
@@ -78,6 +99,7 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
   C = __builtin_amdgcn_readfirstlane(C);
   pitch = __builtin_amdgcn_readfirstlane(pitch);
   NS = __builtin_amdgcn_readfirstlane(NS);
+  tw2_shift = __builtin_amdgcn_readfirstlane(tw2_shift);
   tw4_shift = __builtin_amdgcn_readfirstlane(tw4_shift);
   first = __builtin_amdgcn_readfirstlane((int)first) != 0;
   last = __builtin_amdgcn_readfirstlane((int)last) != 0;
@@ -110,7 +132,10 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
       }
       v[q][r] = y;
     }
-    if (NS > 1) apply_pass_twiddles<R>(v[q], twp, NS, kq[q]);
+    if (NS > 1) {
+      const uint32_t step = (uint32_t)(L / (NS * R));
+      apply_pass_twiddles<R>(v[q], tw2, tw2_shift, (uint32_t)kq[q] * step);
+    }
     Dft<R>::run(v[q]);
   }
   if (!first) __syncthreads();  // every read of this pass precedes the in-place writes
@@ -159,13 +184,19 @@ struct TileLine {
 };
 
 struct LineShape {
-  int L, T, C, pitch, P;
+  int L, T, C, pitch, P, tw2_shift;
   uint64_t codes;
-  const cf *twp;  // pass-twiddle table of the radix sequence (global memory)
+  const cf *tw2;  // two-level table of w_L in global memory (copied to LDS per tile)
   const cf *tw4_lo, *tw4_hi;
   int tw4_shift;
   float scale;
+  int tw_lds;     // LDS element offset of the copied table (after the tile data)
 };
+
+// entries of the two-level table of w_L: 2^s lo entries and ceil(L / 2^s) hi
+__host__ __device__ inline int tw2_entries(int L, int shift) {
+  return (1 << shift) + (L + (1 << shift) - 1) / (1 << shift);
+}
 
 template <int MAP, int OMAP, bool TW4, int SW>
 __device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &t, cf *lds,
@@ -174,15 +205,19 @@ __device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &
     if (t.valid && t.j == 0) t.dst[0] = t.src[0];
     return;
   }
-  const cf *twp = sh.twp;  // part of the pass table of the current pass (p >= 1)
+  // pass twiddles to LDS; the barrier that ends the first pass publishes them
+  // before the second pass reads any
+  lcf *twl = as_lds(lds) + sh.tw_lds;
+  const int ntw = tw2_entries(sh.L, sh.tw2_shift);
+  for (int i = threadIdx.x; i < ntw; i += nthreads) stc(twl, i, sh.tw2[i]);
   int ns = 1;
   for (int p = 0; p < sh.P; ++p) {
     const bool first = p == 0, last = p == sh.P - 1;
     const int R = (int)((sh.codes >> (5 * p)) & 31u);
 #define PASS(RR)                                                                                 \
-  mixed_pass<MAP, OMAP, TW4, SW, RR>(as_glb(t.src), as_glb(t.dst), as_lds(lds), as_glb(twp),    \
+  mixed_pass<MAP, OMAP, TW4, SW, RR>(as_glb(t.src), as_glb(t.dst), as_lds(lds), twl,            \
                                      as_glb(sh.tw4_lo), as_glb(sh.tw4_hi), sh.L, sh.T, sh.C,      \
-                                     sh.pitch, ns, sh.tw4_shift, t.c, t.j, t.valid,               \
+                                     sh.pitch, ns, sh.tw2_shift, sh.tw4_shift, t.c, t.j, t.valid, \
                                      first, last, t.in_e, t.out_e, t.line, sh.scale)
     switch (R) {
       case 2: PASS(2); break;
@@ -194,7 +229,6 @@ __device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &
       default: PASS(16); break;
     }
 #undef PASS
-    if (p >= 1) twp += ns * (R - 1);
     ns *= R;
   }
   if (OMAP != MAP && t.valid2) {

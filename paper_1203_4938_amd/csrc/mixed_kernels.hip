@@ -7,8 +7,8 @@
 // of consecutive passes differ when the radix changes, every pass reads its
 // inputs from LDS (the first pass from HBM) and writes its outputs back to LDS
 // (the last pass to HBM), in place, with a barrier between the reads and the
-// writes.  Pass twiddles w_{Ns R}^{k r} come from a per-pass table made in FP64
-// on the host (one load per twiddle, through the caches).
+// writes.  Pass twiddles w_{Ns R}^{k r} = w_L^{k r L/(Ns R)} are rebuilt from a
+// two-level table of w_L made in FP64 on the host.
 #include "mixed_device.h"
 
 namespace dpfft {
@@ -22,8 +22,8 @@ __global__ void __launch_bounds__(1024) k_mixed(const cf *__restrict__ in, cf *_
   const uint32_t tile = (a.flags & F_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (int64_t)(tile - bb * a.tiles_per_batch) * mp.C;
-  LineShape sh{mp.L, mp.T, mp.C, mp.pitch, mp.P, mp.codes, a.twp,
-               a.tw4_lo, a.tw4_hi, a.tw4_shift, a.scale};
+  LineShape sh{mp.L, mp.T, mp.C, mp.pitch, mp.P, mp.tw2_shift, mp.codes, a.tw2,
+               a.tw4_lo, a.tw4_hi, a.tw4_shift, a.scale, mp.tw_lds};
   TileLine t;
   t.c = MAP == ELEM_FAST ? tid / mp.T : tid % mp.C;
   t.j = MAP == ELEM_FAST ? tid % mp.T : tid / mp.C;
@@ -84,6 +84,9 @@ bool mixed_radices(int64_t L, MixedPlan *mp, int order) {
     mp->codes |= (uint64_t)mp->radix[p] << (5 * p);
   }
   mp->T = (int32_t)((L + 15) / 16);
+  int lg = 0;
+  while ((int64_t(1) << lg) < L) ++lg;
+  mp->tw2_shift = (lg + 1) / 2;
   mp->pitch = (int32_t)(L + (L >> 4) + 1);
   return true;
 }
@@ -100,7 +103,7 @@ int mixed_tile_elems(const MixedPlan &mp, int map, int omap) {
 }
 
 int mixed_lds_bytes(const MixedPlan &mp, int map, int omap) {
-  return mixed_tile_elems(mp, map, omap) * (int)sizeof(cf);
+  return (mixed_tile_elems(mp, map, omap) + tw2_entries(mp.L, mp.tw2_shift)) * (int)sizeof(cf);
 }
 
 const void *mixed_kernel(int map, int omap, bool tw4, int sw) {

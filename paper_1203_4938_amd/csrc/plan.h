@@ -88,7 +88,7 @@ struct MixedStep : Step {
   int threads = 0;
   int lds_bytes = 0;
   int src = BUF_IN, dst = BUF_OUT;
-  size_t twp_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
+  size_t tw2_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
   bool first = false, last = false;
   float inv_scale = 1.0f;
   std::string name;

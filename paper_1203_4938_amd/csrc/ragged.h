@@ -21,10 +21,11 @@ enum : int32_t { RK_SINGLE = 0, RK_COLUMNS = 1, RK_ROWS = 2 };
 
 struct RaggedItem {
   int32_t kind, C, first, n1, n2;
-  int32_t L, P, T, pitch;  // line length of this item and its radix plan
+  int32_t tw_lds;      // LDS element offset of the pass-twiddle table (after the tile data)
+  int32_t L, P, T, pitch, tw2_shift;  // line length of this item and its radix plan
   int32_t tw4_shift;
   uint64_t codes;      // radices, 5 bits each
-  int64_t twp_off;     // pass-twiddle table of the radix sequence in the table buffer
+  int64_t tw2_off;     // two-level pass table of w_L in the table buffer
   int64_t off;         // RK_SINGLE: first index into sigoff; else: the signal's element offset
   int64_t ws_off;      // four-step intermediate of the signal (elements into the workspace)
   int64_t tw4_lo_off, tw4_hi_off;  // four-step twiddle tables of the signal

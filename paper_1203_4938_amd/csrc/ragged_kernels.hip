@@ -23,8 +23,8 @@ template <bool INV>
 __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__restrict__ out,
                                             const RaggedArgs &a, const RaggedItem &d, cf *lds) {
   const int tid = threadIdx.x;
-  LineShape sh{d.L, d.T, d.C, d.pitch, d.P, d.codes, a.tables + d.twp_off,
-               nullptr, nullptr, 0, 1.0f};
+  LineShape sh{d.L, d.T, d.C, d.pitch, d.P, d.tw2_shift, d.codes, a.tables + d.tw2_off,
+               nullptr, nullptr, 0, 1.0f, d.tw_lds};
   TileLine t;
   const bool in_tile = tid < d.C * d.T;
 

@@ -187,11 +187,15 @@ int64_t tile_lds(const MixedPlan &mp, int C, int map) {
   return u + (u >> 4) + 1;
 }
 
+int64_t tw_elems(const MixedPlan &mp) {
+  return (1 << mp.tw2_shift) + (mp.L + (1 << mp.tw2_shift) - 1) / (1 << mp.tw2_shift);
+}
+
 constexpr int64_t kBudget = kRaggedLdsBytes / (int64_t)sizeof(float2);
 
 // the largest length one ragged workgroup transforms in a single pass
 bool fits_single(const MixedPlan &mp) {
-  return mp.T <= kRaggedThreads && tile_lds(mp, 1, ELEM_FAST) <= kBudget;
+  return mp.T <= kRaggedThreads && tile_lds(mp, 1, ELEM_FAST) + tw_elems(mp) <= kBudget;
 }
 
 }  // namespace
@@ -221,7 +225,7 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
   // radix plan and pass-twiddle table of each line length, built once
   struct LineInfo {
     MixedPlan mp;
-    int64_t twp_off;
+    int64_t tw2_off;
   };
   std::map<int64_t, LineInfo> lines;
   auto line_of = [&](int64_t L) -> const LineInfo * {
@@ -229,19 +233,24 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
     if (it != lines.end()) return &it->second;
     MixedPlan mp{};
     if (!mixed_radices(L, &mp)) return nullptr;
-    LineInfo li{mp, (int64_t)P->tables.add(stockham_table(mp.radix, mp.P))};
+    std::vector<std::complex<double>> lo, hi;
+    fourstep_tables(L, mp.tw2_shift, lo, hi);
+    lo.insert(lo.end(), hi.begin(), hi.end());
+    LineInfo li{mp, (int64_t)P->tables.add(lo)};
     return &(lines[L] = li);
   };
-  auto item_for = [](int32_t kind, const LineInfo &li, int C) {
+  auto item_for = [](int32_t kind, const LineInfo &li, int C, int64_t tw_lds) {
     RaggedItem it{};
     it.kind = kind;
     it.C = C;
+    it.tw_lds = (int32_t)tw_lds;
     it.L = li.mp.L;
     it.P = li.mp.P;
     it.T = li.mp.T;
     it.pitch = li.mp.pitch;
+    it.tw2_shift = li.mp.tw2_shift;
     it.codes = li.mp.codes;
-    it.twp_off = li.twp_off;
+    it.tw2_off = li.tw2_off;
     return it;
   };
 
@@ -265,17 +274,17 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
       const LineInfo &li = *line_of(L);
       const MixedPlan &mp = li.mp;
       int C = std::max(1, kRaggedThreads / mp.T);
-      while (C > 1 && tile_lds(mp, C, ELEM_FAST) > kBudget) --C;
+      while (C > 1 && tile_lds(mp, C, ELEM_FAST) + tw_elems(mp) > kBudget) --C;
       const int first = (int)items.size();
       for (size_t s0 = 0; s0 < sigs.size(); s0 += C) {
         const int c = (int)std::min<size_t>(C, sigs.size() - s0);
         const int64_t data = tile_lds(mp, c, ELEM_FAST);
-        RaggedItem it = item_for(RK_SINGLE, li, c);
+        RaggedItem it = item_for(RK_SINGLE, li, c, data);
         it.off = (int64_t)sigoff.size();
         for (int k = 0; k < c; ++k) sigoff.push_back(P->roffsets[sigs[s0 + k]]);
         items.push_back(it);
         cost.push_back((int64_t)(c * L * lg(L)));
-        lds_need = std::max(lds_need, data);
+        lds_need = std::max(lds_need, data + tw_elems(mp));
       }
       st->ranges.push_back({first, (int)items.size() - first});
       ++nsingle_sizes;
@@ -289,9 +298,9 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
     if (!fits_single(m1) || !fits_single(m2))
       return fail(FFT_E_UNSUPPORTED, "ragged size too long for two passes: " + std::to_string(L));
     int CA = std::max(1, kRaggedThreads / m1.T), CB = std::max(1, kRaggedThreads / m2.T);
-    while (CA > 1 && tile_lds(m1, CA, LINE_FAST) > kBudget) --CA;
+    while (CA > 1 && tile_lds(m1, CA, LINE_FAST) + tw_elems(m1) > kBudget) --CA;
     auto rows_lds = [&](int c) { return std::max(tile_lds(m2, c, ELEM_FAST), tile_lds(m2, c, LINE_FAST)); };
-    while (CB > 1 && rows_lds(CB) > kBudget) --CB;
+    while (CB > 1 && rows_lds(CB) + tw_elems(m2) > kBudget) --CB;
     std::vector<std::complex<double>> lo, hi;
     int lgL = 0;
     while ((int64_t(1) << lgL) < L) ++lgL;
@@ -316,9 +325,9 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
       for (int64_t f = 0; f < n2; f += CA) {
         const int c = (int)std::min<int64_t>(CA, n2 - f);
         const int64_t data = tile_lds(m1, c, LINE_FAST);
-        items.push_back(big(item_for(RK_COLUMNS, *l1, c), s, ws, f));
+        items.push_back(big(item_for(RK_COLUMNS, *l1, c, data), s, ws, f));
         cost.push_back((int64_t)(c * n1 * lg(n1)));
-        lds_need = std::max(lds_need, data);
+        lds_need = std::max(lds_need, data + tw_elems(m1));
       }
       ws += L;
     }
@@ -328,9 +337,9 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
       for (int64_t f = 0; f < n1; f += CB) {
         const int c = (int)std::min<int64_t>(CB, n1 - f);
         const int64_t data = rows_lds(c);
-        items.push_back(big(item_for(RK_ROWS, *l2, c), sigs[k], ws_of[k], f));
+        items.push_back(big(item_for(RK_ROWS, *l2, c, data), sigs[k], ws_of[k], f));
         cost.push_back((int64_t)(c * n2 * lg(n2)));
-        lds_need = std::max(lds_need, data);
+        lds_need = std::max(lds_need, data + tw_elems(m2));
       }
     }
     st->ranges.push_back({first_rows, (int)items.size() - first_rows});

@@ -35,21 +35,6 @@ std::vector<std::complex<double>> stockham_table_pow2(int L) {
   return tab;
 }
 
-std::vector<std::complex<double>> stockham_table(const int32_t *radix, int P) {
-  std::vector<std::complex<double>> tab;
-  int64_t ns = 1;
-  for (int p = 0; p < P; ++p) {
-    const int R = radix[p];
-    if (p >= 1) {
-      for (int r = 1; r < R; ++r)
-        for (int64_t k = 0; k < ns; ++k) tab.push_back(omega(ns * R, k * r));
-    }
-    ns *= R;
-  }
-  if (tab.empty()) tab.push_back({1.0, 0.0});
-  return tab;
-}
-
 void fourstep_tables(int64_t N, int shift, std::vector<std::complex<double>> &lo,
                      std::vector<std::complex<double>> &hi) {
   const int64_t B = int64_t(1) << shift;

@@ -15,9 +15,6 @@ std::complex<double> omega(int64_t M, int64_t t);
 // for r = 1..R-1, k = 0..Ns-1, passes concatenated in order.
 std::vector<std::complex<double>> stockham_table_pow2(int L);
 
-// The same table for any radix sequence radix[0..P-1] (runtime-radix kernels).
-std::vector<std::complex<double>> stockham_table(const int32_t *radix, int P);
-
 // Two-level four-step table for length N: lo[l] = w_N^l (l < 2^shift),
 // hi[h] = w_N^{h 2^shift} (h < ceil(N / 2^shift)), so that
 // w_N^e = hi[e >> shift] * lo[e & (2^shift - 1)].
