@@ -145,15 +145,34 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
     const int b = j + T * q;
     const int k = kq[q];
     const int base = (b - k) * R + k;
+    // Four-step twiddles of the last pass: its outputs are k1 = b + r*NS, so
+    // w_N^{line k1} = A * B^r with A = w_N^{line b}, B = w_N^{line NS} (two
+    // table lookups per butterfly) and B^r from a product tree of depth <= 4.
+    cf tw[R];
+    if (TW4 && last) {
+      const uint32_t msk = (1u << tw4_shift) - 1u;
+      const uint32_t ea = (uint32_t)(line * b), eb = (uint32_t)(line * NS);
+      const cf A = cmul(ldc(tw4_hi, ea >> tw4_shift), ldc(tw4_lo, ea & msk));
+      const cf B = cmul(ldc(tw4_hi, eb >> tw4_shift), ldc(tw4_lo, eb & msk));
+      cf Bp[R];
+      Bp[0] = make_float2(1.0f, 0.0f);
+      if constexpr (R > 1) Bp[1] = B;
+#pragma unroll
+      for (int r = 2; r < R; ++r) {
+        int p2 = 1;
+        while (2 * p2 <= r) p2 *= 2;
+        Bp[r] = (r == p2) ? cmul(Bp[p2 / 2], Bp[p2 / 2]) : cmul(Bp[p2], Bp[r - p2]);
+      }
+      tw[0] = A;
+#pragma unroll
+      for (int r = 1; r < R; ++r) tw[r] = cmul(A, Bp[r]);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int pos = base + r * NS;
       cf y = v[q][r];
       if (last) {
-        if (TW4) {
-          const uint32_t e = (uint32_t)(line * pos);
-          y = cmul(y, cmul(ldc(tw4_hi, e >> tw4_shift), ldc(tw4_lo, e & ((1u << tw4_shift) - 1u))));
-        }
+        if (TW4) y = cmul(y, tw[r]);
         if (SW & 2) y = cswap(cscale(y, scale));
         if (OMAP == MAP) {
           stc(dst, (int64_t)pos * out_e, y);
