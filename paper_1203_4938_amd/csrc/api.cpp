@@ -139,10 +139,11 @@ bool LineStep::valid() const {
   // unit strides the kernel assumes, 32-bit in-line offsets, instances present
   const bool in_ok = k.map == ELEM_FAST ? a.in_e == 1 : a.in_l == 1;
   const bool out_ok = k.omap == ELEM_FAST ? a.out_e == 1 : a.out_l == 1;
-  // a tile's elements lie within 2^29 elements (4 GiB) of its first line
+  // a column tile's elements lie within 2^29 elements (32-bit byte offsets)
+  // of its first column; row tiles address each line from its own base
   const int64_t C = k.lines;
-  const int64_t span_in = (C - 1) * a.in_l + (int64_t)(L - 1) * a.in_e;
-  const int64_t span_out = (C - 1) * a.out_l + (int64_t)(L - 1) * a.out_e;
+  const int64_t span_in = k.map == LINE_FAST ? (C - 1) + (int64_t)(L - 1) * a.in_e : 0;
+  const int64_t span_out = k.omap == LINE_FAST ? (C - 1) + (int64_t)(L - 1) * a.out_e : 0;
   const bool off_ok = span_in < (int64_t(1) << 29) && span_out < (int64_t(1) << 29);
   return in_ok && out_ok && off_ok && k.fn_sw[0] && k.fn_sw[inverse_sw()];
 }

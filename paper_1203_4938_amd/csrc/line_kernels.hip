@@ -198,10 +198,11 @@ __device__ __forceinline__ void tw4_apply(cf (&v)[E], const LineArgs &a, uint32_
   tw4_apply_ab<E>(v, tw4_lookup(a, n2 * (uint32_t)j), tw4_lookup(a, n2 * (uint32_t)T));
 }
 
-// Global accesses of a tile: a base address that is the same for the whole
-// workgroup plus a 32-bit byte offset per lane (the plan keeps every tile's
-// span below 4 GiB), so the loads and stores take the scalar-base form with a
-// single offset VGPR each.
+// Global accesses of a column tile: a base address that is the same for the
+// whole workgroup plus a 32-bit byte offset per lane (the plan keeps a column
+// tile's span below 4 GiB), so the loads and stores take the scalar-base form
+// with a single offset VGPR each.  Row tiles address each line from its own
+// 64-bit base: their lines may be any distance apart.
 __device__ __forceinline__ cf ldg(const cf *base, uint32_t idx) {
   return *(const cf *)((const char *)base + (idx << 3));
 }
@@ -244,12 +245,12 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 
   cf v[E];
   if (valid) {
-    const cf *tin = in + bb * a.in_b + line0 * a.in_l;
     if constexpr (MAP == ELEM_FAST) {
-      const uint32_t o = (uint32_t)c * (uint32_t)a.in_l + (uint32_t)j;
+      const cf *src = in + bb * a.in_b + (line0 + c) * a.in_l + j;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m));
+      for (int m = 0; m < E; ++m) v[m] = src[T * m];
     } else {
+      const cf *tin = in + bb * a.in_b + line0;
       const uint32_t es = (uint32_t)a.in_e;
       const uint32_t o = (uint32_t)c + (uint32_t)j * es;
 #pragma unroll
@@ -288,12 +289,12 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
     }
-    cf *tout = out + bb * a.out_b + line0 * a.out_l;
     if constexpr (OMAP == ELEM_FAST) {
-      const uint32_t o = (uint32_t)c2 * (uint32_t)a.out_l + (uint32_t)j2;
+      cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
 #pragma unroll
-      for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m), v[m]);
+      for (int m = 0; m < E; ++m) dst[T * m] = v[m];
     } else {
+      cf *tout = out + bb * a.out_b + line0;
       const uint32_t es = (uint32_t)a.out_e;
       const uint32_t o = (uint32_t)c2 + (uint32_t)j2 * es;
 #pragma unroll
@@ -317,12 +318,12 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (tile - bb * a.tiles_per_batch) * C;
   if (line0 + c < a.lines) {
-    const cf *tin = in + bb * a.in_b + line0 * a.in_l;
     if constexpr (MAP == ELEM_FAST) {
-      const uint32_t o = (uint32_t)c * (uint32_t)a.in_l + (uint32_t)j;
+      const cf *src = in + bb * a.in_b + (line0 + c) * a.in_l + j;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m));
+      for (int m = 0; m < E; ++m) v[m] = src[T * m];
     } else {
+      const cf *tin = in + bb * a.in_b + line0;
       const uint32_t es = (uint32_t)a.in_e;
       const uint32_t o = (uint32_t)c + (uint32_t)j * es;
 #pragma unroll
@@ -442,12 +443,12 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
       }
-      cf *tout = out + bb * a.out_b + line0 * a.out_l;
       if constexpr (OMAP == ELEM_FAST) {
-        const uint32_t o = (uint32_t)c2 * (uint32_t)a.out_l + (uint32_t)j2;
+        cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
 #pragma unroll
-        for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m), v[m]);
+        for (int m = 0; m < E; ++m) dst[T * m] = v[m];
       } else {
+        cf *tout = out + bb * a.out_b + line0;
         const uint32_t es = (uint32_t)a.out_e;
         const uint32_t o = (uint32_t)c2 + (uint32_t)j2 * es;
 #pragma unroll

@@ -133,6 +133,28 @@ def test_inplace_and_strided_dist():
     assert np.array_equal(yh[:, n:], x[:, n:])
 
 
+def test_signals_more_than_4gib_apart():
+    """Rows of one tile lie 2 GiB apart (dist = 2^28 complex64): every line is
+    addressed from its own 64-bit base."""
+    import torch
+    dp = _dp()
+    n, b, dist = 1024, 3, 1 << 28
+    x = synth.uniform_complex(synth.BASE_SEED + 31, n, b)
+    xd = torch.zeros((b - 1) * dist + n, dtype=torch.complex64, device="cuda")
+    for i in range(b):
+        xd[i * dist:i * dist + n] = torch.from_numpy(x[i]).to("cuda")
+    p = dp.Plan(n, b, dist=dist)
+    say("[far apart]", p.describe().replace("\n", " | "))
+    for inv in (False, True):
+        y = run_plan(p, xd, inverse=inv)
+        got = np.stack([y[i * dist:i * dist + n].cpu().numpy() for i in range(b)])
+        e = max_rel(got, oracle.fft_batch(x, inverse=inv))
+        say(f"   inverse={inv} max rel L2 = {e:.3e}")
+        assert e <= TOL_FP32
+    del xd, y
+    torch.cuda.empty_cache()
+
+
 def test_exec_rejects_bad_arguments():
     dp = _dp()
     import torch
