@@ -117,3 +117,12 @@ def test_autotune_without_device_fails_cleanly():
     d, k = dp.make_desc(65536, 8, precision="fp16")
     st, msg = dp.fft_autotune(d)
     assert st == dp.FFT_OK and "nothing to tune" in msg
+
+
+def test_plans_with_signals_far_apart():
+    """Signals 2 GiB apart keep the multi-line row kernels (each line has its
+    own base address); only column tiles need a span below 4 GiB."""
+    t = _dry(n=1024, batch=3, dist=1 << 28)
+    assert "variant=single-pass" in t and "C=4" in t
+    t = _dry(n=1 << 16, batch=2, dist=1 << 28)
+    assert "four-step" in t
