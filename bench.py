@@ -168,8 +168,8 @@ def build_c5(dp, torch, synth, dev):
         items.append(Item(dp, torch, name, p, x.clone(), torch.empty_like(x), fl,
                           16.0 * float(sizes.sum()), compare=cmp))
     return items, {"workload": "c5: ragged batch of 10000 7-smooth sizes in [64, 65536], "
-                               "log-uniform; the step is the persistent two-launch queue in a HIP "
-                               "graph; the same queue without the graph and one launch per "
+                               "log-uniform; the step is the two persistent launches in a HIP "
+                               "graph; the same launches without the graph and one launch per "
                                "distinct length are timed after it for comparison"}
 
 

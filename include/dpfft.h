@@ -76,7 +76,7 @@ typedef enum {
 #define FFT_F_NO_AUTOTUNE 2u /* ignore the autotune cache, use the heuristic plan */
 #define FFT_F_GRAPH 4u       /* ragged plans: replay the launches as a HIP graph */
 #define FFT_F_PER_SIZE 8u    /* ragged plans: one launch per distinct length instead of
-                                the persistent queue (the comparison baseline) */
+                                the two persistent launches (the comparison baseline) */
 
 typedef struct {
   int32_t rank;     /* 1: batched 1D signals; 2: batched images */
@@ -139,8 +139,9 @@ fft_status_t fft_exec_steps(fft_plan_t plan, const void *in, void *out, int dire
 fft_status_t fft_plan_dry(const fft_desc_t *desc, char *buf, size_t len);
 
 /* Autotune: build every compiled kernel variant the planner could use for
- * *desc (tile widths, persistent form, radix order of non-power-of-two
- * lengths), time `reps` forward executions of each on `hip_stream` with HIP
+ * *desc (tile widths, persistent form, the four-step split and chunking of
+ * power-of-two lengths, radix order of non-power-of-two lengths), time `reps`
+ * forward executions of each on `hip_stream` with HIP
  * events on scratch buffers it allocates and frees, and record the fastest
  * for (architecture, shape, batch rounded down to a power of two, precision).
  * Later fft_plan calls for that key use it unless FFT_F_NO_AUTOTUNE is set.

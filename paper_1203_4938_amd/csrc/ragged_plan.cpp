@@ -89,7 +89,7 @@ struct RaggedStep : Step {
 
   unsigned grid_of(const RaggedArgs &r) const { return (unsigned)std::min(resident, r.nitems); }
 
-  hipError_t launch_queue(const ExecCtx &ctx) const {
+  hipError_t launch_persistent(const ExecCtx &ctx) const {
     RaggedArgs r = args_for(ctx);
     hipError_t e = hipSuccess;
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
@@ -161,7 +161,7 @@ struct RaggedStep : Step {
   hipError_t launch(const ExecCtx &ctx) const override {
     if (nitems == 0) return hipSuccess;
     if (per_size) return launch_direct(ctx);
-    return graph ? launch_graph(ctx) : launch_queue(ctx);
+    return graph ? launch_graph(ctx) : launch_persistent(ctx);
   }
 
   std::string describe() const override { return summary; }
