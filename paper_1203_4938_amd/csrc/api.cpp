@@ -151,7 +151,6 @@ bool LineStep::valid() const {
 std::string LineStep::describe() const {
   std::ostringstream o;
   o << name << ": L=" << L << " C=" << k.lines << " threads=" << k.threads;
-  if (k.split_exchange) o << " split-exchange";
   if (k.persistent)
     o << " persistent tiles=" << a.ntiles << " grid<=" << resident;
   else
@@ -297,8 +296,6 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
     if (ov.c[step] < 0 && k.lines > cmax) continue;
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
     if (ov.t[step] >= 0 && k.threads != ov.t[step]) continue;
-    if (ov.x[step] >= 0 && (int)k.split_exchange != ov.x[step]) continue;
-    if (ov.x[step] < 0 && k.split_exchange) continue;  // opt-in until measured
     const bool pf_default = k.persistent && k.threads == 1024 && map == omap;
     if (ov.p[step] < 0 && k.persistent && !pf_default) continue;
     if (k.threads > 1024) continue;

@@ -45,7 +45,6 @@ Override parse_override(const std::string &text) {
       if (kind == 'c') o.c[idx] = val;
       if (kind == 'p') o.p[idx] = val;
       if (kind == 't') o.t[idx] = val;
-      if (kind == 'x') o.x[idx] = val;
     }
   }
   o.text = text;

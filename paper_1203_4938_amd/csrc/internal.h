@@ -25,7 +25,6 @@ int resident_for(int lds_bytes, int threads);
 //   c<i>=<C>   lines (rows or columns) per workgroup
 //   p<i>=0|1   persistent variant off / on
 //   t<i>=<T>   threads per workgroup (instances differing in elements per thread)
-//   x<i>=0|1   split-exchange variant (half-size LDS buffer) off / on
 //   o=0|1      radix order of runtime-radix lengths: powers of two first / odd first
 //   k=<n>      two-pass plans: transforms per chunk (0 = the whole batch at once)
 //   s=<n>      power-of-two four-step: log2 of the column length N1
@@ -35,7 +34,6 @@ struct Override {
   int c[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int p[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int t[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-  int x[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int order = -1;
   int chunk = -1;
   int split = -1;

@@ -84,7 +84,6 @@ struct KernelInfo {
   int lds_bytes = 0;    // static LDS of the instance
   int map = 0, omap = 0;
   bool persistent = false;  // loops over tiles; launch at most one grid of resident workgroups
-  bool split_exchange = false;  // re/im exchanges through a half-size LDS buffer
 };
 
 // Power-of-two line kernel with compile-time length L and C lines per

@@ -57,25 +57,6 @@ __device__ __forceinline__ void lds_exchange(cf (&v)[E], cf *lds, WPos wpos, RPo
   if constexpr (TAIL) __syncthreads();
 }
 
-// The same exchange through a float buffer of half the size: real parts
-// first, then imaginary parts (two more barriers), for the instances whose
-// full-size buffer would leave room for only one workgroup per CU.
-template <int E, bool TAIL, class WPos, class RPos>
-__device__ __forceinline__ void lds_exchange(cf (&v)[E], float *lds, WPos wpos, RPos rpos) {
-#pragma unroll
-  for (int m = 0; m < E; ++m) lds[wpos(m)] = v[m].x;
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < E; ++m) v[m].x = lds[rpos(m)];
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < E; ++m) lds[wpos(m)] = v[m].y;
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < E; ++m) v[m].y = lds[rpos(m)];
-  if constexpr (TAIL) __syncthreads();
-}
-
 // One Stockham pass on the registers of thread (c, j).  Butterfly q of the
 // thread is b = j + T*q; its inputs are v[q + r*QN] and its outputs are left
 // in the same registers, then (unless this is the last pass) exchanged so that
@@ -110,8 +91,8 @@ struct TwLds2 {
   }
 };
 
-template <int L, int EPT, int C, int MAP, int P, class TW, class LT>
-__device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], LT *lds, const TW &tw, int c,
+template <int L, int EPT, int C, int MAP, int P, class TW>
+__device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
                                               int j) {
   using G = P2<L, EPT>;
   constexpr int E = G::E, T = G::T, R = G::radix(P), NS = G::ns(P), QN = E / R;
@@ -145,8 +126,8 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], LT *lds,
   }
 }
 
-template <int L, int EPT, int C, int MAP, class TW, class LT, int... P>
-__device__ __forceinline__ void all_passes(cf (&v)[(P2<L, EPT>::E)], LT *lds, const TW &tw, int c,
+template <int L, int EPT, int C, int MAP, class TW, int... P>
+__device__ __forceinline__ void all_passes(cf (&v)[(P2<L, EPT>::E)], cf *lds, const TW &tw, int c,
                                            int j, std::integer_sequence<int, P...>) {
   (stockham_pass<L, EPT, C, MAP, P>(v, lds, tw, c, j), ...);
 }
@@ -243,20 +224,15 @@ constexpr int lds_pairs() {
 //
 // Addressing: an ELEM_FAST side has unit element stride (x_e == 1) and a
 // LINE_FAST side has unit line stride (x_l == 1); the plan guarantees it.
-//
-// XS: exchanges go through a float buffer of half the size (re, then im), and
-// the instance asks for eight waves per SIMD (at most 64 VGPRs), so that two
-// 1024-thread workgroups fit one CU.
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, bool XS>
-__global__ void __launch_bounds__(C * (P2<L, EPT>::T), XS ? 8 : 1)
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
+__global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
   static_assert(C * G::T <= 1024, "a workgroup holds at most 1024 threads");
   constexpr int E = G::E, T = G::T;
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NP = lds_pairs<L, C, MAP, OMAP>();
-  using LT = std::conditional_t<XS, float, cf>;
-  __shared__ __align__(16) LT lds[NP > 0 ? NP : 1];
+  __shared__ __align__(16) cf lds[NP > 0 ? NP : 1];
 
   const int tid = threadIdx.x;
   int c, j;
@@ -376,12 +352,11 @@ constexpr int pf_tw_entries() {
   }
 }
 
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, bool XS>
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
 __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines_pf(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
   static_assert(C * G::T <= 1024, "a workgroup holds at most 1024 threads");
-  static_assert(!XS, "persistent instances exchange full complex values");
   constexpr int E = G::E, T = G::T, NT = C * G::T;
   constexpr int S = tw2_shift(G::LG), NLO = 1 << S, NHI = (L >> S) > 0 ? (L >> S) : 1;
   using LO = Lds<L, C, OMAP, kPadShift>;
@@ -499,15 +474,14 @@ struct LineEntry {
   int threads;
   int lds;
   bool pf;
-  bool xs;
 };
 
-#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT, KXS>
+#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT>
 #define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
-            (KXS ? 4 : 8) * lds_pairs<L_, C_, M_, O_>() +                           \
+            (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
                 (KPF ? (int)sizeof(cf) * pf_tw_entries<L_, C_, M_, O_>() : 0),      \
-            KPF, KXS}
+            KPF}
 
 // rows: forward, inverse single pass (swap in+out), 2D row pass inverse (swap in)
 #define ROW(L_, C_)                                                                          \
@@ -530,7 +504,6 @@ struct LineEntry {
 #define KFN k_lines
 #define KPF false
 #define KEPT 16
-#define KXS false
 static const LineEntry kLineTable[] = {
     // batched rows (single-pass transforms, 2D row pass)
     ROW(1, 256), ROW(2, 256), ROW(4, 256), ROW(8, 256), ROW(16, 256), ROW(32, 128),
@@ -546,20 +519,12 @@ static const LineEntry kLineTable[] = {
     ROWT(64, 16), ROWT(128, 16), ROWT(256, 16), ROWT(256, 32), ROWT(512, 16),
     ROWT(1024, 16), ROWT(1024, 8), ROWT(2048, 4), ROWT(2048, 8), ROWT(4096, 4),
 };
-#undef KXS
-#define KXS true
-// half-size exchange buffers: two 1024-thread workgroups per CU
-static const LineEntry kLineTableXs[] = {
-    ROW(16384, 1), COL(2048, 8), COLTW(2048, 8), ROWT(2048, 8),
-};
-#undef KXS
 #undef KFN
 #undef KPF
 #undef KEPT
 #define KFN k_lines_pf
 #define KPF true
 #define KEPT 16
-#define KXS false
 // persistent instances, 16 elements per thread.  Transposed-row tiles have
 // none (with the re-tiling exchange the two register sets do not fit the
 // 1024-thread budget without spills), nor do the 2048-point column tiles,
@@ -570,7 +535,6 @@ static const LineEntry kLineTablePf[] = {
 #undef KFN
 #undef KPF
 #undef KEPT
-#undef KXS
 
 static void fill(const LineEntry &e, KernelInfo *out) {
   for (int i = 0; i < 4; ++i) out->fn_sw[i] = e.fn[i];
@@ -581,13 +545,11 @@ static void fill(const LineEntry &e, KernelInfo *out) {
   out->map = e.map;
   out->omap = e.omap;
   out->persistent = e.pf;
-  out->split_exchange = e.xs;
 }
 
 template <class F>
 static void for_each_entry(F f) {
   for (const auto &e : kLineTable) f(e);
-  for (const auto &e : kLineTableXs) f(e);
   for (const auto &e : kLineTablePf) f(e);
 }
 

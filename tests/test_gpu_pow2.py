@@ -186,8 +186,6 @@ VARIANTS = [
     (1 << 20, 3, "p0=1"), (1 << 20, 3, "p0=0"),
     # other four-step splits of 2^22 (1024 x 4096, 4096 x 1024)
     (1 << 22, 1, "s=10"), (1 << 22, 1, "s=12"),
-    # half-size exchange buffers, two 1024-thread workgroups per CU
-    (16384, 9, "x0=1"), (1 << 22, 1, "x0=1 x1=1"),
 ]
 
 
@@ -208,7 +206,7 @@ def test_forced_variants(n, batch, force, monkeypatch):
         assert e <= TOL_FP32, (n, force, inv, e)
 
 
-@pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (1024, "p1=0"), (2048, "x1=1")])
+@pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (1024, "p1=0")])
 def test_forced_2d_variants(n, force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
