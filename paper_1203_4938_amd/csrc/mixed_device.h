@@ -114,23 +114,36 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
   cf v[QM][R];
   bool act[QM];
   int kq[QM];
+  // all loads of the pass first (one branch on the source for the whole
+  // pass), so every butterfly's data is in flight before the first one is
+  // computed
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
     const int b = j + T * q;
     act[q] = valid && b < M;
     kq[q] = NS > 1 ? b % NS : 0;
-    if (!act[q]) continue;
+  }
+  if (first) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int pos = b + r * M;
-      cf y;
-      if (first) {
-        y = ldc(src, (int64_t)pos * in_e);
-        if (SW & 1) y = cswap(y);
-      } else {
-        y = ldc(lds, li(MAP, pos));
-      }
-      v[q][r] = y;
+    for (int q = 0; q < QM; ++q) {
+      if (!act[q]) continue;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = ldc(src, (int64_t)(j + T * q + r * M) * in_e);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      if (!act[q]) continue;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = ldc(lds, li(MAP, j + T * q + r * M));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    if (!act[q]) continue;
+    if ((SW & 1) && first) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = cswap(v[q][r]);
     }
     if (NS > 1) {
       const uint32_t step = (uint32_t)(L / (NS * R));
