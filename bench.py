@@ -236,8 +236,8 @@ def copy_probe(torch, dev, reps=10):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(batched transforms shard by signal with no communication; see the design notes)",
+        print(f"bench.py: the benchmark runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (batched transforms would shard by signal with no communication)",
               file=sys.stderr)
         sys.exit(2)
     import torch
