@@ -191,10 +191,11 @@ void MixedStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_
 }
 
 bool MixedStep::valid() const {
-  // element strides travel to the passes as 32-bit values
+  // in-line element offsets travel to the passes as 32-bit values
+  const int64_t span = (int64_t)(a.mp.L - 1) * std::max(a.in_e, a.out_e);
   return fn_sw[0] && fn_sw[inverse_sw()] && threads > 0 && threads <= 1024 &&
          threads == a.mp.C * a.mp.T && lds_bytes <= kLdsBytes && a.mp.T * 16 >= a.mp.L &&
-         a.in_e < (int64_t(1) << 31) && a.out_e < (int64_t(1) << 31);
+         span < (int64_t(1) << 31);
 }
 
 std::string MixedStep::describe() const {

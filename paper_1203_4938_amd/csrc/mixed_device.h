@@ -19,13 +19,13 @@ __device__ __forceinline__ lcf *as_lds(cf *p) { return (lcf *)p; }
 __device__ __forceinline__ gcf *as_glb(cf *p) { return (gcf *)p; }
 __device__ __forceinline__ const gcf *as_glb(const cf *p) { return (const gcf *)p; }
 
-template <class P>
-__device__ __forceinline__ cf ldc(P *p, int64_t i) {
+template <class P, class I>
+__device__ __forceinline__ cf ldc(P *p, I i) {
   const v2f v = p[i];
   return make_float2(v.x, v.y);
 }
-template <class P>
-__device__ __forceinline__ void stc(P *p, int64_t i, cf y) {
+template <class P, class I>
+__device__ __forceinline__ void stc(P *p, I i, cf y) {
   v2f v;
   v.x = y.x;
   v.y = y.y;
@@ -103,8 +103,10 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
   tw4_shift = __builtin_amdgcn_readfirstlane(tw4_shift);
   first = __builtin_amdgcn_readfirstlane((int)first) != 0;
   last = __builtin_amdgcn_readfirstlane((int)last) != 0;
-  in_e = (int64_t)__builtin_amdgcn_readfirstlane((int)in_e);
-  out_e = (int64_t)__builtin_amdgcn_readfirstlane((int)out_e);
+  // element strides and in-line offsets fit 32 bits (checked by the planner:
+  // (L - 1) * stride < 2^31), so the per-element index math stays 32-bit
+  const uint32_t ie = (uint32_t)__builtin_amdgcn_readfirstlane((int)in_e);
+  const uint32_t oe = (uint32_t)__builtin_amdgcn_readfirstlane((int)out_e);
   scale = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(scale)));
   const int M = L / R;
   constexpr int QM = (16 + R - 1) / R;  // butterflies per thread (T >= L/16)
@@ -128,7 +130,7 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
     for (int q = 0; q < QM; ++q) {
       if (!act[q]) continue;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = ldc(src, (int64_t)(j + T * q + r * M) * in_e);
+      for (int r = 0; r < R; ++r) v[q][r] = ldc(src, (uint32_t)(j + T * q + r * M) * ie);
     }
   } else {
 #pragma unroll
@@ -164,7 +166,7 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
     cf tw[R];
     if (TW4 && last) {
       const uint32_t msk = (1u << tw4_shift) - 1u;
-      const uint32_t ea = (uint32_t)(line * b), eb = (uint32_t)(line * NS);
+      const uint32_t ea = (uint32_t)line * (uint32_t)b, eb = (uint32_t)line * (uint32_t)NS;
       const cf A = cmul(ldc(tw4_hi, ea >> tw4_shift), ldc(tw4_lo, ea & msk));
       const cf B = cmul(ldc(tw4_hi, eb >> tw4_shift), ldc(tw4_lo, eb & msk));
       cf Bp[R];
@@ -188,7 +190,7 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
         if (TW4) y = cmul(y, tw[r]);
         if (SW & 2) y = cswap(cscale(y, scale));
         if (OMAP == MAP) {
-          stc(dst, (int64_t)pos * out_e, y);
+          stc(dst, (uint32_t)pos * oe, y);
           continue;
         }
         stc(lds, li(OMAP, pos), y);
