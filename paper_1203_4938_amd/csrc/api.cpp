@@ -277,14 +277,12 @@ Override read_override() {
 // Workgroups of a persistent instance that stay resident on the device.
 int resident_workgroups(const KernelInfo &k) { return resident_for(k.lds_bytes, k.threads); }
 
-// Heuristic choice among the compiled instances of a line kernel: the most
-// resident waves per CU that the 160 KB LDS allows (counted up to 16), then
-// for row tiles the smaller tile (more workgroups to overlap), for column
-// tiles the wider tile (longer contiguous segments).  Persistent instances are
-// taken by default where a single 1024-thread workgroup fills the CU's LDS
-// (rows of 16384 points, 1024-point column tiles): there the prefetch of the
-// next tile is the only overlap of memory and compute the CU gets.  Elsewhere
-// they are opt-in.
+// Heuristic choice among the compiled instances of a line kernel: an instance
+// the registry marks as the measured default of its shape wins; otherwise the
+// most resident waves per CU that the 160 KB LDS allows (counted up to 16),
+// then for row tiles the smaller tile (more workgroups to overlap), for column
+// tiles the wider tile (longer contiguous segments).  Other persistent
+// instances are opt-in (override or tuner).
 bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const Override &ov,
                  KernelInfo *out) {
   KernelInfo cand[32];
@@ -297,15 +295,14 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
     if (ov.c[step] < 0 && k.lines > cmax) continue;
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
     if (ov.t[step] >= 0 && k.threads != ov.t[step]) continue;
-    const bool pf_default = k.persistent && k.threads == 1024 && map == omap;
-    if (ov.p[step] < 0 && k.persistent && !pf_default) continue;
+    if (ov.p[step] < 0 && k.persistent && !k.preferred) continue;
     if (k.threads > 1024) continue;
     int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 64;
     int by_thr = 2048 / k.threads;
     int wg = std::min(by_lds, by_thr);
     double waves = wg * (k.threads / 64.0);
     double tie = (map == LINE_FAST || omap == LINE_FAST) ? k.lines : 1.0 / k.lines;
-    double score = std::min(waves, 16.0) * 1000 + tie * 10 + (pf_default ? 1 : 0);
+    double score = std::min(waves, 16.0) * 1000 + tie * 10 + (k.preferred ? 1e6 : 0);
     if (score > best) {
       best = score;
       *out = k;

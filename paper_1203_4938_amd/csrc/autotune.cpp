@@ -165,15 +165,18 @@ std::vector<std::string> candidates(const fft_desc_t *d) {
     int n = std::min(32, list_line_kernels(L, map, omap, tw4, k, 32));
     std::vector<std::string> v;
     for (int i = 0; i < n; ++i)
-      if (k[i].threads <= 1024) v.push_back(std::to_string(k[i].lines) + " " + std::to_string((int)k[i].persistent));
+      if (k[i].threads <= 1024)
+        v.push_back(std::to_string(k[i].lines) + " " + std::to_string((int)k[i].persistent) + " " +
+                    std::to_string(k[i].threads));
     return v;
   };
-  auto enc = [](int step, const std::string &cp) {
-    std::istringstream in(cp);
-    int c, p;
-    in >> c >> p;
-    return "c" + std::to_string(step) + "=" + std::to_string(c) + " p" + std::to_string(step) + "=" +
-           std::to_string(p);
+  auto enc = [](int step, const std::string &cpt) {
+    std::istringstream in(cpt);
+    int c, p, t;
+    in >> c >> p >> t;
+    const std::string i = std::to_string(step);
+    return "c" + i + "=" + std::to_string(c) + " p" + i + "=" + std::to_string(p) + " t" + i + "=" +
+           std::to_string(t);
   };
   // two-pass plans: chunk sizes keeping one chunk's intermediate within 64,
   // 128 or 256 MiB (the memory-side cache holds 256 MB)

@@ -1,5 +1,5 @@
 // Device building blocks for the gfx950 FFT kernels: complex arithmetic and
-// in-register DFTs of radix 2, 3, 4, 5, 7, 8 and 16.
+// in-register DFTs of radix 2, 3, 4, 5, 7, 8, 16 and 32.
 //
 // Every DFT here is the forward transform X[k] = sum_j x[j] w_R^{jk} with
 // w_R = exp(-2 pi i / R), computed in place in natural order.  The inverse
@@ -71,6 +71,32 @@ __device__ __forceinline__ cf mulw16(cf x) {
   }
 }
 
+// cos and sin of 2*pi*e/32 for the odd e (the even ones are kCos16/kSin16)
+__device__ constexpr float kCos32Odd[16] = {
+    0.980785280403230449f,  0.831469612302545237f,  0.555570233019602225f,  0.195090322016128268f,
+    -0.195090322016128268f, -0.555570233019602225f, -0.831469612302545237f, -0.980785280403230449f,
+    -0.980785280403230449f, -0.831469612302545237f, -0.555570233019602225f, -0.195090322016128268f,
+    0.195090322016128268f,  0.555570233019602225f,  0.831469612302545237f,  0.980785280403230449f};
+__device__ constexpr float kSin32Odd[16] = {
+    0.195090322016128268f,  0.555570233019602225f,  0.831469612302545237f,  0.980785280403230449f,
+    0.980785280403230449f,  0.831469612302545237f,  0.555570233019602225f,  0.195090322016128268f,
+    -0.195090322016128268f, -0.555570233019602225f, -0.831469612302545237f, -0.980785280403230449f,
+    -0.980785280403230449f, -0.831469612302545237f, -0.555570233019602225f, -0.195090322016128268f};
+
+// x * w_R^E for R a divisor of 32: even multiples of 2pi/32 go to mulw16,
+// odd ones are a constant complex product (entry (e-1)/2 of the odd table).
+template <int R, int E>
+__device__ __forceinline__ cf mulw32(cf x) {
+  static_assert(32 % R == 0, "radix must divide 32");
+  constexpr int e = ((E % R) + R) % R * (32 / R);  // exponent in units of 2pi/32
+  if constexpr (e % 2 == 0) {
+    return mulw16<16, e / 2>(x);
+  } else {
+    constexpr float c = kCos32Odd[(e - 1) / 2], s = kSin32Odd[(e - 1) / 2];  // w = c - i s
+    return make_float2(x.x * c + x.y * s, x.y * c - x.x * s);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // power-of-two DFTs
 // ---------------------------------------------------------------------------
@@ -110,7 +136,10 @@ __device__ __forceinline__ void twiddle_row(cf *b) {
   // b[k1] *= w_{R1 R2}^{N2 k1} for k1 = 1..R1-1 (compile-time unrolled)
   if constexpr (N2 > 0) {
     [&]<int... K>(std::integer_sequence<int, K...>) {
-      ((b[K] = mulw16<R1 * R2, N2 * K>(b[K])), ...);
+      if constexpr (16 % (R1 * R2) == 0)
+        ((b[K] = mulw16<R1 * R2, N2 * K>(b[K])), ...);
+      else
+        ((b[K] = mulw32<R1 * R2, N2 * K>(b[K])), ...);
     }(std::make_integer_sequence<int, R1>{});
   }
 }
@@ -145,6 +174,9 @@ template <> struct Dft<8> {
 };
 template <> struct Dft<16> {
   __device__ __forceinline__ static void run(cf *a) { dft_two_factor<4, 4>(a); }
+};
+template <> struct Dft<32> {
+  __device__ __forceinline__ static void run(cf *a) { dft_two_factor<8, 4>(a); }
 };
 
 // ---------------------------------------------------------------------------

@@ -35,8 +35,9 @@ struct LineArgs {
 
 // Radix plan of the power-of-two line kernels, shared by the device code and
 // the host twiddle generator.  E elements per thread (EPT, or L if smaller;
-// a multiple of every radix), T threads per line,
-// NP passes: radix 16 first, then one radix 2/4/8 remainder pass.
+// a multiple of every radix), T threads per line.  With 16 elements per
+// thread: radix-16 passes, then one radix 2/4/8 remainder pass; with 32:
+// radix-32 passes, then one radix 2/4/8/16 remainder pass.
 template <int L, int EPT = 16> struct P2 {
   static constexpr int lg() {
     int k = 0;
@@ -44,10 +45,11 @@ template <int L, int EPT = 16> struct P2 {
     return k;
   }
   static constexpr int LG = lg();
+  static constexpr int RB = EPT >= 32 ? 5 : 4;  // log2 of the main radix
   static constexpr int E = L >= EPT ? EPT : L;
   static constexpr int T = L / E;
-  static constexpr int NP = (LG + 3) / 4;
-  static constexpr int radix(int p) { return (p < LG / 4) ? 16 : (1 << (LG % 4)); }
+  static constexpr int NP = (LG + RB - 1) / RB;
+  static constexpr int radix(int p) { return (p < LG / RB) ? (1 << RB) : (1 << (LG % RB)); }
   static constexpr int ns(int p) {
     int s = 1;
     for (int i = 0; i < p; ++i) s *= radix(i);
@@ -84,6 +86,7 @@ struct KernelInfo {
   int lds_bytes = 0;    // static LDS of the instance
   int map = 0, omap = 0;
   bool persistent = false;  // loops over tiles; launch at most one grid of resident workgroups
+  bool preferred = false;   // the planner's default for its shape (measured fastest)
 };
 
 // Power-of-two line kernel with compile-time length L and C lines per

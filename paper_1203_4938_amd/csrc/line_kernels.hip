@@ -338,13 +338,15 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
 // Pass twiddles of a persistent instance: the whole per-pass table when it
 // fits in LDS next to the tile, else the two-level table (one more product per
 // twiddle).  Returns the LDS entries taken.
-template <int L, int C, int MAP, int OMAP>
+// (The host builds the per-pass table for the 16-elements-per-thread radix
+// plan, so only those instances can take it.)
+template <int L, int C, int MAP, int OMAP, int EPT>
 constexpr bool pf_direct_tw() {
-  return (lds_pairs<L, C, MAP, OMAP>() + P2<L>::twoff(P2<L>::NP)) * 8 <= 160 * 1024;
+  return EPT == 16 && (lds_pairs<L, C, MAP, OMAP>() + P2<L>::twoff(P2<L>::NP)) * 8 <= 160 * 1024;
 }
-template <int L, int C, int MAP, int OMAP>
+template <int L, int C, int MAP, int OMAP, int EPT>
 constexpr int pf_tw_entries() {
-  if constexpr (pf_direct_tw<L, C, MAP, OMAP>()) {
+  if constexpr (pf_direct_tw<L, C, MAP, OMAP, EPT>()) {
     return P2<L>::twoff(P2<L>::NP) > 0 ? P2<L>::twoff(P2<L>::NP) : 1;
   } else {
     return (1 << tw2_shift(P2<L>::LG)) +
@@ -362,8 +364,8 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NPR = lds_pairs<L, C, MAP, OMAP>();
   __shared__ __align__(16) cf lds[NPR > 0 ? NPR : 1];
-  constexpr bool DIRECT = pf_direct_tw<L, C, MAP, OMAP>();
-  constexpr int NTW = pf_tw_entries<L, C, MAP, OMAP>();
+  constexpr bool DIRECT = pf_direct_tw<L, C, MAP, OMAP, EPT>();
+  constexpr int NTW = pf_tw_entries<L, C, MAP, OMAP, EPT>();
   __shared__ cf twl[NTW];
   const cf *tsrc = DIRECT ? a.tw : a.tw2;
   for (int i = threadIdx.x; i < NTW; i += NT) twl[i] = tsrc[i];
@@ -474,14 +476,15 @@ struct LineEntry {
   int threads;
   int lds;
   bool pf;
+  bool pref;          // the planner's default for its shape (measured fastest)
 };
 
 #define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT>
 #define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
             (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
-                (KPF ? (int)sizeof(cf) * pf_tw_entries<L_, C_, M_, O_>() : 0),      \
-            KPF}
+                (KPF ? (int)sizeof(cf) * pf_tw_entries<L_, C_, M_, O_, KEPT>() : 0), \
+            KPF, KPREF}
 
 // rows: forward, inverse single pass (swap in+out), 2D row pass inverse (swap in)
 #define ROW(L_, C_)                                                                          \
@@ -503,6 +506,7 @@ struct LineEntry {
 
 #define KFN k_lines
 #define KPF false
+#define KPREF false
 #define KEPT 16
 static const LineEntry kLineTable[] = {
     // batched rows (single-pass transforms, 2D row pass)
@@ -530,10 +534,26 @@ static const LineEntry kLineTable[] = {
 // 1024-thread budget without spills), nor do the 2048-point column tiles,
 // whose persistent form measured slower than the plain one.
 static const LineEntry kLineTablePf[] = {
-    ROW(4096, 2), ROW(8192, 1), ROW(16384, 1), COL(1024, 16), COLTW(1024, 16),
+    ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
+};
+#undef KPREF
+#define KPREF true
+// defaults of their shapes: where a single 1024-thread workgroup fills the
+// CU's LDS the prefetch of the next tile is the only overlap of memory and
+// compute the CU gets (measured 5-13% faster than the plain instances)
+static const LineEntry kLineTablePfPref[] = {
+    COL(1024, 16), COLTW(1024, 16),
+};
+#undef KEPT
+#define KEPT 32
+// 32 elements per thread: radix-32 passes, one exchange fewer than radix 16
+// (rows of 16384: 8% faster than the 16-element persistent kernel, 8192: 4%)
+static const LineEntry kLineTablePf32[] = {
+    ROW(16384, 1), ROW(8192, 1),
 };
 #undef KFN
 #undef KPF
+#undef KPREF
 #undef KEPT
 
 static void fill(const LineEntry &e, KernelInfo *out) {
@@ -545,12 +565,15 @@ static void fill(const LineEntry &e, KernelInfo *out) {
   out->map = e.map;
   out->omap = e.omap;
   out->persistent = e.pf;
+  out->preferred = e.pref;
 }
 
 template <class F>
 static void for_each_entry(F f) {
   for (const auto &e : kLineTable) f(e);
   for (const auto &e : kLineTablePf) f(e);
+  for (const auto &e : kLineTablePfPref) f(e);
+  for (const auto &e : kLineTablePf32) f(e);
 }
 
 bool find_line_kernel(int L, int C, int map, int omap, bool tw4, KernelInfo *out) {

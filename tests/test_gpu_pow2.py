@@ -182,10 +182,12 @@ VARIANTS = [
     # chunked four-step: the batch in groups of k signals, with a short last group
     (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
     # persistent 1024-thread instances
-    (16384, 300, "p0=1"), (16384, 7, "p0=0"), (4096, 9, "c0=2 p0=0"),
+    (16384, 300, "p0=1 t0=1024"), (16384, 7, "p0=0"), (4096, 9, "c0=2 p0=0"),
     (1 << 20, 3, "p0=1"), (1 << 20, 3, "p0=0"),
     # other four-step splits of 2^22 (1024 x 4096, 4096 x 1024)
     (1 << 22, 1, "s=10"), (1 << 22, 1, "s=12"),
+    # 32 elements per thread, radix-32 passes
+    (16384, 11, "p0=1 t0=512"), (8192, 7, "p0=1 t0=256"),
 ]
 
 
