@@ -317,7 +317,7 @@ std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, in
   if (!choose_line(L, map, omap, tw4, cmax, step, ov, &s->k)) return nullptr;
   s->L = L;
   s->name = name;
-  s->tw_off = P->tables.add(stockham_table_pow2(L));
+  s->tw_off = P->tables.add(stockham_table_pow2(L, s->k.ept));
   s->a.scale = 1.0f;
   if (s->k.persistent) {
     std::vector<std::complex<double>> lo, hi;

@@ -35,9 +35,8 @@ struct LineArgs {
 
 // Radix plan of the power-of-two line kernels, shared by the device code and
 // the host twiddle generator.  E elements per thread (EPT, or L if smaller;
-// a multiple of every radix), T threads per line.  With 16 elements per
-// thread: radix-16 passes, then one radix 2/4/8 remainder pass; with 32:
-// radix-32 passes, then one radix 2/4/8/16 remainder pass.
+// a multiple of every radix), T threads per line.  The main radix is EPT
+// (16 or 32), followed by one smaller power-of-two remainder pass.
 template <int L, int EPT = 16> struct P2 {
   static constexpr int lg() {
     int k = 0;
@@ -66,16 +65,19 @@ template <int L, int EPT = 16> struct P2 {
 // hi[e >> S] * lo[e & (2^S - 1)] with 2^S lo and L / 2^S hi entries.
 constexpr int tw2_shift(int lg) { return (lg + 1) / 2; }
 
-// Runtime twin of P2<L> for the host.
-inline int pow2_radix(int L, int p) {
+// Runtime twin of P2<L, EPT> for the host.
+inline int pow2_rb(int ept) { return ept >= 32 ? 5 : 4; }
+inline int pow2_radix(int L, int p, int ept = 16) {
   int lg = 0;
   while ((1 << lg) < L) ++lg;
-  return (p < lg / 4) ? 16 : (1 << (lg % 4));
+  const int rb = pow2_rb(ept);
+  return (p < lg / rb) ? (1 << rb) : (1 << (lg % rb));
 }
-inline int pow2_passes(int L) {
+inline int pow2_passes(int L, int ept = 16) {
   int lg = 0;
   while ((1 << lg) < L) ++lg;
-  return (lg + 3) / 4;
+  const int rb = pow2_rb(ept);
+  return (lg + rb - 1) / rb;
 }
 
 struct KernelInfo {
@@ -87,6 +89,7 @@ struct KernelInfo {
   int map = 0, omap = 0;
   bool persistent = false;  // loops over tiles; launch at most one grid of resident workgroups
   bool preferred = false;   // the planner's default for its shape (measured fastest)
+  int ept = 16;             // elements per thread (sets the radix plan of the pass table)
 };
 
 // Power-of-two line kernel with compile-time length L and C lines per

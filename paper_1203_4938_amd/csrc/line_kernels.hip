@@ -477,6 +477,7 @@ struct LineEntry {
   int lds;
   bool pf;
   bool pref;          // the planner's default for its shape (measured fastest)
+  int ept;
 };
 
 #define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT>
@@ -484,7 +485,7 @@ struct LineEntry {
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
             (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
                 (KPF ? (int)sizeof(cf) * pf_tw_entries<L_, C_, M_, O_, KEPT>() : 0), \
-            KPF, KPREF}
+            KPF, KPREF, KEPT}
 
 // rows: forward, inverse single pass (swap in+out), 2D row pass inverse (swap in)
 #define ROW(L_, C_)                                                                          \
@@ -566,6 +567,7 @@ static void fill(const LineEntry &e, KernelInfo *out) {
   out->omap = e.omap;
   out->persistent = e.pf;
   out->preferred = e.pref;
+  out->ept = e.ept;
 }
 
 template <class F>

@@ -19,12 +19,12 @@ std::complex<double> omega(int64_t M, int64_t t) {
   return {std::cos(ang), std::sin(ang)};
 }
 
-std::vector<std::complex<double>> stockham_table_pow2(int L) {
+std::vector<std::complex<double>> stockham_table_pow2(int L, int ept) {
   std::vector<std::complex<double>> tab;
-  const int np = pow2_passes(L);
+  const int np = pow2_passes(L, ept);
   int ns = 1;
   for (int p = 0; p < np; ++p) {
-    const int R = pow2_radix(L, p);
+    const int R = pow2_radix(L, p, ept);
     if (p >= 1) {
       for (int r = 1; r < R; ++r)
         for (int k = 0; k < ns; ++k) tab.push_back(omega((int64_t)ns * R, (int64_t)k * r));
