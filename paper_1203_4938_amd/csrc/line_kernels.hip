@@ -65,7 +65,11 @@ __device__ __forceinline__ void lds_exchange(cf (&v)[E], cf *lds, WPos wpos, RPo
 // TwLds2 rebuilds w_{Ns R}^{k r} = w_L^{k r L/(Ns R)} from the two-level table
 // held in LDS (one product, no global load, so nothing waits behind a
 // prefetch).
+// tree<..>(): where a lookup costs more than a product, for radix 8, 16 and 32
+// only w^r for r = 1, 2, 3 and the multiples of 4 are looked up and the
+// others are formed as w^{4s} w^l (one product each).
 struct TwTable {
+  template <int TWO> static constexpr bool tree() { return false; }
   const cf *__restrict__ tw;
   template <int L, int TWO, int NS, int R>
   __device__ __forceinline__ cf get(int r, int k) const {
@@ -74,6 +78,7 @@ struct TwTable {
 };
 // TwLdsTable: the per-pass table itself, copied to LDS (one read per twiddle)
 struct TwLdsTable {
+  template <int TWO> static constexpr bool tree() { return false; }
   const cf *t;
   template <int L, int TWO, int NS, int R>
   __device__ __forceinline__ cf get(int r, int k) const {
@@ -81,6 +86,7 @@ struct TwLdsTable {
   }
 };
 struct TwLds2 {
+  template <int TWO> static constexpr bool tree() { return true; }
   const cf *lo;
   const cf *hi;
   template <int L, int TWO, int NS, int R>
@@ -88,6 +94,20 @@ struct TwLds2 {
     constexpr int S = tw2_shift(P2<L>::LG);
     const uint32_t e = (uint32_t)(k * r) * (uint32_t)(L / (NS * R));
     return cmul(hi[e >> S], lo[e & ((1u << S) - 1u)]);
+  }
+};
+// TwLdsFirst: the first pass with twiddles (table offset 0) reads its own part
+// of the per-pass table from LDS; the later passes use the two-level table.
+struct TwLdsFirst {
+  template <int TWO> static constexpr bool tree() { return TWO != 0; }
+  const cf *first;
+  TwLds2 rest;
+  template <int L, int TWO, int NS, int R>
+  __device__ __forceinline__ cf get(int r, int k) const {
+    if constexpr (TWO == 0)
+      return first[(r - 1) * NS + k];
+    else
+      return rest.template get<L, TWO, NS, R>(r, k);
   }
 };
 
@@ -107,8 +127,21 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds,
     for (int r = 0; r < R; ++r) x[r] = v[q + r * QN];
     if constexpr (NS > 1) {
       const int k = b & (NS - 1);
+      if constexpr (TW::template tree<TWO>() && R >= 8) {
+        cf wl[4], w4[R / 4];
 #pragma unroll
-      for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw.template get<L, TWO, NS, R>(r, k));
+        for (int l = 1; l < 4; ++l) wl[l] = tw.template get<L, TWO, NS, R>(l, k);
+#pragma unroll
+        for (int g = 1; g < R / 4; ++g) w4[g] = tw.template get<L, TWO, NS, R>(4 * g, k);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int g = r / 4, l = r % 4;
+          x[r] = cmul(x[r], g == 0 ? wl[l] : (l == 0 ? w4[g] : cmul(w4[g], wl[l])));
+        }
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw.template get<L, TWO, NS, R>(r, k));
+      }
     }
     Dft<R>::run(x);
 #pragma unroll
@@ -344,13 +377,31 @@ template <int L, int C, int MAP, int OMAP, int EPT>
 constexpr bool pf_direct_tw() {
   return EPT == 16 && (lds_pairs<L, C, MAP, OMAP>() + P2<L>::twoff(P2<L>::NP)) * 8 <= 160 * 1024;
 }
+// Otherwise the two-level table, plus the first twiddle pass's own part of
+// the per-pass table when that still fits.
+template <int L, int EPT>
+constexpr int pf_tw2_entries() {
+  return (1 << tw2_shift(P2<L>::LG)) +
+         ((L >> tw2_shift(P2<L>::LG)) > 0 ? (L >> tw2_shift(P2<L>::LG)) : 1);
+}
+template <int L, int EPT>
+constexpr int pf_first_entries() {
+  return P2<L, EPT>::NP > 1 ? P2<L, EPT>::twoff(2) : 0;
+}
+template <int L, int C, int MAP, int OMAP, int EPT>
+constexpr bool pf_first_tw() {
+  return !pf_direct_tw<L, C, MAP, OMAP, EPT>() && pf_first_entries<L, EPT>() > 0 &&
+         (lds_pairs<L, C, MAP, OMAP>() + pf_tw2_entries<L, EPT>() + pf_first_entries<L, EPT>()) *
+                 8 <= 160 * 1024;
+}
 template <int L, int C, int MAP, int OMAP, int EPT>
 constexpr int pf_tw_entries() {
   if constexpr (pf_direct_tw<L, C, MAP, OMAP, EPT>()) {
     return P2<L>::twoff(P2<L>::NP) > 0 ? P2<L>::twoff(P2<L>::NP) : 1;
+  } else if constexpr (pf_first_tw<L, C, MAP, OMAP, EPT>()) {
+    return pf_tw2_entries<L, EPT>() + pf_first_entries<L, EPT>();
   } else {
-    return (1 << tw2_shift(P2<L>::LG)) +
-           ((L >> tw2_shift(P2<L>::LG)) > 0 ? (L >> tw2_shift(P2<L>::LG)) : 1);
+    return pf_tw2_entries<L, EPT>();
   }
 }
 
@@ -365,15 +416,23 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   constexpr int NPR = lds_pairs<L, C, MAP, OMAP>();
   __shared__ __align__(16) cf lds[NPR > 0 ? NPR : 1];
   constexpr bool DIRECT = pf_direct_tw<L, C, MAP, OMAP, EPT>();
+  constexpr bool FIRST = pf_first_tw<L, C, MAP, OMAP, EPT>();
   constexpr int NTW = pf_tw_entries<L, C, MAP, OMAP, EPT>();
+  constexpr int N2L = pf_tw2_entries<L, EPT>();
   __shared__ cf twl[NTW];
-  const cf *tsrc = DIRECT ? a.tw : a.tw2;
-  for (int i = threadIdx.x; i < NTW; i += NT) twl[i] = tsrc[i];
+  if constexpr (DIRECT) {
+    for (int i = threadIdx.x; i < NTW; i += NT) twl[i] = a.tw[i];
+  } else {
+    // two-level table, then (FIRST) the first twiddle pass's part of a.tw
+    for (int i = threadIdx.x; i < NTW; i += NT) twl[i] = i < N2L ? a.tw2[i] : a.tw[i - N2L];
+  }
   __syncthreads();
-  using TWS = std::conditional_t<DIRECT, TwLdsTable, TwLds2>;
+  using TWS = std::conditional_t<DIRECT, TwLdsTable, std::conditional_t<FIRST, TwLdsFirst, TwLds2>>;
   TWS tw;
   if constexpr (DIRECT) {
     tw = TwLdsTable{twl};
+  } else if constexpr (FIRST) {
+    tw = TwLdsFirst{twl + N2L, TwLds2{twl, twl + NLO}};
   } else {
     tw = TwLds2{twl, twl + NLO};
   }
