@@ -200,11 +200,12 @@ std::vector<std::string> candidates(const fft_desc_t *d) {
     } else {
       int lg = 0;
       while ((int64_t(1) << lg) < N) ++lg;
-      // the balanced split N1 = 2^(lg/2) and its two neighbours
+      // the balanced split N1 = 2^(lg/2) and its two neighbours, each named
+      // explicitly (the planner's default split is not always the balanced one)
       for (int lg1 : {lg / 2, lg / 2 - 1, lg / 2 + 1}) {
         if (lg1 < 1 || lg1 >= lg) continue;
         const int N1 = 1 << lg1, N2 = 1 << (lg - lg1);
-        const std::string sp = lg1 == lg / 2 ? "" : "s=" + std::to_string(lg1) + " ";
+        const std::string sp = "s=" + std::to_string(lg1) + " ";
         for (const auto &a : cs(N1, LINE_FAST, LINE_FAST, true, ks))
           for (const auto &b : cs(N2, ELEM_FAST, LINE_FAST, false, kb))
             out.push_back(sp + enc(0, a) + " " + enc(1, b));

@@ -596,20 +596,31 @@ static const LineEntry kLineTable[] = {
 static const LineEntry kLineTablePf[] = {
     ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
 };
-#undef KPREF
-#define KPREF true
-// defaults of their shapes: where a single 1024-thread workgroup fills the
-// CU's LDS the prefetch of the next tile is the only overlap of memory and
-// compute the CU gets (measured 5-13% faster than the plain instances)
-static const LineEntry kLineTablePfPref[] = {
+// 1024-point column tiles: where a single workgroup fills the CU's LDS the
+// prefetch of the next tile is the only overlap of memory and compute the CU
+// gets (5-13% faster than the plain instances; the 32-element form below is
+// faster still)
+static const LineEntry kLineTablePfCol[] = {
     COL(1024, 16), COLTW(1024, 16),
 };
 #undef KEPT
 #define KEPT 32
-// 32 elements per thread: radix-32 passes, one exchange fewer than radix 16
-// (rows of 16384: 8% faster than the 16-element persistent kernel, 8192: 4%)
+// 32 elements per thread, radix-32 passes: one pass and one exchange fewer
+// than radix 16 for L = 2^10, 2^13 and 2^14 (rows of 16384: 8% faster than
+// the 16-element persistent kernel, 8192: 4%; 1024-point column tiles: 8-9%).
+// These are the defaults of their shapes.
+#undef KPREF
+#define KPREF true
 static const LineEntry kLineTablePf32[] = {
-    ROW(16384, 1), ROW(8192, 1),
+    ROW(16384, 1), ROW(8192, 1), COL(1024, 16), COLTW(1024, 16),
+};
+// opt-in: 2048-point column tiles (no faster than the plain instances) and
+// transposed-row tiles (the re-tiling exchange next to the two register sets
+// spills)
+#undef KPREF
+#define KPREF false
+static const LineEntry kLineTablePf32x[] = {
+    COLTW(2048, 8), ROWT(2048, 8), COL(2048, 8), ROWT(1024, 16),
 };
 #undef KFN
 #undef KPF
@@ -633,8 +644,9 @@ template <class F>
 static void for_each_entry(F f) {
   for (const auto &e : kLineTable) f(e);
   for (const auto &e : kLineTablePf) f(e);
-  for (const auto &e : kLineTablePfPref) f(e);
+  for (const auto &e : kLineTablePfCol) f(e);
   for (const auto &e : kLineTablePf32) f(e);
+  for (const auto &e : kLineTablePf32x) f(e);
 }
 
 bool find_line_kernel(int L, int C, int map, int omap, bool tw4, KernelInfo *out) {

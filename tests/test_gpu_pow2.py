@@ -177,17 +177,20 @@ def test_exec_rejects_bad_arguments():
 
 VARIANTS = [
     (4096, 10, "p0=1"), (8192, 6, "p0=1"), (1024, 37, "c0=8"), (2048, 9, "c0=4"),
-    (4096, 7, "c0=2"), (1 << 22, 1, "c0=4 c1=4"), (1 << 20, 2, "c0=8 c1=8"),
-    (1 << 18, 3, "c0=16 c1=16"), (1 << 22, 1, "c0=8 c1=8"),
+    (4096, 7, "c0=2"), (1 << 22, 1, "s=11 c0=4 c1=4"), (1 << 20, 2, "c0=8 c1=8"),
+    (1 << 18, 3, "c0=16 c1=16"), (1 << 22, 1, "s=11 c0=8 c1=8"),
     # chunked four-step: the batch in groups of k signals, with a short last group
     (1 << 18, 5, "k=2"), (1 << 15, 7, "k=3"), (1 << 20, 3, "k=1"),
     # persistent 1024-thread instances
     (16384, 300, "p0=1 t0=1024"), (16384, 7, "p0=0"), (4096, 9, "c0=2 p0=0"),
-    (1 << 20, 3, "p0=1"), (1 << 20, 3, "p0=0"),
-    # other four-step splits of 2^22 (1024 x 4096, 4096 x 1024)
-    (1 << 22, 1, "s=10"), (1 << 22, 1, "s=12"),
+    (1 << 20, 3, "p0=1 t0=1024"), (1 << 20, 3, "p0=0"),
+    # other four-step splits of 2^22 (2048 x 2048, 4096 x 1024)
+    (1 << 22, 1, "s=11"), (1 << 22, 1, "s=12"),
     # 32 elements per thread, radix-32 passes
     (16384, 11, "p0=1 t0=512"), (8192, 7, "p0=1 t0=256"),
+    # persistent column and transposed-row tiles with 32 elements per thread
+    (1 << 22, 1, "s=11 p0=1 t0=512 p1=1 t1=512"), (1 << 20, 3, "p0=1 t0=512 p1=1 t1=512"),
+    (1 << 22, 2, "p0=1 t0=1024"),
 ]
 
 
@@ -208,7 +211,8 @@ def test_forced_variants(n, batch, force, monkeypatch):
         assert e <= TOL_FP32, (n, force, inv, e)
 
 
-@pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (1024, "p1=0")])
+@pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (1024, "p1=0"),
+                                     (2048, "p1=1 t1=512"), (1024, "p1=1 t1=512")])
 def test_forced_2d_variants(n, force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
