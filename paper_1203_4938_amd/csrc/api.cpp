@@ -282,7 +282,8 @@ int resident_workgroups(const KernelInfo &k) { return resident_for(k.lds_bytes, 
 // most resident waves per CU that the 160 KB LDS allows (counted up to 16),
 // then for row tiles the smaller tile (more workgroups to overlap), for column
 // tiles the wider tile (longer contiguous segments).  Other persistent
-// instances are opt-in (override or tuner).
+// instances and other instances with 32 elements per thread are opt-in
+// (override or tuner).
 bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const Override &ov,
                  KernelInfo *out) {
   KernelInfo cand[32];
@@ -296,6 +297,7 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
     if (ov.t[step] >= 0 && k.threads != ov.t[step]) continue;
     if (ov.p[step] < 0 && k.persistent && !k.preferred) continue;
+    if (ov.t[step] < 0 && k.ept != 16 && !k.preferred) continue;
     if (k.threads > 1024) continue;
     int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 64;
     int by_thr = 2048 / k.threads;
