@@ -281,11 +281,12 @@ int resident_workgroups(const KernelInfo &k) { return resident_for(k.lds_bytes, 
 // the registry marks as the measured default of its shape wins; otherwise the
 // most resident waves per CU that the 160 KB LDS allows (counted up to 16),
 // then for row tiles the smaller tile (more workgroups to overlap), for column
-// tiles the wider tile (longer contiguous segments).  Other persistent
+// tiles the wider tile (longer contiguous segments); the caller's cap on lines
+// per tile applies to the heuristic choice only.  Other persistent
 // instances and other instances with 32 elements per thread are opt-in
 // (override or tuner).
-bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const Override &ov,
-                 KernelInfo *out) {
+bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, int64_t lines_total,
+                 const Override &ov, KernelInfo *out) {
   KernelInfo cand[32];
   int n = list_line_kernels(L, map, omap, tw4, cand, 32);
   if (n > 32) n = 32;
@@ -293,10 +294,16 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
   for (int i = 0; i < n; ++i) {
     const KernelInfo &k = cand[i];
     if (ov.c[step] >= 0 && k.lines != ov.c[step]) continue;
-    if (ov.c[step] < 0 && k.lines > cmax) continue;
+    if (ov.c[step] < 0 && k.lines > cmax && !k.preferred) continue;
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
     if (ov.t[step] >= 0 && k.threads != ov.t[step]) continue;
     if (ov.p[step] < 0 && k.persistent && !k.preferred) continue;
+    // a persistent default pays off only where every resident workgroup gets
+    // more than one tile (its prefetch needs a next tile); small batches take
+    // the heuristic choice
+    if (ov.p[step] < 0 && k.persistent &&
+        (lines_total + k.lines - 1) / k.lines <= resident_workgroups(k))
+      continue;
     if (ov.t[step] < 0 && k.ept != 16 && !k.preferred) continue;
     if (k.threads > 1024) continue;
     int by_lds = k.lds_bytes ? kLdsBytes / k.lds_bytes : 64;
@@ -314,9 +321,10 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, const O
 }
 
 std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, int map, int omap,
-                                    bool tw4, int cmax, int step, const Override &ov) {
+                                    bool tw4, int cmax, int step, int64_t lines_total,
+                                    const Override &ov) {
   auto s = std::make_unique<LineStep>();
-  if (!choose_line(L, map, omap, tw4, cmax, step, ov, &s->k)) return nullptr;
+  if (!choose_line(L, map, omap, tw4, cmax, step, lines_total, ov, &s->k)) return nullptr;
   s->L = L;
   s->name = name;
   s->tw_off = P->tables.add(stockham_table_pow2(L, s->k.ept));
@@ -370,7 +378,7 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   const Override ov = read_override();
   if (N <= kSinglePassMax) {
     const int L = (int)N;
-    auto s = make_line(P, "stockham_rows", L, ELEM_FAST, ELEM_FAST, false, 256, 0, ov);
+    auto s = make_line(P, "stockham_rows", L, ELEM_FAST, ELEM_FAST, false, 256, 0, B, ov);
     if (!s) return fail(FFT_E_INTERNAL, "no row kernel for L=" + std::to_string(L));
     const int C = s->k.lines;
     s->a.in_b = s->a.out_b = 0;
@@ -401,8 +409,8 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
     lg1 = 10;
   if (ov.split > 0 && ov.split < lg) lg1 = ov.split;
   const int N1 = 1 << lg1, N2 = 1 << (lg - lg1);
-  auto a = make_line(P, "fourstep_columns", N1, LINE_FAST, LINE_FAST, true, 16, 0, ov);
-  auto b = make_line(P, "fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false, 16, 1, ov);
+  auto a = make_line(P, "fourstep_columns", N1, LINE_FAST, LINE_FAST, true, 16, 0, B * N2, ov);
+  auto b = make_line(P, "fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false, 16, 1, B * N1, ov);
   if (!a || !b) return fail(FFT_E_UNSUPPORTED, "no four-step kernels for N=" + std::to_string(N));
   const int CA = a->k.lines, CB = b->k.lines;
   std::vector<std::complex<double>> lo, hi;
@@ -455,8 +463,8 @@ fft_status_t plan_pow2_2d(dpfft_plan_s *P) {
   const Override ov = read_override();
   // row pass: in -> out; column pass: in place on out (column tiles read and
   // written by the same workgroup, so no transpose and no workspace)
-  auto r = make_line(P, "rows", (int)NX, ELEM_FAST, ELEM_FAST, false, 256, 0, ov);
-  auto c = make_line(P, "columns", (int)NY, LINE_FAST, LINE_FAST, false, 64, 1, ov);
+  auto r = make_line(P, "rows", (int)NX, ELEM_FAST, ELEM_FAST, false, 256, 0, B * NY, ov);
+  auto c = make_line(P, "columns", (int)NY, LINE_FAST, LINE_FAST, false, 64, 1, B * NX, ov);
   if (!r || !c) return fail(FFT_E_UNSUPPORTED, "no 2D kernels for this shape");
   const int CR = r->k.lines, CC = c->k.lines;
   r->a.in_b = r->a.out_b = D;

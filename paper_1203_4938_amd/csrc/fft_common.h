@@ -23,6 +23,13 @@ __device__ __forceinline__ cf cmul(cf a, cf b) {
 }
 __device__ __forceinline__ cf cscale(cf a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ cf cswap(cf a) { return make_float2(a.y, a.x); }
+// An empty asm statement that reads and rewrites both halves: every load into
+// them has to complete here, and the compiler keeps them in VGPRs.
+__device__ __forceinline__ void pin_regs(cf &a) {
+  float x = a.x, y = a.y;
+  asm volatile("" : "+v"(x), "+v"(y));
+  a = make_float2(x, y);
+}
 // multiply by -i
 __device__ __forceinline__ cf mul_mi(cf a) { return make_float2(a.y, -a.x); }
 

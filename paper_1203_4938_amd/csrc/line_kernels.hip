@@ -344,27 +344,26 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 // through the passes and barriers.  Pass twiddles come from LDS.  Each round
 // of gridDim tiles is split so that every XCD sweeps a contiguous slice.
 // ---------------------------------------------------------------------------
+// A lane whose line lies past the last one of a ragged last tile loads the
+// last line instead (and its results are never stored): no branch, so the
+// loads of a prefetch land directly in the registers that hold them.
 template <int L, int EPT, int C, int MAP>
 __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__restrict__ in,
                                           const LineArgs &a, int64_t tile, int c, int j) {
   constexpr int E = P2<L, EPT>::E, T = P2<L, EPT>::T;
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (tile - bb * a.tiles_per_batch) * C;
-  if (line0 + c < a.lines) {
-    if constexpr (MAP == ELEM_FAST) {
-      const cf *src = in + bb * a.in_b + (line0 + c) * a.in_l + j;
+  const int64_t lc = line0 + c < a.lines ? c : a.lines - 1 - line0;
+  if constexpr (MAP == ELEM_FAST) {
+    const cf *src = in + bb * a.in_b + (line0 + lc) * a.in_l + j;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = src[T * m];
-    } else {
-      const cf *tin = in + bb * a.in_b + line0;
-      const uint32_t es = (uint32_t)a.in_e;
-      const uint32_t o = (uint32_t)c + (uint32_t)j * es;
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m) * es);
-    }
+    for (int m = 0; m < E; ++m) v[m] = src[T * m];
   } else {
+    const cf *tin = in + bb * a.in_b + line0;
+    const uint32_t es = (uint32_t)a.in_e;
+    const uint32_t o = (uint32_t)lc + (uint32_t)j * es;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = make_float2(0.0f, 0.0f);
+    for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m) * es);
   }
 }
 
@@ -452,33 +451,44 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   load_tile<L, EPT, C, MAP>(v, in, a, tile, c, j);
   cf A = make_float2(1.f, 0.f), B = A;
   cf nAh = A, nAl = A, nBh = A, nBl = A;  // tw4 table entries of the next tile
-  auto line_of = [&](int64_t t) {
+  auto line_of = [&](int64_t t) {  // clamped like the loads of load_tile
     const int64_t bb = t / a.tiles_per_batch;
-    return (t - bb * a.tiles_per_batch) * C + c;
+    const int64_t line = (t - bb * a.tiles_per_batch) * C + c;
+    return line < a.lines ? line : a.lines - 1;
   };
   if constexpr (TW4) {
     const uint32_t n2 = (uint32_t)line_of(tile);
     A = tw4_lookup(a, n2 * (uint32_t)j);
     B = tw4_lookup(a, n2 * (uint32_t)T);
   }
+  // Wait for the first tile here.  Otherwise the wait-count analysis merges
+  // these loads, still pending at the loop entry, with the path on which no
+  // prefetch is issued, and makes the first pass of every tile wait for the
+  // prefetch of the next one as well (no overlap at all).
+#pragma unroll
+  for (int m = 0; m < E; ++m) pin_regs(v[m]);
+  pin_regs(A);
+  pin_regs(B);
 
   for (; tile < a.ntiles; tile += Gd) {
     // Keep the compiler from hoisting every pass's LDS addresses and twiddles
     // out of the tile loop: they would not fit next to the two register sets.
     asm volatile("" : "+v"(c), "+v"(j));
-    const int64_t next = tile + Gd;
-    if (next < a.ntiles) {
-      if constexpr (TW4) {
-        const uint32_t n2 = (uint32_t)line_of(next);
-        const uint32_t eA = n2 * (uint32_t)j, eB = n2 * (uint32_t)T;
-        const uint32_t msk = (1u << a.tw4_shift) - 1u;
-        nAh = a.tw4_hi[eA >> a.tw4_shift];
-        nAl = a.tw4_lo[eA & msk];
-        nBh = a.tw4_hi[eB >> a.tw4_shift];
-        nBl = a.tw4_lo[eB & msk];
-      }
-      load_tile<L, EPT, C, MAP>(vn, in, a, next, c, j);
+    // In the last round every workgroup prefetches the last tile once more
+    // (L2 hits): an unconditional prefetch lets its loads land directly in
+    // the registers of the next tile, where a branch around it makes the
+    // compiler copy them, and wait for them, right after they are issued.
+    const int64_t next = tile + Gd < a.ntiles ? tile + Gd : a.ntiles - 1;
+    if constexpr (TW4) {
+      const uint32_t n2 = (uint32_t)line_of(next);
+      const uint32_t eA = n2 * (uint32_t)j, eB = n2 * (uint32_t)T;
+      const uint32_t msk = (1u << a.tw4_shift) - 1u;
+      nAh = a.tw4_hi[eA >> a.tw4_shift];
+      nAl = a.tw4_lo[eA & msk];
+      nBh = a.tw4_hi[eB >> a.tw4_shift];
+      nBl = a.tw4_lo[eB & msk];
     }
+    load_tile<L, EPT, C, MAP>(vn, in, a, next, c, j);
     if constexpr (SW & 1) {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
@@ -498,23 +508,26 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
       auto rpos = [&](int m) { return LO::idx(c2, j2 + T * m); };
       lds_exchange<E, true>(v, lds, wpos, rpos);
     }
-    const int64_t line2 = line0 + c2;
-    if (line2 < a.lines) {
-      if constexpr (SW & 2) {
+    // Lanes past the last line of a ragged last tile hold that line's results
+    // (they loaded it, with its twiddles) and store them once more to the same
+    // addresses: identical values, and no branch around the stores.  With a
+    // branch, the wait for the prefetch (on the copy below) would also wait
+    // for the stores, which then could not drain during the next tile.
+    const int64_t lc2 = line0 + c2 < a.lines ? c2 : a.lines - 1 - line0;
+    if constexpr (SW & 2) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
-      }
-      if constexpr (OMAP == ELEM_FAST) {
-        cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
+      for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
+    }
+    if constexpr (OMAP == ELEM_FAST) {
+      cf *dst = out + bb * a.out_b + (line0 + lc2) * a.out_l + j2;
 #pragma unroll
-        for (int m = 0; m < E; ++m) dst[T * m] = v[m];
-      } else {
-        cf *tout = out + bb * a.out_b + line0;
-        const uint32_t es = (uint32_t)a.out_e;
-        const uint32_t o = (uint32_t)c2 + (uint32_t)j2 * es;
+      for (int m = 0; m < E; ++m) dst[T * m] = v[m];
+    } else {
+      cf *tout = out + bb * a.out_b + line0;
+      const uint32_t es = (uint32_t)a.out_e;
+      const uint32_t o = (uint32_t)lc2 + (uint32_t)j2 * es;
 #pragma unroll
-        for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m) * es, v[m]);
-      }
+      for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m) * es, v[m]);
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = vn[m];
@@ -586,17 +599,17 @@ static const LineEntry kLineTable[] = {
 #undef KEPT
 #define KEPT 32
 // 32 elements per thread without the persistent loop: two radix-32/16 passes
-// for 512-point column tiles instead of three (4-5% faster; the defaults of
-// their shapes), and opt-in instances the tuner may try
+// for 512-point tiles instead of three.  The 2D column tiles of 512 are the
+// default of their shape (4-5% faster); the others are opt-in for the tuner.
 #undef KPREF
 #define KPREF true
 static const LineEntry kLineTable32Pref[] = {
-    COLTW(512, 16), COL(512, 16),
+    COL(512, 16),
 };
 #undef KPREF
 #define KPREF false
 static const LineEntry kLineTable32[] = {
-    ROW(1024, 8), ROW(1024, 16), COLTW(512, 32), ROWT(512, 16), ROWT(512, 32),
+    ROW(1024, 8), ROW(1024, 16), COLTW(512, 16), COLTW(512, 32), ROWT(512, 16), ROWT(512, 32),
 };
 #undef KFN
 #undef KPF
@@ -604,40 +617,40 @@ static const LineEntry kLineTable32[] = {
 #define KFN k_lines_pf
 #define KPF true
 #define KEPT 16
-// persistent instances, 16 elements per thread.  Transposed-row tiles have
-// none (with the re-tiling exchange the two register sets do not fit the
-// 1024-thread budget without spills), nor do the 2048-point column tiles,
-// whose persistent form measured slower than the plain one.
-static const LineEntry kLineTablePf[] = {
-    ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
+// Persistent instances, 16 elements per thread.  Rows of 4096, two per tile,
+// are the default of their shape (3.5% faster than the plain 1-row tiles);
+// the others are opt-in: the 32-element forms below are faster.
+#undef KPREF
+#define KPREF true
+static const LineEntry kLineTablePfPref[] = {
+    ROW(4096, 2),
 };
-// 1024-point column tiles: where a single workgroup fills the CU's LDS the
-// prefetch of the next tile is the only overlap of memory and compute the CU
-// gets (5-13% faster than the plain instances; the 32-element form below is
-// faster still)
-static const LineEntry kLineTablePfCol[] = {
-    COL(1024, 16), COLTW(1024, 16),
+#undef KPREF
+#define KPREF false
+static const LineEntry kLineTablePf[] = {
+    ROW(8192, 1), ROW(16384, 1), COL(1024, 16), COLTW(1024, 16),
 };
 #undef KEPT
 #define KEPT 32
-// 32 elements per thread, radix-32 passes: one pass and one exchange fewer
-// than radix 16 for L = 2^10, 2^13 and 2^14 (rows of 16384: 8% faster than
-// the 16-element persistent kernel, 8192: 4%; 1024-point column tiles: 8-9%;
-// rows of 1024, 16 per tile: 6% faster than the plain 4-row tiles).
-// These are the defaults of their shapes.
+// Persistent instances, 32 elements per thread (radix-32 passes: one pass and
+// one exchange fewer than radix 16 for L = 2^10, 2^13 and 2^14), whose tiles
+// fill the CU's LDS.  The defaults of their shapes, measured against the best
+// other instance: rows of 16384 8% faster, of 8192 4%; 1024-point column
+// tiles 8-9%; 1024-point transposed rows 19%; 512-point column tiles of 32
+// columns 4%, transposed rows 1%; rows of 1024, 16 per tile, as fast as the
+// plain 4-row tiles.
 #undef KPREF
 #define KPREF true
 static const LineEntry kLineTablePf32[] = {
-    ROW(16384, 1), ROW(8192, 1), COL(1024, 16), COLTW(1024, 16), ROW(1024, 16),
+    ROW(16384, 1), ROW(8192, 1), ROW(1024, 16), COL(1024, 16), COLTW(1024, 16), ROWT(1024, 16),
+    COLTW(512, 32), ROWT(512, 32),
 };
-// opt-in: 2048-point column tiles (no faster than the plain instances) and
-// transposed-row tiles (the re-tiling exchange next to the two register sets
-// spills)
+// opt-in: 2048-point column and transposed-row tiles (no faster than the
+// plain instances), 512-point tiles of 16 lines, 4096-point transposed rows
 #undef KPREF
 #define KPREF false
 static const LineEntry kLineTablePf32x[] = {
-    COLTW(2048, 8), ROWT(2048, 8), COL(2048, 8), ROWT(1024, 16),
-    COLTW(512, 32), ROWT(512, 32), COLTW(512, 16), ROWT(512, 16),
+    COLTW(2048, 8), ROWT(2048, 8), COL(2048, 8), COLTW(512, 16), ROWT(512, 16), ROWT(4096, 4),
 };
 #undef KFN
 #undef KPF
@@ -662,8 +675,8 @@ static void for_each_entry(F f) {
   for (const auto &e : kLineTable) f(e);
   for (const auto &e : kLineTable32Pref) f(e);
   for (const auto &e : kLineTable32) f(e);
+  for (const auto &e : kLineTablePfPref) f(e);
   for (const auto &e : kLineTablePf) f(e);
-  for (const auto &e : kLineTablePfCol) f(e);
   for (const auto &e : kLineTablePf32) f(e);
   for (const auto &e : kLineTablePf32x) f(e);
 }

@@ -133,11 +133,14 @@ def test_inplace_and_strided_dist():
     assert np.array_equal(yh[:, n:], x[:, n:])
 
 
-def test_signals_more_than_4gib_apart():
+@pytest.mark.parametrize("force", ["", "p0=1 t0=512"])
+def test_signals_more_than_4gib_apart(force, monkeypatch):
     """Rows of one tile lie 2 GiB apart (dist = 2^28 complex64): every line is
-    addressed from its own 64-bit base."""
+    addressed from its own 64-bit base (plain 4-row tiles, and the persistent
+    16-row tiles, whose 13 idle lanes repeat the last row)."""
     import torch
     dp = _dp()
+    monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
     n, b, dist = 1024, 3, 1 << 28
     x = synth.uniform_complex(synth.BASE_SEED + 31, n, b)
     xd = torch.zeros((b - 1) * dist + n, dtype=torch.complex64, device="cuda")
@@ -193,7 +196,8 @@ VARIANTS = [
     (1 << 22, 2, "p0=1 t0=1024"),
     (1024, 37, "c0=8 t0=256"), (1024, 37, "c0=16 t0=512 p0=0"), (1024, 37, "p0=1 t0=512"),
     (1 << 18, 3, "c0=16 t0=256 p0=0 c1=16 t1=256 p1=0"), (1 << 18, 3, "t0=512"),
-    (1024, 37, "c0=4 p0=0"),
+    (1024, 37, "c0=4 p0=0"), (4096, 9, "c0=1"), (1 << 22, 2, "p1=1 t1=512"), (1 << 20, 3, "p1=0"),
+    (1 << 18, 3, "p0=0 p1=0"),
     (1 << 18, 3, "c0=32 t0=512 p0=0 c1=32 t1=512 p1=0"),
     (1 << 18, 3, "p0=1 c0=32 t0=512 p1=1 c1=32 t1=512"), (1 << 18, 3, "p0=1 c0=16 t0=256 p1=1 c1=16 t1=256"),
 ]

@@ -123,6 +123,8 @@ def test_plans_with_signals_far_apart():
     """Signals 2 GiB apart keep the multi-line row kernels (each line has its
     own base address); only column tiles need a span below 4 GiB."""
     t = _dry(n=1024, batch=3, dist=1 << 28)
-    assert "variant=single-pass" in t and "C=16" in t
+    assert "variant=single-pass" in t and "C=4" in t
+    t = _dry(n=1024, batch=5000, dist=1 << 28)
+    assert "variant=single-pass" in t and "C=16" in t and "persistent" in t
     t = _dry(n=1 << 16, batch=2, dist=1 << 28)
     assert "four-step" in t
