@@ -2,8 +2,8 @@
 //
 // A workgroup transforms C "lines" (signals, matrix rows or matrix columns) of
 // compile-time length L = 2^k.  Each line is owned by T = L/E threads that
-// hold E = 16 elements each in registers (thread j owns elements j + T*m).
-// Passes are radix 16 with one radix 2/4/8 remainder pass last.
+// hold E = 16 (or 32) elements each in registers (thread j owns elements
+// j + T*m).  Passes are radix 16 (32) with one smaller remainder pass last.
 //
 // Pass with radix R over butterflies b = 0..L/R-1 and span Ns (the product of
 // the earlier radices), the self-sorting Stockham form of Cooley-Tukey
@@ -651,6 +651,7 @@ static const LineEntry kLineTablePf32[] = {
 #define KPREF false
 static const LineEntry kLineTablePf32x[] = {
     COLTW(2048, 8), ROWT(2048, 8), COL(2048, 8), COLTW(512, 16), ROWT(512, 16), ROWT(4096, 4),
+    COLTW(4096, 4),
 };
 #undef KFN
 #undef KPF
