@@ -92,10 +92,8 @@ struct KernelInfo {
   int ept = 16;             // elements per thread (sets the radix plan of the pass table)
 };
 
-// Power-of-two line kernel with compile-time length L and C lines per
-// workgroup.  tw4 = apply the four-step twiddle w_N^{line*i} before the store.
-bool find_line_kernel(int L, int C, int map, int omap, bool tw4, KernelInfo *out);
-
+// Power-of-two line kernels have compile-time length L and C lines per
+// workgroup; tw4 = apply the four-step twiddle w_N^{line*i} before the store.
 // All compiled instances for (L, map, omap, tw4); returns how many exist and
 // fills up to `max` of them.
 int list_line_kernels(int L, int map, int omap, bool tw4, KernelInfo *out, int max);

@@ -236,11 +236,37 @@ __device__ __forceinline__ void tw4_apply(cf (&v)[E], const LineArgs &a, uint32_
 // tile's span below 4 GiB), so the loads and stores take the scalar-base form
 // with a single offset VGPR each.  Row tiles address each line from its own
 // 64-bit base: their lines may be any distance apart.
-__device__ __forceinline__ cf ldg(const cf *base, uint32_t idx) {
-  return *(const cf *)((const char *)base + (idx << 3));
+// Tile data in HBM.  NT bit 0 marks the loads, bit 1 the stores nontemporal
+// (streamed past the caches' usual allocation): 2-5% faster for the tiles
+// whose rows move whole 128-byte segments both ways, slower for narrower
+// column tiles and for some persistent kernels, so the registry sets it per
+// instance from measurements.
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <int NT>
+__device__ __forceinline__ cf ld_data(const cf *p) {
+  if constexpr (NT & 1) {
+    const f2v r = __builtin_nontemporal_load((const f2v *)p);
+    return make_float2(r.x, r.y);
+  } else {
+    return *p;
+  }
 }
+template <int NT>
+__device__ __forceinline__ void st_data(cf *p, cf v) {
+  if constexpr (NT & 2) {
+    const f2v r = {v.x, v.y};
+    __builtin_nontemporal_store(r, (f2v *)p);
+  } else {
+    *p = v;
+  }
+}
+template <int NT>
+__device__ __forceinline__ cf ldg(const cf *base, uint32_t idx) {
+  return ld_data<NT>((const cf *)((const char *)base + (idx << 3)));
+}
+template <int NT>
 __device__ __forceinline__ void stg(cf *base, uint32_t idx, cf v) {
-  *(cf *)((char *)base + (idx << 3)) = v;
+  st_data<NT>((cf *)((char *)base + (idx << 3)), v);
 }
 
 // LDS complex elements an instance needs (0 if it never exchanges)
@@ -257,7 +283,7 @@ constexpr int lds_pairs() {
 //
 // Addressing: an ELEM_FAST side has unit element stride (x_e == 1) and a
 // LINE_FAST side has unit line stride (x_l == 1); the plan guarantees it.
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, int NT>
 __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
@@ -281,13 +307,13 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     if constexpr (MAP == ELEM_FAST) {
       const cf *src = in + bb * a.in_b + (line0 + c) * a.in_l + j;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = src[T * m];
+      for (int m = 0; m < E; ++m) v[m] = ld_data<NT>(src + T * m);
     } else {
       const cf *tin = in + bb * a.in_b + line0;
       const uint32_t es = (uint32_t)a.in_e;
       const uint32_t o = (uint32_t)c + (uint32_t)j * es;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m) * es);
+      for (int m = 0; m < E; ++m) v[m] = ldg<NT>(tin, o + (uint32_t)(T * m) * es);
     }
     if constexpr (SW & 1) {
 #pragma unroll
@@ -325,13 +351,13 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     if constexpr (OMAP == ELEM_FAST) {
       cf *dst = out + bb * a.out_b + line2 * a.out_l + j2;
 #pragma unroll
-      for (int m = 0; m < E; ++m) dst[T * m] = v[m];
+      for (int m = 0; m < E; ++m) st_data<NT>(dst + T * m, v[m]);
     } else {
       cf *tout = out + bb * a.out_b + line0;
       const uint32_t es = (uint32_t)a.out_e;
       const uint32_t o = (uint32_t)c2 + (uint32_t)j2 * es;
 #pragma unroll
-      for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m) * es, v[m]);
+      for (int m = 0; m < E; ++m) stg<NT>(tout, o + (uint32_t)(T * m) * es, v[m]);
     }
   }
 }
@@ -347,7 +373,7 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 // A lane whose line lies past the last one of a ragged last tile loads the
 // last line instead (and its results are never stored): no branch, so the
 // loads of a prefetch land directly in the registers that hold them.
-template <int L, int EPT, int C, int MAP>
+template <int L, int EPT, int C, int MAP, int NT>
 __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__restrict__ in,
                                           const LineArgs &a, int64_t tile, int c, int j) {
   constexpr int E = P2<L, EPT>::E, T = P2<L, EPT>::T;
@@ -357,13 +383,13 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
   if constexpr (MAP == ELEM_FAST) {
     const cf *src = in + bb * a.in_b + (line0 + lc) * a.in_l + j;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = src[T * m];
+    for (int m = 0; m < E; ++m) v[m] = ld_data<NT>(src + T * m);
   } else {
     const cf *tin = in + bb * a.in_b + line0;
     const uint32_t es = (uint32_t)a.in_e;
     const uint32_t o = (uint32_t)lc + (uint32_t)j * es;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = ldg(tin, o + (uint32_t)(T * m) * es);
+    for (int m = 0; m < E; ++m) v[m] = ldg<NT>(tin, o + (uint32_t)(T * m) * es);
   }
 }
 
@@ -404,12 +430,12 @@ constexpr int pf_tw_entries() {
   }
 }
 
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT>
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int EPT, int NT>
 __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     k_lines_pf(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   using G = P2<L, EPT>;
   static_assert(C * G::T <= 1024, "a workgroup holds at most 1024 threads");
-  constexpr int E = G::E, T = G::T, NT = C * G::T;
+  constexpr int E = G::E, T = G::T, NTH = C * G::T;
   constexpr int S = tw2_shift(G::LG), NLO = 1 << S, NHI = (L >> S) > 0 ? (L >> S) : 1;
   using LO = Lds<L, C, OMAP, kPadShift>;
   constexpr int NPR = lds_pairs<L, C, MAP, OMAP>();
@@ -420,10 +446,10 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   constexpr int N2L = pf_tw2_entries<L, EPT>();
   __shared__ cf twl[NTW];
   if constexpr (DIRECT) {
-    for (int i = threadIdx.x; i < NTW; i += NT) twl[i] = a.tw[i];
+    for (int i = threadIdx.x; i < NTW; i += NTH) twl[i] = a.tw[i];
   } else {
     // two-level table, then (FIRST) the first twiddle pass's part of a.tw
-    for (int i = threadIdx.x; i < NTW; i += NT) twl[i] = i < N2L ? a.tw2[i] : a.tw[i - N2L];
+    for (int i = threadIdx.x; i < NTW; i += NTH) twl[i] = i < N2L ? a.tw2[i] : a.tw[i - N2L];
   }
   __syncthreads();
   using TWS = std::conditional_t<DIRECT, TwLdsTable, std::conditional_t<FIRST, TwLdsFirst, TwLds2>>;
@@ -448,7 +474,7 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   // the four-step twiddle inputs of the next tile are loaded before its data:
   // every wait for an older load then leaves the prefetch in flight.
   cf v[E], vn[E];
-  load_tile<L, EPT, C, MAP>(v, in, a, tile, c, j);
+  load_tile<L, EPT, C, MAP, NT>(v, in, a, tile, c, j);
   cf A = make_float2(1.f, 0.f), B = A;
   cf nAh = A, nAl = A, nBh = A, nBl = A;  // tw4 table entries of the next tile
   auto line_of = [&](int64_t t) {  // clamped like the loads of load_tile
@@ -488,7 +514,7 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
       nBh = a.tw4_hi[eB >> a.tw4_shift];
       nBl = a.tw4_lo[eB & msk];
     }
-    load_tile<L, EPT, C, MAP>(vn, in, a, next, c, j);
+    load_tile<L, EPT, C, MAP, NT>(vn, in, a, next, c, j);
     if constexpr (SW & 1) {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
@@ -521,13 +547,13 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     if constexpr (OMAP == ELEM_FAST) {
       cf *dst = out + bb * a.out_b + (line0 + lc2) * a.out_l + j2;
 #pragma unroll
-      for (int m = 0; m < E; ++m) dst[T * m] = v[m];
+      for (int m = 0; m < E; ++m) st_data<NT>(dst + T * m, v[m]);
     } else {
       cf *tout = out + bb * a.out_b + line0;
       const uint32_t es = (uint32_t)a.out_e;
       const uint32_t o = (uint32_t)lc2 + (uint32_t)j2 * es;
 #pragma unroll
-      for (int m = 0; m < E; ++m) stg(tout, o + (uint32_t)(T * m) * es, v[m]);
+      for (int m = 0; m < E; ++m) stg<NT>(tout, o + (uint32_t)(T * m) * es, v[m]);
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = vn[m];
@@ -552,7 +578,7 @@ struct LineEntry {
   int ept;
 };
 
-#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT>
+#define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT, KNT>
 #define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
             (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
@@ -581,21 +607,30 @@ struct LineEntry {
 #define KPF false
 #define KPREF false
 #define KEPT 16
+#define KNT 0
 static const LineEntry kLineTable[] = {
     // batched rows (single-pass transforms, 2D row pass)
     ROW(1, 256), ROW(2, 256), ROW(4, 256), ROW(8, 256), ROW(16, 256), ROW(32, 128),
     ROW(64, 64), ROW(128, 32), ROW(256, 16), ROW(512, 8), ROW(1024, 4), ROW(1024, 8),
-    ROW(2048, 2), ROW(2048, 4), ROW(4096, 1), ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
+    ROW(2048, 4), ROW(4096, 1), ROW(4096, 2), ROW(8192, 1), ROW(16384, 1),
     // column tiles (2D column pass)
     COL(16, 64), COL(32, 32), COL(64, 16), COL(128, 16), COL(256, 16), COL(512, 16),
     COL(1024, 16), COL(1024, 8), COL(2048, 4), COL(2048, 8), COL(4096, 4),
     // column tiles with the four-step twiddle (first four-step pass)
-    COLTW(64, 16), COLTW(128, 16), COLTW(256, 16), COLTW(256, 32), COLTW(512, 16),
+    COLTW(64, 16), COLTW(128, 16), COLTW(256, 32), COLTW(512, 16),
     COLTW(1024, 16), COLTW(1024, 8), COLTW(2048, 4), COLTW(2048, 8), COLTW(4096, 4),
     // rows stored transposed (second four-step pass)
-    ROWT(64, 16), ROWT(128, 16), ROWT(256, 16), ROWT(256, 32), ROWT(512, 16),
+    ROWT(64, 16), ROWT(128, 16), ROWT(256, 32), ROWT(512, 16),
     ROWT(1024, 16), ROWT(1024, 8), ROWT(2048, 4), ROWT(2048, 8), ROWT(4096, 4),
 };
+// nontemporal tile data (rows of 2048, the 256 x 256 four-step): 2-4% faster
+#undef KNT
+#define KNT 3
+static const LineEntry kLineTableNt[] = {
+    ROW(2048, 2), COLTW(256, 16), ROWT(256, 16),
+};
+#undef KNT
+#define KNT 0
 #undef KEPT
 #define KEPT 32
 // 32 elements per thread without the persistent loop: two radix-32/16 passes
@@ -618,13 +653,18 @@ static const LineEntry kLineTable32[] = {
 #define KPF true
 #define KEPT 16
 // Persistent instances, 16 elements per thread.  Rows of 4096, two per tile,
-// are the default of their shape (3.5% faster than the plain 1-row tiles);
-// the others are opt-in: the 32-element forms below are faster.
+// are the default of their shape (3.5% faster than the plain 1-row tiles,
+// nontemporal data 1% more); the others are opt-in: the 32-element forms
+// below are faster.
 #undef KPREF
 #define KPREF true
+#undef KNT
+#define KNT 3
 static const LineEntry kLineTablePfPref[] = {
     ROW(4096, 2),
 };
+#undef KNT
+#define KNT 0
 #undef KPREF
 #define KPREF false
 static const LineEntry kLineTablePf[] = {
@@ -642,9 +682,22 @@ static const LineEntry kLineTablePf[] = {
 #undef KPREF
 #define KPREF true
 static const LineEntry kLineTablePf32[] = {
-    ROW(16384, 1), ROW(8192, 1), ROW(1024, 16), COL(1024, 16), COLTW(1024, 16), ROWT(1024, 16),
-    COLTW(512, 32), ROWT(512, 32),
+    ROW(16384, 1), ROW(8192, 1), COL(1024, 16), COLTW(1024, 16), ROWT(1024, 16), ROWT(512, 32),
 };
+// the same with nontemporal stores (rows of 1024: 2%) or loads and stores
+// (512-point column tiles: 5%)
+#undef KNT
+#define KNT 2
+static const LineEntry kLineTablePf32Nts[] = {
+    ROW(1024, 16),
+};
+#undef KNT
+#define KNT 3
+static const LineEntry kLineTablePf32Nt[] = {
+    COLTW(512, 32),
+};
+#undef KNT
+#define KNT 0
 // opt-in: 2048-point column and transposed-row tiles (no faster than the
 // plain instances), 512-point tiles of 16 lines, 4096-point transposed rows
 #undef KPREF
@@ -657,6 +710,7 @@ static const LineEntry kLineTablePf32x[] = {
 #undef KPF
 #undef KPREF
 #undef KEPT
+#undef KNT
 
 static void fill(const LineEntry &e, KernelInfo *out) {
   for (int i = 0; i < 4; ++i) out->fn_sw[i] = e.fn[i];
@@ -674,22 +728,15 @@ static void fill(const LineEntry &e, KernelInfo *out) {
 template <class F>
 static void for_each_entry(F f) {
   for (const auto &e : kLineTable) f(e);
+  for (const auto &e : kLineTableNt) f(e);
   for (const auto &e : kLineTable32Pref) f(e);
   for (const auto &e : kLineTable32) f(e);
   for (const auto &e : kLineTablePfPref) f(e);
   for (const auto &e : kLineTablePf) f(e);
   for (const auto &e : kLineTablePf32) f(e);
+  for (const auto &e : kLineTablePf32Nts) f(e);
+  for (const auto &e : kLineTablePf32Nt) f(e);
   for (const auto &e : kLineTablePf32x) f(e);
-}
-
-bool find_line_kernel(int L, int C, int map, int omap, bool tw4, KernelInfo *out) {
-  for (const auto &e : kLineTable) {
-    if (e.L == L && e.C == C && e.map == map && e.omap == omap && e.tw4 == tw4) {
-      fill(e, out);
-      return true;
-    }
-  }
-  return false;
 }
 
 int list_line_kernels(int L, int map, int omap, bool tw4, KernelInfo *out, int max) {
