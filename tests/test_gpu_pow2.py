@@ -190,7 +190,7 @@ VARIANTS = [
     # other four-step splits of 2^22 (2048 x 2048, 1024 x 4096)
     (1 << 22, 1, "s=11"), (1 << 22, 1, "s=10"),
     # 32 elements per thread, radix-32 passes
-    (16384, 11, "p0=1 t0=512"), (8192, 7, "p0=1 t0=256"),
+    (16384, 11, "p0=1 t0=512"), (8192, 7, "p0=1 t0=256"), (8192, 5, "p0=0"),
     # persistent column and transposed-row tiles with 32 elements per thread
     (1 << 22, 1, "s=11 p0=1 t0=512 p1=1 t1=512"), (1 << 20, 3, "p0=1 t0=512 p1=1 t1=512"),
     (1 << 22, 2, "s=10 p0=1 t0=1024"),
@@ -221,7 +221,8 @@ def test_forced_variants(n, batch, force, monkeypatch):
 
 
 @pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (1024, "p1=0"),
-                                     (2048, "p1=1 t1=512"), (1024, "p1=1 t1=512"), (512, "c1=16 t1=256"), (512, "c1=16 t1=512")])
+                                     (2048, "p1=1 t1=512"), (1024, "p1=1 t1=512"), (512, "c1=16 t1=256"), (512, "c1=16 t1=512"),
+                                     (2048, "p1=0")])
 def test_forced_2d_variants(n, force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
