@@ -39,6 +39,18 @@ namespace {
 
 constexpr int kPitch = 256 + 16 + 1;  // LDS pitch of a line (pad: one per 16, plus one)
 
+// Tile data moves with the nontemporal hint: every tile row is a whole
+// 128-byte segment or more, where it measured faster.
+typedef float f2s __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cf ld_stream(const cf *p) {
+  const f2s r = __builtin_nontemporal_load((const f2s *)p);
+  return make_float2(r.x, r.y);
+}
+__device__ __forceinline__ void st_stream(cf *p, cf v) {
+  const f2s r = {v.x, v.y};
+  __builtin_nontemporal_store(r, (f2s *)p);
+}
+
 __device__ __forceinline__ int tidx(int c, int pos) { return c * kPitch + pos + (pos >> 4); }
 
 template <int PREC> struct Piece;
@@ -157,10 +169,12 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
     const int j = MAP == ELEM_FAST ? tid & 15 : tid >> 4;
     const int64_t line = line0 + c;
     if (line < a.lines) {
+      // per-line base, 32-bit element offsets (at most 255 x 256 elements)
       const cf *src = in + bb * a.in_b + line * a.in_l;
+      const uint32_t es = (uint32_t)a.in_e;
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
-        cf v = src[(int64_t)(j + 16 * m) * a.in_e];
+        cf v = ld_stream(src + (uint32_t)(j + 16 * m) * es);
         if (SW & 1) v = cswap(v);
         tile[tidx(c, j + 16 * m)] = v;
       }
@@ -173,6 +187,21 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
 
   const int part = g4 >> 1, kb = 8 * (g4 & 1);
   cf *scr = scratch[wave];
+  // four-step twiddle bases of the wave's lines, loaded before the first
+  // stage so that no stage waits on them: A = w_N^{line (col + 64 g4)},
+  // S = w_N^{16 line}
+  cf tA[C / 4], tS[C / 4];
+  if constexpr (TW4) {
+    const uint32_t m = (1u << a.tw4_shift) - 1u;
+#pragma unroll
+    for (int u = 0; u < C / 4; ++u) {
+      const uint32_t line = (uint32_t)(line0 + wave * (C / 4) + u);
+      const uint32_t e0 = line * (uint32_t)(col + 64 * g4), e1 = line * 16u;
+      tA[u] = cmul(a.tw4_hi[e0 >> a.tw4_shift], a.tw4_lo[e0 & m]);
+      tS[u] = cmul(a.tw4_hi[e1 >> a.tw4_shift], a.tw4_lo[e1 & m]);
+    }
+  }
+#pragma unroll
   for (int u = 0; u < C / 4; ++u) {
     const int c = wave * (C / 4) + u;
     // stage 1: vector n2 = col, element n1 = kb + t: x[n2 + 16 n1]
@@ -206,12 +235,8 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
 #pragma unroll
     for (int t = 0; t < 4; ++t) y4[t] = make_float2(dre[t], dim[t]);
     if constexpr (TW4) {
-      // w_N^{line k}, k = col + 16 (4 g4 + t): A = w^{line (col + 64 g4)}, S = w^{16 line}
-      const uint32_t e0 = (uint32_t)line * (uint32_t)(col + 64 * g4);
-      const uint32_t e1 = (uint32_t)line * 16u;
-      const uint32_t m = (1u << a.tw4_shift) - 1u;
-      const cf A = cmul(a.tw4_hi[e0 >> a.tw4_shift], a.tw4_lo[e0 & m]);
-      const cf S = cmul(a.tw4_hi[e1 >> a.tw4_shift], a.tw4_lo[e1 & m]);
+      // w_N^{line k}, k = col + 16 (4 g4 + t) = A S^t
+      const cf A = tA[u], S = tS[u];
       const cf S2 = cmul(S, S);
       y4[0] = cmul(y4[0], A);
       y4[1] = cmul(y4[1], cmul(A, S));
@@ -237,8 +262,9 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
     const int64_t line = line0 + c;
     if (line < a.lines) {
       cf *dst = out + bb * a.out_b + line * a.out_l;
+      const uint32_t es = (uint32_t)a.out_e;
 #pragma unroll
-      for (int m = 0; m < 16; ++m) dst[(int64_t)(j + 16 * m) * a.out_e] = tile[tidx(c, j + 16 * m)];
+      for (int m = 0; m < 16; ++m) st_stream(dst + (uint32_t)(j + 16 * m) * es, tile[tidx(c, j + 16 * m)]);
     }
   }
 }
