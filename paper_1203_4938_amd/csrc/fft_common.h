@@ -104,6 +104,24 @@ __device__ __forceinline__ cf mulw32(cf x) {
   }
 }
 
+// x * w_9^E with w_9 = exp(-2 pi i / 9): cos and sin of 2*pi*e/9, e = 0..8
+__device__ constexpr float kCos9[9] = {
+    1.000000000000000000f, 0.766044443118978013f, 0.173648177666930414f, -0.500000000000000000f, -0.939692620785908317f,
+    -0.939692620785908317f, -0.500000000000000000f, 0.173648177666930414f, 0.766044443118978013f};
+__device__ constexpr float kSin9[9] = {
+    0.000000000000000000f, 0.642787609686539252f, 0.984807753012208020f, 0.866025403784438708f, 0.342020143325668879f,
+    -0.342020143325668879f, -0.866025403784438708f, -0.984807753012208020f, -0.642787609686539252f};
+template <int E>
+__device__ __forceinline__ cf mulw9(cf x) {
+  constexpr int e = ((E % 9) + 9) % 9;
+  if constexpr (e == 0) {
+    return x;
+  } else {
+    constexpr float c = kCos9[e], s = kSin9[e];  // w = c - i s
+    return make_float2(x.x * c + x.y * s, x.y * c - x.x * s);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // power-of-two DFTs
 // ---------------------------------------------------------------------------
@@ -145,6 +163,8 @@ __device__ __forceinline__ void twiddle_row(cf *b) {
     [&]<int... K>(std::integer_sequence<int, K...>) {
       if constexpr (16 % (R1 * R2) == 0)
         ((b[K] = mulw16<R1 * R2, N2 * K>(b[K])), ...);
+      else if constexpr (R1 * R2 == 9)
+        ((b[K] = mulw9<N2 * K>(b[K])), ...);
       else
         ((b[K] = mulw32<R1 * R2, N2 * K>(b[K])), ...);
     }(std::make_integer_sequence<int, R1>{});
@@ -252,6 +272,10 @@ template <> struct Dft<5> {
 };
 template <> struct Dft<7> {
   __device__ __forceinline__ static void run(cf *a) { dft_prime<7>(a); }
+};
+// DFT-9 as 3 x 3: two passes of 3 fewer through LDS for every pair of 3s
+template <> struct Dft<9> {
+  __device__ __forceinline__ static void run(cf *a) { dft_two_factor<3, 3>(a); }
 };
 
 // ---------------------------------------------------------------------------

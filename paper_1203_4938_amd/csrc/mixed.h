@@ -1,4 +1,4 @@
-// Runtime-radix (mixed 2/3/4/5/7/8/16) Stockham transforms: argument blocks
+// Runtime-radix (mixed 2/3/4/5/7/8/9/16) Stockham transforms: argument blocks
 // shared by the host planner and the device code.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -39,8 +39,9 @@ struct MixedArgs {
 };
 
 // Host: radix sequence for a 7-smooth L.  order 0: 16s, then 8/4/2, then 7,
-// 5, 3; order 1: 7, 5, 3 first, then the powers of two.  Returns false if L
-// has a prime factor above 7 or needs too many passes.
+// 5, 9 (pairs of 3), 3; order 1: the odd radices first, then the powers of
+// two.  Returns false if L has a prime factor above 7 or needs too many
+// passes.
 bool mixed_radices(int64_t L, MixedPlan *mp, int order = 0);
 
 // Host: the kernel instance for (map, omap, tw4, swap mode); nullptr if none.

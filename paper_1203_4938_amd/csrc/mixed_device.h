@@ -259,6 +259,7 @@ __device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &
       case 4: PASS(4); break;
       case 5: PASS(5); break;
       case 7: PASS(7); break;
+      case 9: PASS(9); break;
       case 8: PASS(8); break;
       default: PASS(16); break;
     }

@@ -59,9 +59,14 @@ bool mixed_radices(int64_t L, MixedPlan *mp, int order) {
     return true;
   };
   auto push_odd = [&]() {
-    for (int p : {7, 5, 3})
+    for (int p : {7, 5})
       for (int i = 0; i < cnt[p]; ++i)
         if (!push(p)) return false;
+    // pairs of 3s as radix-9 passes (3 x 3 in registers): one LDS exchange
+    // fewer per pair
+    for (int i = 0; i < cnt[3] / 2; ++i)
+      if (!push(9)) return false;
+    if (cnt[3] % 2 && !push(3)) return false;
     return true;
   };
   if (order == 1 && !push_odd()) return false;
