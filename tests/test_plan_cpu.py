@@ -41,6 +41,9 @@ def test_radix_plans_of_mixed_lengths():
     assert "radices=8x5x5x5" in _dry(n=1000, batch=1)
     assert "radices=16x7x3" in _dry(n=336, batch=1)
     assert "radices=7x7x7x7" in _dry(n=2401, batch=1)
+    # pairs of 3s become radix-9 passes, a lone 3 stays
+    assert "radices=9x9x9x9" in _dry(n=6561, batch=1)
+    assert "radices=16x7x5x9x3" in _dry(n=15120, batch=1)
     assert "mixed four-step 49x343" in _dry(n=16807, batch=1)
 
 
