@@ -329,14 +329,16 @@ std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, in
   s->name = name;
   s->tw_off = P->tables.add(stockham_table_pow2(L, s->k.ept));
   s->a.scale = 1.0f;
-  if (s->k.persistent) {
+  // two-level table of w_L (pass twiddles rebuilt in LDS by the kernels whose
+  // LDS holds no per-pass table)
+  {
     std::vector<std::complex<double>> lo, hi;
     const int sh = tw2_shift(ilog2(L));
     fourstep_tables(L, sh, lo, hi);
     lo.insert(lo.end(), hi.begin(), hi.end());
     s->tw2_off = P->tables.add(lo);
-    s->resident = resident_workgroups(s->k);
   }
+  if (s->k.persistent) s->resident = resident_workgroups(s->k);
   return s;
 }
 

@@ -277,6 +277,97 @@ constexpr int lds_pairs() {
   return need ? (a > b ? a : b) : 0;
 }
 
+// Pass twiddles of a persistent instance: the whole per-pass table when it
+// fits in LDS next to the tile, else the two-level table (one more product per
+// twiddle).  Returns the LDS entries taken.
+// (The host builds the per-pass table for the 16-elements-per-thread radix
+// plan, so only those instances can take it.)
+template <int L, int C, int MAP, int OMAP, int EPT>
+constexpr bool pf_direct_tw() {
+  return EPT == 16 && (lds_pairs<L, C, MAP, OMAP>() + P2<L>::twoff(P2<L>::NP)) * 8 <= 160 * 1024;
+}
+// Otherwise the two-level table, plus the first twiddle pass's own part of
+// the per-pass table when that still fits.
+template <int L, int EPT>
+constexpr int pf_tw2_entries() {
+  return (1 << tw2_shift(P2<L>::LG)) +
+         ((L >> tw2_shift(P2<L>::LG)) > 0 ? (L >> tw2_shift(P2<L>::LG)) : 1);
+}
+template <int L, int EPT>
+constexpr int pf_first_entries() {
+  return P2<L, EPT>::NP > 1 ? P2<L, EPT>::twoff(2) : 0;
+}
+template <int L, int C, int MAP, int OMAP, int EPT>
+constexpr bool pf_first_tw() {
+  return !pf_direct_tw<L, C, MAP, OMAP, EPT>() && pf_first_entries<L, EPT>() > 0 &&
+         (lds_pairs<L, C, MAP, OMAP>() + pf_tw2_entries<L, EPT>() + pf_first_entries<L, EPT>()) *
+                 8 <= 160 * 1024;
+}
+template <int L, int C, int MAP, int OMAP, int EPT>
+constexpr int pf_tw_entries() {
+  if constexpr (pf_direct_tw<L, C, MAP, OMAP, EPT>()) {
+    return P2<L>::twoff(P2<L>::NP) > 0 ? P2<L>::twoff(P2<L>::NP) : 1;
+  } else if constexpr (pf_first_tw<L, C, MAP, OMAP, EPT>()) {
+    return pf_tw2_entries<L, EPT>() + pf_first_entries<L, EPT>();
+  } else {
+    return pf_tw2_entries<L, EPT>();
+  }
+}
+
+// Pass twiddles of a plain (one tile per workgroup) instance, copied to LDS
+// when that costs no resident workgroup: the whole per-pass table, else (tiles
+// without a re-tiling exchange) the first twiddle pass's part plus the
+// two-level table, else the two-level table alone; otherwise they are read
+// from the table in global memory.  Measured: 4-10% faster for the
+// one-workgroup-per-CU column tiles and the 256-point four-step tiles; the
+// two-level forms made the transposed-row tiles of 4096 9-15% slower (their
+// LDS already carries three exchanges), hence the exclusion.  The copy is
+// published by the barrier of the first exchange, which precedes the first
+// pass with twiddles.
+template <int L, int C, int MAP, int OMAP, int EPT, int NTH>
+struct PlainTw {
+  static constexpr int kLds = 160 * 1024;
+  static constexpr int BASE = lds_pairs<L, C, MAP, OMAP>() * 8;
+  static constexpr int WG0 = (BASE > 0 ? kLds / BASE : 64) < 2048 / NTH ? (BASE > 0 ? kLds / BASE : 64)
+                                                                        : 2048 / NTH;
+  static constexpr bool fits(int entries) {
+    return BASE + entries * 8 <= kLds && kLds / (BASE + entries * 8) >= WG0;
+  }
+  static constexpr int DIRECT_N = EPT == 16 ? P2<L>::twoff(P2<L>::NP) : 0;
+  static constexpr int N2L = pf_tw2_entries<L, EPT>();
+  static constexpr int FIRST_N = pf_first_entries<L, EPT>();
+  // 0: global table, 1: per-pass table, 2: first pass's table + two-level, 3: two-level
+  static constexpr int MODE = P2<L, EPT>::NP < 2                        ? 0
+                              : (DIRECT_N > 0 && fits(DIRECT_N))         ? 1
+                              : OMAP != MAP                              ? 0
+                              : (FIRST_N > 0 && fits(N2L + FIRST_N))     ? 2
+                              : fits(N2L)                                ? 3
+                                                                         : 0;
+  static constexpr int NTW = MODE == 1 ? DIRECT_N : MODE == 2 ? N2L + FIRST_N : MODE == 3 ? N2L : 0;
+  using type = std::conditional_t<
+      MODE == 0, TwTable,
+      std::conditional_t<MODE == 1, TwLdsTable, std::conditional_t<MODE == 2, TwLdsFirst, TwLds2>>>;
+  __device__ static void fill(cf *twl, const LineArgs &a, int tid) {
+    if constexpr (MODE == 1) {
+      for (int i = tid; i < NTW; i += NTH) twl[i] = a.tw[i];
+    } else if constexpr (MODE >= 2) {
+      for (int i = tid; i < NTW; i += NTH) twl[i] = i < N2L ? a.tw2[i] : a.tw[i - N2L];
+    }
+  }
+  __device__ static type make(const cf *twl, const LineArgs &a) {
+    constexpr int NLO = 1 << tw2_shift(P2<L>::LG);
+    if constexpr (MODE == 0) {
+      return TwTable{a.tw};
+    } else if constexpr (MODE == 1) {
+      return TwLdsTable{twl};
+    } else if constexpr (MODE == 2) {
+      return TwLdsFirst{twl + N2L, TwLds2{twl, twl + NLO}};
+    } else {
+      return TwLds2{twl, twl + NLO};
+    }
+  }
+};
+
 // SW bit 0: exchange re/im on load; bit 1: exchange on store (the inverse
 // transform is swap(FFT(swap(x))), so the first launch of an inverse swaps on
 // load and the last one on store).
@@ -324,7 +415,10 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     for (int m = 0; m < E; ++m) v[m] = make_float2(0.0f, 0.0f);
   }
 
-  all_passes<L, EPT, C, MAP>(v, lds, TwTable{a.tw}, c, j,
+  using PT = PlainTw<L, C, MAP, OMAP, EPT, C * G::T>;
+  __shared__ cf twl[PT::NTW > 0 ? PT::NTW : 1];
+  PT::fill(twl, a, tid);
+  all_passes<L, EPT, C, MAP>(v, lds, PT::make(twl, a), c, j,
                              std::make_integer_sequence<int, G::NP>{});
 
   // epilogue in registers: four-step twiddle, inverse scale
@@ -390,43 +484,6 @@ __device__ __forceinline__ void load_tile(cf (&v)[(P2<L, EPT>::E)], const cf *__
     const uint32_t o = (uint32_t)lc + (uint32_t)j * es;
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = ldg<NT>(tin, o + (uint32_t)(T * m) * es);
-  }
-}
-
-// Pass twiddles of a persistent instance: the whole per-pass table when it
-// fits in LDS next to the tile, else the two-level table (one more product per
-// twiddle).  Returns the LDS entries taken.
-// (The host builds the per-pass table for the 16-elements-per-thread radix
-// plan, so only those instances can take it.)
-template <int L, int C, int MAP, int OMAP, int EPT>
-constexpr bool pf_direct_tw() {
-  return EPT == 16 && (lds_pairs<L, C, MAP, OMAP>() + P2<L>::twoff(P2<L>::NP)) * 8 <= 160 * 1024;
-}
-// Otherwise the two-level table, plus the first twiddle pass's own part of
-// the per-pass table when that still fits.
-template <int L, int EPT>
-constexpr int pf_tw2_entries() {
-  return (1 << tw2_shift(P2<L>::LG)) +
-         ((L >> tw2_shift(P2<L>::LG)) > 0 ? (L >> tw2_shift(P2<L>::LG)) : 1);
-}
-template <int L, int EPT>
-constexpr int pf_first_entries() {
-  return P2<L, EPT>::NP > 1 ? P2<L, EPT>::twoff(2) : 0;
-}
-template <int L, int C, int MAP, int OMAP, int EPT>
-constexpr bool pf_first_tw() {
-  return !pf_direct_tw<L, C, MAP, OMAP, EPT>() && pf_first_entries<L, EPT>() > 0 &&
-         (lds_pairs<L, C, MAP, OMAP>() + pf_tw2_entries<L, EPT>() + pf_first_entries<L, EPT>()) *
-                 8 <= 160 * 1024;
-}
-template <int L, int C, int MAP, int OMAP, int EPT>
-constexpr int pf_tw_entries() {
-  if constexpr (pf_direct_tw<L, C, MAP, OMAP, EPT>()) {
-    return P2<L>::twoff(P2<L>::NP) > 0 ? P2<L>::twoff(P2<L>::NP) : 1;
-  } else if constexpr (pf_first_tw<L, C, MAP, OMAP, EPT>()) {
-    return pf_tw2_entries<L, EPT>() + pf_first_entries<L, EPT>();
-  } else {
-    return pf_tw2_entries<L, EPT>();
   }
 }
 
@@ -582,7 +639,9 @@ struct LineEntry {
 #define ENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                  \
   LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * P2<L_, KEPT>::T,            \
             (int)sizeof(cf) * lds_pairs<L_, C_, M_, O_>() +                         \
-                (KPF ? (int)sizeof(cf) * pf_tw_entries<L_, C_, M_, O_, KEPT>() : 0), \
+                (int)sizeof(cf) * (KPF ? pf_tw_entries<L_, C_, M_, O_, KEPT>()        \
+                                       : PlainTw<L_, C_, M_, O_, KEPT,                \
+                                                 C_ * P2<L_, KEPT>::T>::NTW),         \
             KPF, KPREF, KEPT}
 
 // rows: forward, inverse single pass (swap in+out), 2D row pass inverse (swap in)
