@@ -289,5 +289,18 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
   if (bid >= full) return bid;
   return (bid % X) * (nblocks / X) + bid / X;
 }
+// The same in rounds: each round of 256 consecutive tiles gives every XCD 32
+// consecutive ones (one per CU), so the tiles in flight sweep whole rows of the
+// matrix together (DRAM page locality) while tiles sharing cache lines still
+// share an L2.  Measured on the power-of-two line and MFMA kernels: 4-11%
+// faster for the 256 x 256 four-step, the 4096-point column tiles of 2D
+// images and the transposed-row tiles of 2048 and 4096.  Falls back to
+// xcd_remap when the grid is not a whole number of rounds.
+__device__ __forceinline__ uint32_t xcd_remap_rounds(uint32_t bid, uint32_t nblocks) {
+  constexpr uint32_t X = 8, K = 32;
+  if (nblocks % (X * K) != 0) return xcd_remap(bid, nblocks);
+  const uint32_t slot = bid / X;
+  return (slot / K) * (X * K) + (bid % X) * K + slot % K;
+}
 
 }  // namespace dpfft

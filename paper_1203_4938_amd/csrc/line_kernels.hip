@@ -387,7 +387,9 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   const int tid = threadIdx.x;
   int c, j;
   lane_map<L, EPT, C, MAP>(tid, c, j);
-  const uint32_t tile = (a.flags & F_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const uint32_t tile = !(a.flags & F_REMAP)  ? blockIdx.x
+                        : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x)
+                                               : xcd_remap(blockIdx.x, gridDim.x);
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (int64_t)(tile - bb * a.tiles_per_batch) * C;
   const int64_t line = line0 + c;
