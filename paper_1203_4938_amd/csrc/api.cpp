@@ -401,15 +401,11 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   // four-step: N = N1 * N2, x[n1*N2 + n2]; pass A: N1-point column FFTs
   // (stride N2) and twiddle w_N^{n2 k1} into the workspace Y[k1][n2]; pass B:
   // N2-point FFTs along the rows of Y, stored transposed: X[k1 + N1 k2].
-  // Default split: N1 = N2 (or N2 = 2 N1), except that above 2^21 the rows
-  // become N2 = 1024 when columns of 2^(lg-10) have a kernel: 1024-point
-  // transposed rows run as a persistent 32-element tile at 5.3 TB/s, and the
-  // pair measured 3% faster than 2048 x 2048, whose tiles hold only 8 lines
-  // (64-byte segments) in one CU's LDS.
+  // Default split: N1 = N2 (or N2 = 2 N1).  For 2^22, 2048 x 2048 measured
+  // 1.5% faster than 4096 x 1024 (and steadier) and 2% faster than
+  // 1024 x 4096; the tuner tries all three (override s=).
   const int lg = ilog2(N);
   int lg1 = lg / 2;
-  if (lg1 > 10 && list_line_kernels(1 << (lg - 10), LINE_FAST, LINE_FAST, true, nullptr, 0) > 0)
-    lg1 = lg - 10;
   if (ov.split > 0 && ov.split < lg) lg1 = ov.split;
   const int N1 = 1 << lg1, N2 = 1 << (lg - lg1);
   auto a = make_line(P, "fourstep_columns", N1, LINE_FAST, LINE_FAST, true, 16, 0, B * N2, ov);

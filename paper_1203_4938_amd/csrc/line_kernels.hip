@@ -17,9 +17,10 @@
 // registers holding j + T*m, which is also the coalesced order of the load,
 // so the first load and the last store go straight between HBM and VGPRs.
 //
-// Twiddles of pass p >= 1 are read from a per-length table built on the host
-// in FP64: entry (r-1)*Ns + k holds w_{Ns R}^{k r}, consecutive k for
-// consecutive lanes.
+// Twiddles of pass p >= 1 come from a per-length table built on the host in
+// FP64: entry (r-1)*Ns + k holds w_{Ns R}^{k r}, consecutive k for
+// consecutive lanes.  Where LDS has room next to the tile, the kernels copy
+// it (or its first pass's part plus a two-level table of w_L) to LDS first.
 #include <type_traits>
 
 #include "fft_common.h"

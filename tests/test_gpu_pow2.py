@@ -187,8 +187,8 @@ VARIANTS = [
     # persistent 1024-thread instances
     (16384, 300, "p0=1 t0=1024"), (16384, 7, "p0=0"), (4096, 9, "c0=2 p0=0"),
     (1 << 20, 3, "p0=1 t0=1024"), (1 << 20, 3, "p0=0"),
-    # other four-step splits of 2^22 (2048 x 2048, 1024 x 4096)
-    (1 << 22, 1, "s=11"), (1 << 22, 1, "s=10"),
+    # other four-step splits of 2^22 (4096 x 1024, 1024 x 4096)
+    (1 << 22, 1, "s=12"), (1 << 22, 1, "s=10"),
     # 32 elements per thread, radix-32 passes
     (16384, 11, "p0=1 t0=512"), (8192, 7, "p0=1 t0=256"), (8192, 5, "p0=0"),
     # persistent column and transposed-row tiles with 32 elements per thread
@@ -197,7 +197,7 @@ VARIANTS = [
     (1024, 37, "c0=8 t0=256"), (1024, 37, "c0=16 t0=512 p0=0"), (1024, 37, "p0=1 t0=512"),
     (1 << 18, 3, "c0=16 t0=256 p0=0 c1=16 t1=256 p1=0"), (1 << 18, 3, "t0=512"),
     (1024, 37, "c0=4 p0=0"), (4096, 9, "c0=1"), (1 << 22, 2, "s=10 p1=1 t1=512"), (1 << 20, 3, "p1=0"),
-    (1 << 18, 3, "p0=0 p1=0"), (1 << 22, 2, "p0=1 t0=512"),
+    (1 << 18, 3, "p0=0 p1=0"), (1 << 22, 2, "s=12 p0=1 t0=512"),
     (1 << 18, 3, "c0=32 t0=512 p0=0 c1=32 t1=512 p1=0"),
     (1 << 18, 3, "p0=1 c0=32 t0=512 p1=1 c1=32 t1=512"), (1 << 18, 3, "p0=1 c0=16 t0=256 p1=1 c1=16 t1=256"),
 ]

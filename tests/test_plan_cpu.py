@@ -27,7 +27,7 @@ def _dry(**kw):
 @pytest.mark.parametrize("n,variant,launches", [
     (1, "single-pass", 1), (4096, "single-pass", 1), (16384, "single-pass", 1),
     (1 << 15, "four-step 128x256", 2), (1 << 18, "four-step 512x512", 2),
-    (1 << 22, "four-step 4096x1024", 2), (1 << 24, "four-step 4096x4096", 2),
+    (1 << 22, "four-step 2048x2048", 2), (1 << 24, "four-step 4096x4096", 2),
     (1000, "mixed single-pass", 1), (15625, "mixed single-pass", 1),
     (78125, "mixed four-step 125x625", 2), (3 ** 15, "mixed four-step 2187x6561", 2),
 ])
