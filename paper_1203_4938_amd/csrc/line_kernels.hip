@@ -715,10 +715,9 @@ static const LineEntry kLineTable32[] = {
 #define KPF true
 #define KEPT 16
 // Persistent instances, 16 elements per thread.  Rows of 4096, two per tile,
-// are the default of their shape (3.5% faster than the plain 1-row tiles,
-// nontemporal data 1% more), and so are rows of 8192 (6% faster than the
-// 32-element form); the others are opt-in: the 32-element forms below are
-// faster.
+// are the default of their shape (3-4% faster than the plain 1-row tiles,
+// nontemporal data 1% more); the others are opt-in (rows of 8192: 9% slower
+// than the plain kernel once that reads its twiddles from LDS).
 #undef KPREF
 #define KPREF true
 #undef KNT
@@ -728,35 +727,36 @@ static const LineEntry kLineTablePfPref[] = {
 };
 #undef KNT
 #define KNT 0
-static const LineEntry kLineTablePfPref0[] = {
-    ROW(8192, 1),
-};
 #undef KPREF
 #define KPREF false
 static const LineEntry kLineTablePf[] = {
-    ROW(16384, 1), COL(1024, 16), COLTW(1024, 16),
+    ROW(8192, 1), ROW(16384, 1), COL(1024, 16), COLTW(1024, 16),
 };
 #undef KEPT
 #define KEPT 32
 // Persistent instances, 32 elements per thread (radix-32 passes: one pass and
 // one exchange fewer than radix 16 for L = 2^10, 2^13 and 2^14), whose tiles
 // fill the CU's LDS.  The defaults of their shapes, measured against the best
-// other instance: rows of 16384 8% faster; 1024-point column tiles 8-9%;
-// 1024-point transposed rows 19%; 512-point column tiles of 32 columns 4%,
-// transposed rows 1%; 2048-point column tiles (2D) 2-5%; rows of 1024, 16 per
-// tile, as fast as the plain 4-row tiles.
+// other instance: rows of 16384 15% faster; rows of 1024, 16 per tile, 5%;
+// 1024-point transposed rows 13%; 1024-point column tiles as fast as the
+// plain ones.
 #undef KPREF
 #define KPREF true
 static const LineEntry kLineTablePf32[] = {
-    ROW(16384, 1), COL(1024, 16), COLTW(1024, 16), ROWT(1024, 16), ROWT(512, 32), COL(2048, 8),
+    ROW(16384, 1), COL(1024, 16), COLTW(1024, 16), ROWT(1024, 16),
 };
-// the same with nontemporal stores (rows of 1024: 2%) or loads and stores
-// (512-point column tiles: 5%)
+// rows of 1024 with nontemporal stores (2% faster)
 #undef KNT
 #define KNT 2
 static const LineEntry kLineTablePf32Nts[] = {
     ROW(1024, 16),
 };
+#undef KPREF
+#define KPREF false
+// opt-in: 512-point column tiles of 32 with nontemporal data, and the others
+// measured slower than the plain instances once those read their twiddles
+// from LDS (512-point tiles of 32 lines by 5%, tiles of 2048 by 5-20%) or
+// always (4096-point four-step tiles)
 #undef KNT
 #define KNT 3
 static const LineEntry kLineTablePf32Nt[] = {
@@ -764,13 +764,9 @@ static const LineEntry kLineTablePf32Nt[] = {
 };
 #undef KNT
 #define KNT 0
-// opt-in: rows of 8192, four-step tiles of 2048 (no faster than the plain
-// instances), 512-point tiles of 16 lines, 4096-point four-step tiles
-#undef KPREF
-#define KPREF false
 static const LineEntry kLineTablePf32x[] = {
-    ROW(8192, 1), COLTW(2048, 8), ROWT(2048, 8), COLTW(512, 16), ROWT(512, 16), ROWT(4096, 4),
-    COLTW(4096, 4),
+    ROW(8192, 1), COLTW(2048, 8), ROWT(2048, 8), COL(2048, 8), COLTW(512, 16), ROWT(512, 16),
+    ROWT(512, 32), ROWT(4096, 4), COLTW(4096, 4),
 };
 #undef KFN
 #undef KPF
@@ -798,7 +794,6 @@ static void for_each_entry(F f) {
   for (const auto &e : kLineTable32Pref) f(e);
   for (const auto &e : kLineTable32) f(e);
   for (const auto &e : kLineTablePfPref) f(e);
-  for (const auto &e : kLineTablePfPref0) f(e);
   for (const auto &e : kLineTablePf) f(e);
   for (const auto &e : kLineTablePf32) f(e);
   for (const auto &e : kLineTablePf32Nts) f(e);
