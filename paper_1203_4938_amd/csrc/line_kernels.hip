@@ -279,10 +279,10 @@ constexpr int lds_pairs() {
 }
 
 // Pass twiddles of a persistent instance: the whole per-pass table when it
-// fits in LDS next to the tile, else the two-level table (one more product per
-// twiddle).  Returns the LDS entries taken.
-// (The host builds the per-pass table for the 16-elements-per-thread radix
-// plan, so only those instances can take it.)
+// fits in LDS next to the tile (taken for 16-element instances only: a
+// 32-element tile of 512 or 1024 points has a single twiddle pass, which the
+// first-pass table below covers, and the longer ones do not fit), else the
+// two-level table (one more product per twiddle).
 template <int L, int C, int MAP, int OMAP, int EPT>
 constexpr bool pf_direct_tw() {
   return EPT == 16 && (lds_pairs<L, C, MAP, OMAP>() + P2<L>::twoff(P2<L>::NP)) * 8 <= 160 * 1024;
