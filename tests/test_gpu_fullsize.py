@@ -1,7 +1,8 @@
 """Parity at the benchmark's full sizes, in the plans the benchmark times.
 
-The c2 batches (N = 2^10 ... 2^22, batch*N = 2^27) and the c3 image batch
-(16 x 2048^2) are generated and transformed exactly as the benchmark does;
+The c2 batches (N = 2^10 ... 2^22, batch*N = 2^27), the FP32 c4 batch
+(N = 2^16 x 4096) and the c3 image batch (16 x 2048^2) are generated and
+transformed exactly as the benchmark does;
 the oracle then recomputes a seeded sample of whole signals (first, last and
 random ones) one by one, and the inverse of the full output must return the
 input on those signals."""
@@ -45,6 +46,32 @@ def test_c2_full_batch_sampled(n, b, k):
         r = max_rel(z[s:s + 1].cpu().numpy(), xs.astype(np.complex128))
         say(f"   signal {s}: forward rel L2 {e:.3e}, round trip {r:.3e}")
         assert e <= TOL_FP32 and r <= TOL_FP32, (n, s, e, r)
+
+
+def test_c4_fp32_full_batch_sampled():
+    """C4 shape (N = 2^16, batch 4096, 2 GiB) in FP32, in the launch
+    configuration the benchmark times (65536 tiles per pass, the round-based
+    tile order); a seeded sample of whole signals against the oracle."""
+    import torch
+
+    import paper_1203_4938_amd as dp
+    n, b = 1 << 16, 4096
+    seed = synth.BASE_SEED + 4
+    say(f"[full c4 fp32] n={n} batch={b}")
+    x = synth.uniform_complex_torch(seed, n, b, "cuda")
+    p = dp.Plan(n, b)
+    say("   plan:", p.describe().replace("\n", " | "))
+    y = p.exec(x)
+    z = p.exec(y, inverse=True)
+    torch.cuda.synchronize()
+    for s in _sample(b, 5, 4242):
+        xs = synth.uniform_complex(seed, n, 1, first=s)
+        e = max_rel(y[s:s + 1].cpu().numpy(), oracle.fft_batch(xs))
+        r = max_rel(z[s:s + 1].cpu().numpy(), xs.astype(np.complex128))
+        say(f"   signal {s}: forward rel L2 {e:.3e}, round trip {r:.3e}")
+        assert e <= TOL_FP32 and r <= TOL_FP32, (s, e, r)
+    del x, y, z
+    torch.cuda.empty_cache()
 
 
 def test_c3_full_batch_sampled():
