@@ -47,23 +47,26 @@ def test_mfma_bf16_plain(n, batch):
         pytest.xfail(f"plain BF16 rel L2 {e:.2e} exceeds the 2e-3 bound (8-bit significands)")
 
 
-def test_mfma_c4_sampled_full_size():
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp16_split", "bf16_split", "bf16_split3"])
+def test_mfma_c4_sampled_full_size(prec):
     """C4 shape (N=2^16, batch 4096) in the launch configuration the benchmark
-    times: sampled signals against the oracle, for the FP16 split form."""
+    times: sampled signals against the oracle, for each matrix-core form.  Plain
+    BF16 is held to its sanity bound (its 2e-3 miss is recorded above)."""
     import torch
 
     import paper_1203_4938_amd as dp
     n, batch = 1 << 16, 4096
-    w = synth.workloads()["c4_n2^16_b4096_fp16_split"]
+    w = synth.workloads()[f"c4_n2^16_b4096_{prec}"]
     x = synth.uniform_complex_torch(w.seed, n, batch, "cuda")
-    p = dp.Plan(n, batch, precision="fp16_split")
+    p = dp.Plan(n, batch, precision=prec)
     y = run_plan(p, x)
+    tol = SANITY.get(prec, TOL[prec])
     for b in (0, 1, 2047, 4095):
         xs = synth.uniform_complex(w.seed, n, 1, first=b)
         ref = oracle.fft_batch(xs)
         e = max_rel(y[b:b + 1].cpu().numpy(), ref)
-        say(f"   signal {b}: rel L2 {e:.3e}")
-        assert e <= TOL["fp16_split"]
+        say(f"   [{prec}] signal {b}: rel L2 {e:.3e}")
+        assert e <= tol, (prec, b, e)
     del x, y
     torch.cuda.empty_cache()
 
