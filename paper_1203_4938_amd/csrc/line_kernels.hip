@@ -21,6 +21,7 @@
 // FP64: entry (r-1)*Ns + k holds w_{Ns R}^{k r}, consecutive k for
 // consecutive lanes.  Where LDS has room next to the tile, the kernels copy
 // it (or its first pass's part plus a two-level table of w_L) to LDS first.
+#include <numeric>
 #include <type_traits>
 
 #include "fft_common.h"
@@ -42,6 +43,18 @@ template <int L, int C, int MAP, int PADSH> struct Lds {
       int u = pos * C + c;
       return u + (u >> PADSH);
     }
+  }
+  // idx(c, pos + d) for an offset d that is constant once the caller's loop
+  // is unrolled: d is split as d0 + d1 with d1's share of the flat index a
+  // multiple of the padding period, so idx(c, pos + d1 + d0) = idx(c, pos + d0)
+  // + d1's padded share exactly.  Offsets with the same d0 share one base, and
+  // the rest folds into the LDS instruction's immediate offset.
+  __device__ __forceinline__ static int idx_off(int c, int pos, int d) {
+    constexpr int U = (MAP == ELEM_FAST) ? 1 : C;  // flat-index units per position
+    constexpr int PER = 1 << PADSH;
+    constexpr int P = PER / std::gcd(U, PER);      // smallest p with p * U % PER == 0
+    const int d0 = d % P, d1u = (d - d0) * U;
+    return idx(c, pos + d0) + d1u + (d1u >> PADSH);
   }
 };
 
@@ -151,11 +164,17 @@ __device__ __forceinline__ void stockham_pass(cf (&v)[(P2<L, EPT>::E)], cf *lds,
   if constexpr (!LAST) {
     auto wpos = [&](int m) {
       const int q = m % QN, r = m / QN;
-      const int b = j + T * q;
-      const int k = b & (NS - 1);
-      return LD::idx(c, (b - k) * R + k + r * NS);
+      if constexpr (T % NS == 0) {
+        // k = b mod NS is the same for every butterfly of the thread
+        const int k = j & (NS - 1);
+        return LD::idx_off(c, (j - k) * R + k, T * q * R + r * NS);
+      } else {
+        const int b = j + T * q;
+        const int k = b & (NS - 1);
+        return LD::idx(c, (b - k) * R + k + r * NS);
+      }
     };
-    auto rpos = [&](int m) { return LD::idx(c, j + T * m); };
+    auto rpos = [&](int m) { return LD::idx_off(c, j, T * m); };
     lds_exchange<E, true>(v, lds, wpos, rpos);
   }
 }
@@ -436,8 +455,8 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     // re-tile through LDS so the store is coalesced in the output layout
     lane_map<L, EPT, C, OMAP>(tid, c2, j2);
     line2 = line0 + c2;
-    auto wpos = [&](int m) { return LO::idx(c, j + T * m); };
-    auto rpos = [&](int m) { return LO::idx(c2, j2 + T * m); };
+    auto wpos = [&](int m) { return LO::idx_off(c, j, T * m); };
+    auto rpos = [&](int m) { return LO::idx_off(c2, j2, T * m); };
     lds_exchange<E, false>(v, lds, wpos, rpos);
   }
   if (line2 < a.lines) {
@@ -590,8 +609,8 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
     int c2 = c, j2 = j;
     if constexpr (OMAP != MAP) {
       lane_map<L, EPT, C, OMAP>(tid, c2, j2);
-      auto wpos = [&](int m) { return LO::idx(c, j + T * m); };
-      auto rpos = [&](int m) { return LO::idx(c2, j2 + T * m); };
+      auto wpos = [&](int m) { return LO::idx_off(c, j, T * m); };
+      auto rpos = [&](int m) { return LO::idx_off(c2, j2, T * m); };
       lds_exchange<E, true>(v, lds, wpos, rpos);
     }
     // Lanes past the last line of a ragged last tile hold that line's results
