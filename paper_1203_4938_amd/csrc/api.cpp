@@ -245,7 +245,7 @@ std::string MfmaStep::describe() const {
   static const char *names[] = {"fp32", "fp16", "bf16", "fp16_split", "bf16_split", "bf16_split3"};
   std::ostringstream o;
   o << name << ": L=256 (DFT-16 x DFT-16 on MFMA, " << names[prec] << ") C=" << kMfmaLines
-    << " threads=" << kMfmaThreads << " grid=" << grid.x << " lds=" << mfma_lds_bytes() << "B";
+    << " threads=" << kMfmaThreads << " grid=" << grid.x << " lds=" << mfma_lds_bytes(prec) << "B";
   return o.str();
 }
 

@@ -43,6 +43,6 @@ const void *mfma_kernel(int prec, int map, int omap, bool tw4, int sw);
 // Threads and lines per workgroup of the MFMA instances, and their LDS bytes.
 constexpr int kMfmaThreads = 256;
 constexpr int kMfmaLines = 16;
-int mfma_lds_bytes();
+int mfma_lds_bytes(int prec);
 
 }  // namespace dpfft

@@ -133,15 +133,22 @@ __device__ __forceinline__ void dft16_stage(const typename Piece<base_of<PREC>()
 
 // C = 16 lines of 256 points per workgroup of 256 threads (4 waves, 4 lines
 // each).  The tile is loaded coalesced into LDS, each wave runs the two MFMA
-// stages of its lines (the stage-1 result goes through a per-wave LDS scratch
-// to reach the B layout of stage 2), and the tile is stored coalesced.
+// stages of its lines, and the tile is stored coalesced.  The stage-1 result
+// reaches the B layout of stage 2 through the line's own LDS region: a wave
+// alone owns its lines, and an MFMA issues only once every lane's operands
+// (the reads of the whole line) are in registers, so its results may
+// overwrite the line.  Without a scratch buffer beside the tile four
+// workgroups fit a CU instead of three: plain forms 4% faster, two-piece
+// forms 1%.  The three-piece form, bound by its six products per stage,
+// measured 2% slower so and keeps a per-wave scratch buffer.
 template <int PREC, int MAP, int OMAP, bool TW4, int SW>
 __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__ in,
                                                           cf *__restrict__ out, MfmaArgs a) {
   constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
   constexpr int C = kMfmaLines;
+  constexpr bool SCRATCH = NPC == 3;
   __shared__ cf tile[C * kPitch];
-  __shared__ cf scratch[4][16 * 17];
+  __shared__ cf scratch[SCRATCH ? 4 : 1][SCRATCH ? 16 * 17 : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tileid = !(a.flags & F_REMAP)  ? blockIdx.x
@@ -164,6 +171,33 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
   cf tw[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) tw[t] = a.tw16[(4 * g4 + t) * 16 + col];
+
+  // four-step twiddle bases of the wave's lines, A = w_N^{line (col + 64 g4)}
+  // and S = w_N^{16 line}, multiplied out where they are used.  Their table
+  // entries are loaded ahead of the tile, so they arrive with it (split forms
+  // 2% faster); the three-piece form, whose registers would then no longer
+  // allow four waves per SIMD, loads them after the tile.
+  constexpr bool TW4_EARLY = NPC < 3;
+  cf tAh[C / 4], tAl[C / 4], tSh[C / 4], tSl[C / 4];  // early: table entries
+  cf tA[C / 4], tS[C / 4];                           // late: the bases
+  auto tw4_parts = [&]() {
+    const uint32_t m = (1u << a.tw4_shift) - 1u;
+#pragma unroll
+    for (int u = 0; u < C / 4; ++u) {
+      const uint32_t line = (uint32_t)(line0 + wave * (C / 4) + u);
+      const uint32_t e0 = line * (uint32_t)(col + 64 * g4), e1 = line * 16u;
+      if constexpr (TW4_EARLY) {
+        tAh[u] = a.tw4_hi[e0 >> a.tw4_shift];
+        tAl[u] = a.tw4_lo[e0 & m];
+        tSh[u] = a.tw4_hi[e1 >> a.tw4_shift];
+        tSl[u] = a.tw4_lo[e1 & m];
+      } else {
+        tA[u] = cmul(a.tw4_hi[e0 >> a.tw4_shift], a.tw4_lo[e0 & m]);
+        tS[u] = cmul(a.tw4_hi[e1 >> a.tw4_shift], a.tw4_lo[e1 & m]);
+      }
+    }
+  };
+  if constexpr (TW4 && TW4_EARLY) tw4_parts();
 
   // ---- load the tile (C lines x 256) coalesced, into LDS ----
   {
@@ -188,21 +222,7 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
   __syncthreads();
 
   const int part = g4 >> 1, kb = 8 * (g4 & 1);
-  cf *scr = scratch[wave];
-  // four-step twiddle bases of the wave's lines, loaded before the first
-  // stage so that no stage waits on them: A = w_N^{line (col + 64 g4)},
-  // S = w_N^{16 line}
-  cf tA[C / 4], tS[C / 4];
-  if constexpr (TW4) {
-    const uint32_t m = (1u << a.tw4_shift) - 1u;
-#pragma unroll
-    for (int u = 0; u < C / 4; ++u) {
-      const uint32_t line = (uint32_t)(line0 + wave * (C / 4) + u);
-      const uint32_t e0 = line * (uint32_t)(col + 64 * g4), e1 = line * 16u;
-      tA[u] = cmul(a.tw4_hi[e0 >> a.tw4_shift], a.tw4_lo[e0 & m]);
-      tS[u] = cmul(a.tw4_hi[e1 >> a.tw4_shift], a.tw4_lo[e1 & m]);
-    }
-  }
+  if constexpr (TW4 && !TW4_EARLY) tw4_parts();
 #pragma unroll
   for (int u = 0; u < C / 4; ++u) {
     const int c = wave * (C / 4) + u;
@@ -215,7 +235,10 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
     }
     f32x4 dre, dim;
     dft16_stage<PREC>(are, aim, xv, dre, dim);
-    // D: column n2 = col, rows k1 = 4 g4 + t -> twiddle, to scratch[k1][n2]
+    // D: column n2 = col, rows k1 = 4 g4 + t -> twiddle, to Y[k1][n2] at
+    // position 16 k1 + n2 of the line, or of the wave's scratch buffer (pitch
+    // 17 per k1 row either way)
+    cf *scr = SCRATCH ? scratch[wave] : tile + c * kPitch;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const cf y = cmul(make_float2(dre[t], dim[t]), tw[t]);
@@ -238,7 +261,14 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
     for (int t = 0; t < 4; ++t) y4[t] = make_float2(dre[t], dim[t]);
     if constexpr (TW4) {
       // w_N^{line k}, k = col + 16 (4 g4 + t) = A S^t
-      const cf A = tA[u], S = tS[u];
+      cf A, S;
+      if constexpr (TW4_EARLY) {
+        A = cmul(tAh[u], tAl[u]);
+        S = cmul(tSh[u], tSl[u]);
+      } else {
+        A = tA[u];
+        S = tS[u];
+      }
       const cf S2 = cmul(S, S);
       y4[0] = cmul(y4[0], A);
       y4[1] = cmul(y4[1], cmul(A, S));
@@ -251,9 +281,12 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
       if (SW & 2) y = cswap(cscale(y, a.scale));
       tile[tidx(c, col + 16 * (4 * g4 + t))] = y;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if constexpr (SCRATCH) {
+      // the next line's stage 1 reuses the scratch buffer
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
   __syncthreads();
 
@@ -271,7 +304,9 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
   }
 }
 
-int mfma_lds_bytes() { return (int)sizeof(cf) * (kMfmaLines * kPitch + 4 * 16 * 17); }
+int mfma_lds_bytes(int prec) {
+  return (int)sizeof(cf) * (kMfmaLines * kPitch + (mfma_pieces(prec) == 3 ? 4 * 16 * 17 : 1));
+}
 
 const void *mfma_kernel(int prec, int map, int omap, bool tw4, int sw) {
 #define MK2(P)                                                                                 \
