@@ -172,29 +172,25 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
 #pragma unroll
   for (int t = 0; t < 4; ++t) tw[t] = a.tw16[(4 * g4 + t) * 16 + col];
 
-  // four-step twiddle bases of the wave's lines, A = w_N^{line (col + 64 g4)}
-  // and S = w_N^{16 line}, multiplied out where they are used.  Their table
-  // entries are loaded ahead of the tile, so they arrive with it (split forms
-  // 2% faster); the three-piece form, whose registers would then no longer
-  // allow four waves per SIMD, loads them after the tile.
+  // four-step twiddle bases of the wave's lines l = l0 + u (u < C/4):
+  // A_u = w_N^{l (col + 64 g4)} and S_u = w_N^{16 l}, multiplied out where
+  // they are used.  Only the first line's bases are looked up; the others
+  // follow as A_u = A_{u-1} D and S_u = S_{u-1} G with D = w_N^{col + 64 g4}
+  // and G = w_N^{16} (at most three products each), so a lane reads two
+  // scattered table pairs per tile instead of one per line.  The table
+  // entries are loaded ahead of the tile, so they arrive with it; the
+  // three-piece form, whose registers would then no longer allow four waves
+  // per SIMD, loads them after the tile.
   constexpr bool TW4_EARLY = NPC < 3;
-  cf tAh[C / 4], tAl[C / 4], tSh[C / 4], tSl[C / 4];  // early: table entries
-  cf tA[C / 4], tS[C / 4];                           // late: the bases
+  cf tw4e[8];  // A0 hi/lo, D hi/lo, S0 hi/lo, G hi/lo
   auto tw4_parts = [&]() {
     const uint32_t m = (1u << a.tw4_shift) - 1u;
+    const uint32_t l0 = (uint32_t)(line0 + wave * (C / 4));
+    const uint32_t e[4] = {l0 * (uint32_t)(col + 64 * g4), (uint32_t)(col + 64 * g4), l0 * 16u, 16u};
 #pragma unroll
-    for (int u = 0; u < C / 4; ++u) {
-      const uint32_t line = (uint32_t)(line0 + wave * (C / 4) + u);
-      const uint32_t e0 = line * (uint32_t)(col + 64 * g4), e1 = line * 16u;
-      if constexpr (TW4_EARLY) {
-        tAh[u] = a.tw4_hi[e0 >> a.tw4_shift];
-        tAl[u] = a.tw4_lo[e0 & m];
-        tSh[u] = a.tw4_hi[e1 >> a.tw4_shift];
-        tSl[u] = a.tw4_lo[e1 & m];
-      } else {
-        tA[u] = cmul(a.tw4_hi[e0 >> a.tw4_shift], a.tw4_lo[e0 & m]);
-        tS[u] = cmul(a.tw4_hi[e1 >> a.tw4_shift], a.tw4_lo[e1 & m]);
-      }
+    for (int q = 0; q < 4; ++q) {
+      tw4e[2 * q] = a.tw4_hi[e[q] >> a.tw4_shift];
+      tw4e[2 * q + 1] = a.tw4_lo[e[q] & m];
     }
   };
   if constexpr (TW4 && TW4_EARLY) tw4_parts();
@@ -223,6 +219,13 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
 
   const int part = g4 >> 1, kb = 8 * (g4 & 1);
   if constexpr (TW4 && !TW4_EARLY) tw4_parts();
+  cf A, S, Dw, Gw;  // bases of the current line and their steps
+  if constexpr (TW4) {
+    A = cmul(tw4e[0], tw4e[1]);
+    Dw = cmul(tw4e[2], tw4e[3]);
+    S = cmul(tw4e[4], tw4e[5]);
+    Gw = cmul(tw4e[6], tw4e[7]);
+  }
 #pragma unroll
   for (int u = 0; u < C / 4; ++u) {
     const int c = wave * (C / 4) + u;
@@ -261,19 +264,13 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
     for (int t = 0; t < 4; ++t) y4[t] = make_float2(dre[t], dim[t]);
     if constexpr (TW4) {
       // w_N^{line k}, k = col + 16 (4 g4 + t) = A S^t
-      cf A, S;
-      if constexpr (TW4_EARLY) {
-        A = cmul(tAh[u], tAl[u]);
-        S = cmul(tSh[u], tSl[u]);
-      } else {
-        A = tA[u];
-        S = tS[u];
-      }
       const cf S2 = cmul(S, S);
       y4[0] = cmul(y4[0], A);
       y4[1] = cmul(y4[1], cmul(A, S));
       y4[2] = cmul(y4[2], cmul(A, S2));
       y4[3] = cmul(y4[3], cmul(A, cmul(S2, S)));
+      A = cmul(A, Dw);  // the next line's bases
+      S = cmul(S, Gw);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
