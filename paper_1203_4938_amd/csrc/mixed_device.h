@@ -119,11 +119,20 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
   // all loads of the pass first (one branch on the source for the whole
   // pass), so every butterfly's data is in flight before the first one is
   // computed
+  // k = b mod NS for b = j + T q: one division per pass, then a step of
+  // T mod NS (a scalar) and a conditional subtraction per butterfly
+  {
+    const int k0 = NS > 1 ? j % NS : 0;
+    const int tstep = NS > 1 ? T % NS : 0;
+    int k = k0;
 #pragma unroll
-  for (int q = 0; q < QM; ++q) {
-    const int b = j + T * q;
-    act[q] = valid && b < M;
-    kq[q] = NS > 1 ? b % NS : 0;
+    for (int q = 0; q < QM; ++q) {
+      const int b = j + T * q;
+      act[q] = valid && b < M;
+      kq[q] = k;
+      k += tstep;
+      if (k >= NS) k -= NS;
+    }
   }
   if (first) {
 #pragma unroll
