@@ -90,7 +90,11 @@ __device__ __forceinline__ void split8(const float (&x)[8],
     for (int q = 0; q < NPC; ++q) {
       const auto h = Piece<B>::cvt(r);
       p[q][t] = h;
-      r = (r - Piece<B>::back(h)) * up;  // exact: the remainder has <= 24 - width bits
+      // (r - h) * up, exact: the remainder has <= 24 - width bits and the
+      // scale is a power of two.  As one fused multiply-add of the scaled
+      // value, the conversion of an FP16 piece folds into a mixed-precision
+      // FMA (one instruction fewer per piece).
+      if (q + 1 < NPC) r = __builtin_fmaf(-Piece<B>::back(h), up, r * up);
     }
   }
 }
