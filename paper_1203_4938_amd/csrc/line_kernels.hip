@@ -435,10 +435,11 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   using PT = PlainTw<L, C, MAP, OMAP, EPT, C * G::T>;
   // Four-step twiddle bases.  Where two or more workgroups share a CU, their
   // table entries are loaded before the passes, so that the latency passes
-  // behind them instead of before the stores (C4-shaped 256-point column
-  // tiles: 3% faster); the one-workgroup-per-CU tiles measured 1% slower so,
-  // and load them after the passes.  A lane past the last line reads the
-  // entries of line 0; it stores nothing.
+  // behind them instead of before the stores (the 256-point column tiles of
+  // a batch of 4096 transforms of 2^16 points: 3% faster).  The
+  // one-workgroup-per-CU tiles gained nothing from it and load them after
+  // the passes.  A lane past the last line reads the entries of line 0; it
+  // stores nothing.
   constexpr bool TW4_EARLY = (NP + PT::NTW) * (int)sizeof(cf) * 2 <= PT::kLds;
   cf tAh, tAl, tBh, tBl;
   auto tw4_parts = [&]() {
