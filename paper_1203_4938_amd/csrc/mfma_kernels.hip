@@ -143,16 +143,13 @@ __device__ __forceinline__ void dft16_stage(const typename Piece<base_of<PREC>()
 // (the reads of the whole line) are in registers, so its results may
 // overwrite the line.  Without a scratch buffer beside the tile four
 // workgroups fit a CU instead of three: plain forms 4% faster, two-piece
-// forms 1%.  The three-piece form, bound by its six products per stage,
-// measured 2% slower so and keeps a per-wave scratch buffer.
+// forms 1%, the three-piece form 2%.
 template <int PREC, int MAP, int OMAP, bool TW4, int SW>
 __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__ in,
                                                           cf *__restrict__ out, MfmaArgs a) {
   constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
   constexpr int C = kMfmaLines;
-  constexpr bool SCRATCH = NPC == 3;
   __shared__ cf tile[C * kPitch];
-  __shared__ cf scratch[SCRATCH ? 4 : 1][SCRATCH ? 16 * 17 : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tileid = !(a.flags & F_REMAP)  ? blockIdx.x
@@ -182,12 +179,9 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
   // follow as A_u = A_{u-1} D and S_u = S_{u-1} G with D = w_N^{col + 64 g4}
   // and G = w_N^{16} (at most three products each), so a lane reads two
   // scattered table pairs per tile instead of one per line.  The table
-  // entries are loaded ahead of the tile, so they arrive with it; the
-  // three-piece form, whose registers would then no longer allow four waves
-  // per SIMD, loads them after the tile.
-  constexpr bool TW4_EARLY = NPC < 3;
+  // entries are loaded ahead of the tile, so they arrive with it.
   cf tw4e[8];  // A0 hi/lo, D hi/lo, S0 hi/lo, G hi/lo
-  auto tw4_parts = [&]() {
+  if constexpr (TW4) {
     const uint32_t m = (1u << a.tw4_shift) - 1u;
     const uint32_t l0 = (uint32_t)(line0 + wave * (C / 4));
     const uint32_t e[4] = {l0 * (uint32_t)(col + 64 * g4), (uint32_t)(col + 64 * g4), l0 * 16u, 16u};
@@ -196,8 +190,7 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
       tw4e[2 * q] = a.tw4_hi[e[q] >> a.tw4_shift];
       tw4e[2 * q + 1] = a.tw4_lo[e[q] & m];
     }
-  };
-  if constexpr (TW4 && TW4_EARLY) tw4_parts();
+  }
 
   // ---- load the tile (C lines x 256) coalesced, into LDS ----
   {
@@ -222,7 +215,6 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
   __syncthreads();
 
   const int part = g4 >> 1, kb = 8 * (g4 & 1);
-  if constexpr (TW4 && !TW4_EARLY) tw4_parts();
   cf A, S, Dw, Gw;  // bases of the current line and their steps
   if constexpr (TW4) {
     A = cmul(tw4e[0], tw4e[1]);
@@ -243,9 +235,8 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
     f32x4 dre, dim;
     dft16_stage<PREC>(are, aim, xv, dre, dim);
     // D: column n2 = col, rows k1 = 4 g4 + t -> twiddle, to Y[k1][n2] at
-    // position 16 k1 + n2 of the line, or of the wave's scratch buffer (pitch
-    // 17 per k1 row either way)
-    cf *scr = SCRATCH ? scratch[wave] : tile + c * kPitch;
+    // position 16 k1 + n2 of the line (pitch 17 per k1 row)
+    cf *scr = tile + c * kPitch;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const cf y = cmul(make_float2(dre[t], dim[t]), tw[t]);
@@ -282,12 +273,6 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
       if (SW & 2) y = cswap(cscale(y, a.scale));
       tile[tidx(c, col + 16 * (4 * g4 + t))] = y;
     }
-    if constexpr (SCRATCH) {
-      // the next line's stage 1 reuses the scratch buffer
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
   }
   __syncthreads();
 
@@ -305,9 +290,7 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
   }
 }
 
-int mfma_lds_bytes(int prec) {
-  return (int)sizeof(cf) * (kMfmaLines * kPitch + (mfma_pieces(prec) == 3 ? 4 * 16 * 17 : 1));
-}
+int mfma_lds_bytes(int) { return (int)sizeof(cf) * kMfmaLines * kPitch; }
 
 const void *mfma_kernel(int prec, int map, int omap, bool tw4, int sw) {
 #define MK2(P)                                                                                 \
