@@ -67,8 +67,10 @@ class OracleLib:
         lib.oracle_fft_ragged_f32.argtypes = [fp, dp, ip, ip, i64, ci, ci]
         lib.oracle_fft2d_f32.argtypes = [fp, dp, i64, i64, i64, ci, ci]
         lib.oracle_threads.argtypes = [ci]
+        lib.oracle_rel_l2_f32.argtypes = [fp, dp, i64, i64, dp, dp, ci]
         for f in (lib.oracle_dft, lib.oracle_fft, lib.oracle_fft_batch_f32,
-                  lib.oracle_fft_ragged_f32, lib.oracle_fft2d_f32, lib.oracle_threads):
+                  lib.oracle_fft_ragged_f32, lib.oracle_fft2d_f32, lib.oracle_threads,
+                  lib.oracle_rel_l2_f32):
             f.restype = ci
         self.lib = lib
         self.path = path
@@ -125,6 +127,23 @@ class OracleLib:
     def threads(self, requested: int = 0) -> int:
         return self.lib.oracle_threads(requested)
 
+    def rel_l2_f32(self, y, ref, threads: int = 0, with_norms: bool = False):
+        """Per-signal relative L2 error of complex64 ``y`` against complex128
+        ``ref`` over the last axis (the last two for 3D input); with
+        ``with_norms`` also the reference norms (for the pooled error)."""
+        y = _c64(y)
+        ref = _c128(ref)
+        if y.shape != ref.shape:
+            raise ValueError(f"shape mismatch {y.shape} vs {ref.shape}")
+        n = y.shape[-1] * (y.shape[-2] if y.ndim == 3 else 1)
+        batch = y.size // n if n else 0
+        err = np.empty(batch, dtype=np.float64)
+        nrm = np.empty(batch, dtype=np.float64)
+        _check(self.lib.oracle_rel_l2_f32(_ptr(y, ctypes.c_float), _ptr(ref, ctypes.c_double),
+                                          n, batch, _ptr(err, ctypes.c_double),
+                                          _ptr(nrm, ctypes.c_double), threads))
+        return (err, nrm) if with_norms else err
+
 
 _default = None
 
@@ -162,6 +181,10 @@ def fft2d(x, inverse: bool = False, threads: int = 0) -> np.ndarray:
 def threads(requested: int = 0) -> int:
     """OpenMP thread count the batch routines use for ``requested`` (0 = default)."""
     return default().threads(requested)
+
+
+def rel_l2_f32(y, ref, threads: int = 0, with_norms: bool = False):
+    return default().rel_l2_f32(y, ref, threads, with_norms)
 
 
 def rel_l2(y, ref) -> np.ndarray:

@@ -296,3 +296,23 @@ int oracle_fft2d_f32(const float *x, double *yd, int64_t ny, int64_t nx,
     free(tab_y);
     return failed ? -1 : 0;
 }
+
+int oracle_rel_l2_f32(const float *y, const double *ref, int64_t n,
+                      int64_t batch, double *err, double *ref_norm,
+                      int threads) {
+    if (!y || !ref || !err || n <= 0 || batch < 0) return -1;
+#pragma omp parallel for schedule(static) num_threads(oracle_threads(threads))
+    for (int64_t b = 0; b < batch; ++b) {
+        const float *yb = y + 2 * b * n;
+        const double *rb = ref + 2 * b * n;
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < 2 * n; ++j) {
+            double d = (double)yb[j] - rb[j];
+            num += d * d;
+            den += rb[j] * rb[j];
+        }
+        err[b] = sqrt(num) / (den > 0.0 ? sqrt(den) : 1.0);
+        if (ref_norm) ref_norm[b] = sqrt(den);
+    }
+    return 0;
+}

@@ -50,6 +50,15 @@ int oracle_fft_ragged_f32(const float *x, double *y, const int64_t *sizes,
 int oracle_fft2d_f32(const float *x, double *y, int64_t ny, int64_t nx,
                      int64_t batch, int inverse, int threads);
 
+/* Error metric of the parity tests: per-signal relative L2 distance
+ * err[b] = ||y_b - ref_b||_2 / ||ref_b||_2 (the denominator taken as 1 when
+ * ref_b is all zeros) of `batch` signals of n complex elements, y as float32
+ * pairs (a transform's output), ref as double pairs (the oracle's).
+ * ref_norm (may be NULL) receives ||ref_b||_2. */
+int oracle_rel_l2_f32(const float *y, const double *ref, int64_t n,
+                      int64_t batch, double *err, double *ref_norm,
+                      int threads);
+
 /* Number of OpenMP threads a parallel region will use with `threads`. */
 int oracle_threads(int threads);
 

@@ -31,13 +31,24 @@ int64_t split_factor(int64_t n) {
   return best;
 }
 
+namespace {
+// compute units the plan being built sizes its persistent grids for (set by
+// fft_plan from the current device; dry plans assume an MI355X's 256)
+thread_local int t_cus = kDefaultCus;
+}  // namespace
+
+void set_plan_cus(int cus) { t_cus = cus > 0 ? cus : kDefaultCus; }
+
+int device_cus() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    return v;
+  return kDefaultCus;
+}
+
 int resident_for(int lds_bytes, int threads) {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-  }
+  const int cus = t_cus;
   int by_lds = lds_bytes ? kLdsBytes / lds_bytes : 8;
   int by_thr = 2048 / threads;
   return cus * std::max(1, std::min(by_lds, by_thr));
@@ -190,6 +201,17 @@ void MixedStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_
   dst_id = dst;
 }
 
+hipError_t MixedStep::prepare() const {
+  // dynamic LDS above the default 64 KB needs an explicit opt-in per function
+  for (int sw = 0; sw < 4; ++sw)
+    if (fn_sw[sw]) {
+      const hipError_t e =
+          hipFuncSetAttribute(fn_sw[sw], hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
 bool MixedStep::valid() const {
   // in-line element offsets travel to the passes as 32-bit values
   const int64_t span = (int64_t)(a.mp.L - 1) * std::max(a.in_e, a.out_e);
@@ -262,14 +284,19 @@ namespace {
 
 // Override in force for a plan being built (see internal.h for the sources).
 thread_local const fft_desc_t *g_building = nullptr;
+thread_local bool g_skip_cache = false;  // a plan rebuilt after its cached override failed
+thread_local bool g_cache_used = false;  // the override in force came from the tuning cache
 
 Override read_override() {
   if (const Override *t = tuner_override()) return *t;
   if (const char *env = getenv("DPFFT_FORCE_PLAN")) return parse_override(env);
-  if (g_building && !(g_building->flags & FFT_F_NO_AUTOTUNE)) {
+  if (g_building && !g_skip_cache && !(g_building->flags & FFT_F_NO_AUTOTUNE)) {
     const std::string key = tune_key(g_building);
     std::string val;
-    if (!key.empty() && tune_cache_lookup(key, &val)) return parse_override(val);
+    if (!key.empty() && tune_cache_lookup(key, &val)) {
+      g_cache_used = true;
+      return parse_override(val);
+    }
   }
   return Override{};
 }
@@ -517,11 +544,6 @@ std::unique_ptr<MixedStep> make_mixed(dpfft_plan_s *P, const char *name, int64_t
   lo.insert(lo.end(), hi.begin(), hi.end());
   s->tw2_off = P->tables.add(lo);
   s->a.scale = 1.0f;
-  // dynamic LDS above the default 64 KB needs an explicit opt-in per function
-  for (int sw = 0; sw < 4; ++sw)
-    if (s->fn_sw[sw])
-      (void)hipFuncSetAttribute(s->fn_sw[sw], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                s->lds_bytes);
   return s;
 }
 
@@ -761,7 +783,7 @@ const char *fft_last_error(void) { return g_last_error.c_str(); }
 }  // extern "C"
 
 // Host part of fft_plan: validation, kernel choice, tables, bounds checks.
-static fft_status_t build_plan(const fft_desc_t *desc, std::unique_ptr<dpfft_plan_s> &out) {
+static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpfft_plan_s> &out) {
   fft_status_t st = validate_desc(desc);
   if (st != FFT_OK) return st;
   auto P = std::make_unique<dpfft_plan_s>();
@@ -829,17 +851,44 @@ static fft_status_t build_plan(const fft_desc_t *desc, std::unique_ptr<dpfft_pla
   o << " variant=" << P->variant << " launches=" << P->steps.size()
     << " workspace=" << P->ws_bytes << "B tables=" << P->tables.host.size() * sizeof(float2) << "B";
   if (!ov.empty()) o << " override=\"" << ov.text << "\"";
+  {
+    const std::string key = tune_key(desc);
+    if (!key.empty()) o << " tune_key=" << key;
+  }
   for (auto &s : P->steps) o << "\n  " << s->describe();
   P->text = o.str();
   out = std::move(P);
   return FFT_OK;
 }
 
+// A tuning-cache entry names kernel choices of the build that wrote it; if the
+// plan they lead to cannot be built (an instance since removed, a shape that
+// no longer fits), the plan is built again with the heuristic choices.
+static fft_status_t build_plan(const fft_desc_t *desc, std::unique_ptr<dpfft_plan_s> &out,
+                               int cus) {
+  set_plan_cus(cus);
+  g_cache_used = false;
+  g_skip_cache = false;
+  fft_status_t st = build_plan_once(desc, out);
+  if (st != FFT_OK && g_cache_used) {
+    const std::string why = fft_last_error();
+    if (getenv("DPFFT_LOG"))
+      fprintf(stderr, "[dpfft] cached plan choice failed (%s); using the default plan\n",
+              why.c_str());
+    g_skip_cache = true;
+    st = build_plan_once(desc, out);
+    g_skip_cache = false;
+  }
+  g_cache_used = false;
+  set_plan_cus(kDefaultCus);
+  return st;
+}
+
 extern "C" {
 
 fft_status_t fft_plan_dry(const fft_desc_t *desc, char *buf, size_t len) {
   std::unique_ptr<dpfft_plan_s> P;
-  fft_status_t st = build_plan(desc, P);
+  fft_status_t st = build_plan(desc, P, kDefaultCus);
   if (st != FFT_OK) return st;
   if (buf && len) {
     const size_t n = std::min(P->text.size(), len - 1);
@@ -853,8 +902,15 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
   if (!out) return fail(FFT_E_INVALID, "out is NULL");
   *out = nullptr;
   std::unique_ptr<dpfft_plan_s> P;
-  fft_status_t st = build_plan(desc, P);
+  fft_status_t st = build_plan(desc, P, device_cus());
   if (st != FFT_OK) return st;
+
+  // per-function launch attributes (dynamic LDS opt-in)
+  for (auto &s : P->steps) {
+    const hipError_t e = s->prepare();
+    if (e != hipSuccess)
+      return fail(FFT_E_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
+  }
 
   // upload every table in one allocation
   hipStream_t stream = (hipStream_t)hip_stream;

@@ -147,7 +147,9 @@ std::string tune_key(const fft_desc_t *d) {
   int bucket = 0;
   while ((int64_t(1) << (bucket + 1)) <= d->batch) ++bucket;
   std::ostringstream o;
-  o << "gfx950|r" << d->rank << "|n=" << d->n[0];
+  char reg[20];
+  snprintf(reg, sizeof reg, "%016llx", (unsigned long long)line_registry_digest());
+  o << "gfx950|k=" << reg << "|r" << d->rank << "|n=" << d->n[0];
   if (d->rank == 2) o << "x" << d->n[1];
   o << "|b=2^" << bucket << "|fp32";
   return o.str();

@@ -18,7 +18,17 @@ fft_status_t fail(fft_status_t s, const std::string &msg);
 // Largest divisor of n that is <= sqrt(n).
 int64_t split_factor(int64_t n);
 
-// Workgroups that fit on the device at once for `lds_bytes` and `threads`.
+// Compute units of an MI355X; the CU count dry plans assume.
+constexpr int kDefaultCus = 256;
+
+// Compute units of the current device (kDefaultCus if it cannot be queried).
+int device_cus();
+
+// CU count the plan builders on this thread size persistent grids for.
+void set_plan_cus(int cus);
+
+// Workgroups that fit on the device at once for `lds_bytes` and `threads`
+// (host arithmetic only, for the CU count set by set_plan_cus).
 int resident_for(int lds_bytes, int threads);
 
 // Kernel-choice overrides for the plan builders, per launch step i:

@@ -99,4 +99,9 @@ struct KernelInfo {
 // fills up to `max` of them.
 int list_line_kernels(int L, int map, int omap, bool tw4, KernelInfo *out, int max);
 
+// Digest of the compiled line-kernel registry (shapes, tiles, variants): part
+// of the tuning-cache key, so entries written by a build with other kernels
+// are not applied.
+uint64_t line_registry_digest();
+
 }  // namespace dpfft

@@ -838,6 +838,23 @@ static void for_each_entry(F f) {
   for (const auto &e : kLineTablePf32x) f(e);
 }
 
+uint64_t line_registry_digest() {
+  // FNV-1a over every field the planner and the tuner read from an entry
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for_each_entry([&](const LineEntry &e) {
+    mix(e.L), mix(e.C), mix(e.map), mix(e.omap), mix(e.tw4), mix(e.threads), mix(e.lds);
+    mix(e.pf), mix(e.pref), mix(e.ept);
+    for (int i = 0; i < 4; ++i) mix(e.fn[i] != nullptr);
+  });
+  return h;
+}
+
 int list_line_kernels(int L, int map, int omap, bool tw4, KernelInfo *out, int max) {
   int n = 0;
   for_each_entry([&](const LineEntry &e) {

@@ -100,14 +100,40 @@ __device__ __forceinline__ void split8(const float (&x)[8],
 }
 
 // One DFT-16 stage: D = W X for the 16 vectors held in B layout.
+//
+// FP16 pieces have a 5-bit exponent: above 65504 they overflow, below 2^-14
+// they lose bits.  A stage's input grows with the transform (up to 4096 times
+// the signal amplitude before the last stage of a 2^16-point four-step), so
+// for the FP16 forms each vector (one B column: its 32 real values sit in
+// lanes col, col + 16, col + 32 and col + 48) is first scaled by an exact
+// power of two 2^-e that brings its largest magnitude into [1/2, 1), and the
+// FP32 products are scaled back by 2^e.  Both scalings are exact, so the
+// result is the same as with unbounded exponents and the error stays
+// relative to the vector's own magnitude, whatever the input range.  BF16
+// pieces share FP32's exponent range and need no scaling.
 template <int PREC>
 __device__ __forceinline__ void dft16_stage(const typename Piece<base_of<PREC>()>::vec (&are)[3],
                                             const typename Piece<base_of<PREC>()>::vec (&aim)[3],
                                             const float (&xv)[8], f32x4 &dre, f32x4 &dim) {
   constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
   constexpr float down = 1.0f / (float)(1 << mfma_piece_shift(PREC));
+  constexpr bool SCALED = B == MP_FP16;
   typename Piece<B>::vec xp[3];
-  split8<PREC>(xv, xp);
+  int ex = 0;
+  if constexpr (SCALED) {
+    float m = __builtin_fabsf(xv[0]);
+#pragma unroll
+    for (int t = 1; t < 8; ++t) m = __builtin_fmaxf(m, __builtin_fabsf(xv[t]));
+    m = __builtin_fmaxf(m, __shfl_xor(m, 16));
+    m = __builtin_fmaxf(m, __shfl_xor(m, 32));
+    ex = __builtin_amdgcn_frexp_expf(m);  // m = f 2^ex, f in [1/2, 1); 0 for m = 0
+    float xs[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xs[t] = __builtin_amdgcn_ldexpf(xv[t], -ex);
+    split8<PREC>(xs, xp);
+  } else {
+    split8<PREC>(xv, xp);
+  }
   const f32x4 z = {0.f, 0.f, 0.f, 0.f};
   f32x4 r0 = mfma<B>(are[0], xp[0], z);
   f32x4 i0 = mfma<B>(aim[0], xp[0], z);
@@ -128,6 +154,13 @@ __device__ __forceinline__ void dft16_stage(const typename Piece<base_of<PREC>()
     }
     r0 = r0 + r1 * down;
     i0 = i0 + i1 * down;
+  }
+  if constexpr (SCALED) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      r0[t] = __builtin_amdgcn_ldexpf(r0[t], ex);
+      i0[t] = __builtin_amdgcn_ldexpf(i0[t], ex);
+    }
   }
   dre = r0;
   dim = i0;

@@ -56,6 +56,9 @@ struct Step {
   virtual void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const = 0;
   // layout assumptions of the kernel hold and every needed instance exists
   virtual bool valid() const = 0;
+  // device-side set-up at fft_plan time (function attributes); never called
+  // for dry plans
+  virtual hipError_t prepare() const { return hipSuccess; }
 };
 
 struct LineStep : Step {
@@ -98,6 +101,7 @@ struct MixedStep : Step {
   std::string describe() const override;
   void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
   bool valid() const override;
+  hipError_t prepare() const override;
 };
 
 struct MfmaStep : Step {

@@ -24,10 +24,15 @@ struct GraphKey {
   void *out, *ws;
   bool inverse;
   hipStream_t stream;
-  bool operator<(const GraphKey &o) const {
-    return std::tie(in, out, ws, inverse, stream) < std::tie(o.in, o.out, o.ws, o.inverse, o.stream);
+  bool operator==(const GraphKey &o) const {
+    return std::tie(in, out, ws, inverse, stream) == std::tie(o.in, o.out, o.ws, o.inverse, o.stream);
   }
 };
+
+// Instantiated graphs a plan keeps, most recently used first.  A caller that
+// rotates buffers gets a new graph per buffer set; beyond this many the
+// least recently used one is released (after its stream has drained).
+constexpr size_t kMaxGraphs = 8;
 
 }  // namespace
 
@@ -43,10 +48,30 @@ struct RaggedStep : Step {
   std::vector<std::pair<int, int>> ranges;  // per-size mode: (first item, count)
   std::string summary;
   mutable std::mutex mu;
-  mutable std::map<GraphKey, hipGraphExec_t> graphs;
+  mutable std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
 
   ~RaggedStep() override {
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  }
+
+  hipError_t prepare() const override {
+    // dynamic LDS above the default 64 KB needs an explicit opt-in per function
+    for (bool inv : {false, true}) {
+      const hipError_t e = hipFuncSetAttribute(ragged_kernel(inv),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  // the cached graph for `key`, moved to the front (nullptr if none)
+  hipGraphExec_t find_graph_locked(const GraphKey &key) const {
+    for (size_t i = 0; i < graphs.size(); ++i)
+      if (graphs[i].first == key) {
+        std::rotate(graphs.begin(), graphs.begin() + i, graphs.begin() + i + 1);
+        return graphs[0].second;
+      }
+    return nullptr;
   }
 
   void bind(const float2 *tables) override {
@@ -112,8 +137,7 @@ struct RaggedStep : Step {
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(mu);
-      auto it = graphs.find(key);
-      if (it != graphs.end()) exec = it->second;
+      exec = find_graph_locked(key);
     }
     if (!exec) {
       RaggedArgs r0 = args_for(ctx), r1 = args_for(ctx);
@@ -147,12 +171,22 @@ struct RaggedStep : Step {
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return e;
       std::lock_guard<std::mutex> lk(mu);
-      auto it = graphs.find(key);
-      if (it != graphs.end()) {
+      if (hipGraphExec_t other = find_graph_locked(key)) {
         (void)hipGraphExecDestroy(exec);
-        exec = it->second;
+        exec = other;
       } else {
-        graphs[key] = exec;
+        if (graphs.size() >= kMaxGraphs) {
+          // the evicted graph may still be running on its stream
+          const auto &old = graphs.back();
+          const hipError_t se = hipStreamSynchronize(old.first.stream);
+          if (se != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            return se;
+          }
+          (void)hipGraphExecDestroy(old.second);
+          graphs.pop_back();
+        }
+        graphs.insert(graphs.begin(), {key, exec});
       }
     }
     return hipGraphLaunch(exec, ctx.stream);
@@ -377,9 +411,6 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
   st->ws_elems = ws;
   P->ws_bytes = (size_t)ws * sizeof(float2);
 
-  for (bool inv : {false, true})
-    (void)hipFuncSetAttribute(ragged_kernel(inv), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              st->lds_bytes);
 
   std::ostringstream o;
   o << "ragged: " << count << " signals, " << nsingle_sizes << " single-pass lengths, "

@@ -2,73 +2,118 @@
 
 Tolerances (relative L2 per signal, gated on the max): 1e-5 for the split
 forms (FP16 hi/lo, BF16 hi/lo, BF16 hi/mid/lo), 2e-3 for plain FP16.  Plain
-BF16 keeps only 8 significant bits per operand; its error is recorded and
-checked against 2e-3 as an expected failure, and against a sanity bound."""
+BF16 keeps only 8 significant bits per operand; it is held to the same 2e-3
+and marked as an expected failure when it misses, with the measured error in
+the reason (it is never passed at a looser bound).
+
+The input-range cases (amplitudes 1e3 and 1e-6, a constant of 16, and the
+inverse of a full-amplitude spectrum) pin the FP16 forms' per-vector
+power-of-two scaling: without it the FP16 pieces overflow or lose their low
+bits."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_util import TOL_FP32, max_rel, run_plan, say, to_dev
+from gpu_util import (TOL_FP32, assert_generator_rows, full_parity, max_rel, run_plan, say,
+                      to_dev)
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp16": 2e-3, "bf16": 2e-3, "fp16_split": 1e-5, "bf16_split": 1e-5, "bf16_split3": 1e-5}
-SANITY = {"bf16": 2e-2}
+FORMS = ["fp16", "bf16", "fp16_split", "bf16_split", "bf16_split3"]
+#: plain BF16 above this is a defect, not the known 8-bit-significand miss
+BF16_DEFECT = 2e-2
 
 
-def _check(prec, n, batch, seed):
+def _gate(prec, e, what):
+    """Hold `e` to the form's tolerance; plain BF16 misses are recorded xfails."""
+    if prec == "bf16":
+        assert e <= BF16_DEFECT, (what, e)
+        if e > TOL["bf16"]:
+            pytest.xfail(f"plain BF16 {what}: measured max rel L2 {e:.3e} > 2e-3 "
+                         "(8-bit significands)")
+    else:
+        assert e <= TOL[prec], (prec, what, e)
+
+
+def _check(prec, x, inverse_input=None):
+    """Forward of x and inverse of `inverse_input` (default x) against the oracle."""
     import paper_1203_4938_amd as dp
-    x = synth.uniform_complex(seed, n, batch)
+    batch, n = x.shape
     p = dp.Plan(n, batch, precision=prec)
-    say(f"[mfma {prec}] n={n} batch={batch} plan: " + p.describe().replace("\n", " | "))
-    xd = to_dev(x)
+    xi = x if inverse_input is None else inverse_input
     errs = []
-    for inv in (False, True):
-        y = run_plan(p, xd, inverse=inv).cpu().numpy()
-        e = max_rel(y, oracle.fft_batch(x, inverse=inv))
-        say(f"   inverse={inv} max rel L2 = {e:.3e}")
+    for inv, inp in ((False, x), (True, xi)):
+        y = run_plan(p, to_dev(inp), inverse=inv).cpu().numpy()
+        e = max_rel(y, oracle.fft_batch(inp, inverse=inv))
+        say(f"   [{prec}] n={n} inverse={inv} max rel L2 = {e:.3e}")
         errs.append(e)
     return max(errs)
 
 
-@pytest.mark.parametrize("prec", ["fp16", "fp16_split", "bf16_split", "bf16_split3"])
+@pytest.mark.parametrize("prec", FORMS)
 @pytest.mark.parametrize("n,batch", [(256, 37), (65536, 3)])
 def test_mfma_forms(prec, n, batch):
-    e = _check(prec, n, batch, synth.BASE_SEED + 700)
-    assert e <= TOL[prec], (prec, n, e)
+    x = synth.uniform_complex(synth.BASE_SEED + 700, n, batch)
+    _gate(prec, _check(prec, x), f"n={n} uniform")
 
 
-@pytest.mark.parametrize("n,batch", [(256, 37), (65536, 3)])
-def test_mfma_bf16_plain(n, batch):
-    e = _check("bf16", n, batch, synth.BASE_SEED + 701)
-    assert e <= SANITY["bf16"], e
-    if e > TOL["bf16"]:
-        pytest.xfail(f"plain BF16 rel L2 {e:.2e} exceeds the 2e-3 bound (8-bit significands)")
+def _spectrum64(x):
+    return oracle.fft_batch(x).astype(np.complex64)
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp16_split", "bf16_split", "bf16_split3"])
-def test_mfma_c4_sampled_full_size(prec):
+RANGES = {
+    # amplitude 1e3 and 1e-6: FP16 overflow after a few stages, FP16 subnormals
+    "amp1e3": lambda x: (x * np.float32(1e3)).astype(np.complex64),
+    "amp1e-6": lambda x: (x * np.float32(1e-6)).astype(np.complex64),
+    # a constant 16: the whole energy lands in one bin, 16 * N at DC
+    "const16": lambda x: np.full_like(x, 16.0 + 0.0j),
+}
+
+
+@pytest.mark.parametrize("prec", FORMS)
+@pytest.mark.parametrize("case", sorted(RANGES))
+@pytest.mark.parametrize("n", [256, 65536])
+def test_mfma_input_range(prec, case, n):
+    base = synth.uniform_complex(synth.BASE_SEED + 702, n, 4)
+    x = RANGES[case](base)
+    _gate(prec, _check(prec, x), f"n={n} {case}")
+
+
+@pytest.mark.parametrize("prec", FORMS)
+@pytest.mark.parametrize("n", [256, 65536])
+def test_mfma_inverse_of_spectrum(prec, n):
+    """Inverse of the oracle's spectrum of a uniform batch (values up to about
+    N in magnitude), against the oracle's inverse of the same complex64 input."""
+    x = synth.uniform_complex(synth.BASE_SEED + 703, n, 4)
+    _gate(prec, _check(prec, x, inverse_input=_spectrum64(x)), f"n={n} inverse of spectrum")
+
+
+@pytest.mark.parametrize("prec", FORMS)
+def test_mfma_c4_full_batch_every_signal(prec):
     """C4 shape (N=2^16, batch 4096) in the launch configuration the benchmark
-    times: sampled signals against the oracle, for each matrix-core form.  Plain
-    BF16 is held to its sanity bound (its 2e-3 miss is recorded above)."""
+    times: every signal against the oracle, the forward transform of the
+    input and the inverse of the oracle's spectrum (the amplitude range the
+    benchmark's inverse sees), plus the round trip."""
     import torch
 
     import paper_1203_4938_amd as dp
     n, batch = 1 << 16, 4096
     w = synth.workloads()[f"c4_n2^16_b4096_{prec}"]
+    say(f"[full c4 {prec}] n={n} batch={batch}: every signal, both directions")
     x = synth.uniform_complex_torch(w.seed, n, batch, "cuda")
+    assert_generator_rows(x, w.seed, n, (0, batch - 1))
     p = dp.Plan(n, batch, precision=prec)
-    y = run_plan(p, x)
-    tol = SANITY.get(prec, TOL[prec])
-    for b in (0, 1, 2047, 4095):
-        xs = synth.uniform_complex(w.seed, n, 1, first=b)
-        ref = oracle.fft_batch(xs)
-        e = max_rel(y[b:b + 1].cpu().numpy(), ref)
-        say(f"   [{prec}] signal {b}: rel L2 {e:.3e}")
-        assert e <= tol, (prec, b, e)
-    del x, y
+    say("   plan:", p.describe().replace("\n", " | "))
+    st = full_parity(p, x, label=f"c4 {prec}")
+    del x
     torch.cuda.empty_cache()
+    # the round trip goes through two transforms of this form
+    rt_tol = 2 * TOL[prec]
+    assert st["round_trip"].max <= (BF16_DEFECT if prec == "bf16" else rt_tol), \
+        st["round_trip"].line()
+    _gate(prec, max(st["forward"].max, st["inverse"].max), "c4 full batch")
 
 
 def test_mfma_unsupported_length_is_reported():
@@ -76,3 +121,16 @@ def test_mfma_unsupported_length_is_reported():
     with pytest.raises(dp.FftError) as ei:
         dp.Plan(4096, 4, precision="fp16_split")
     assert ei.value.status == dp.FFT_E_UNSUPPORTED
+
+
+def test_fp32_reference_at_the_same_ranges():
+    """The FP32 path on the same range cases, for comparison (bound 1e-5)."""
+    import paper_1203_4938_amd as dp
+    for case, f in sorted(RANGES.items()):
+        x = f(synth.uniform_complex(synth.BASE_SEED + 702, 65536, 4))
+        p = dp.Plan(65536, 4)
+        for inv in (False, True):
+            y = run_plan(p, to_dev(x), inverse=inv).cpu().numpy()
+            e = max_rel(y, oracle.fft_batch(x, inverse=inv))
+            say(f"   [fp32] {case} inverse={inv} max rel L2 {e:.3e}")
+            assert e <= TOL_FP32, (case, inv, e)

@@ -53,3 +53,20 @@ def test_rel_l2_metric():
     e = oracle.rel_l2(y, ref)
     assert e[0] == pytest.approx(0.1)
     assert e[1] == 0.0
+
+
+def test_rel_l2_f32_metric():
+    """The C metric of the full-size parity tests: hand-computed values (3-4-5
+    triangle, an all-zero reference) and agreement with the numpy metric."""
+    ref = np.array([[3 + 4j, 0], [1, 1], [0, 0]], np.complex128)
+    y = ref.astype(np.complex64)
+    y[0, 1] += 0.5
+    y[2, 0] = 2.0
+    e = oracle.rel_l2_f32(y, ref)
+    assert e[0] == pytest.approx(0.1, rel=1e-15)
+    assert e[1] == 0.0
+    assert e[2] == 2.0  # ||ref|| = 0: the absolute distance
+    rng = np.random.default_rng(5)
+    ref = rng.standard_normal((4, 7, 9)) + 1j * rng.standard_normal((4, 7, 9))
+    y = (ref * (1 + 1e-3 * rng.standard_normal(ref.shape))).astype(np.complex64)
+    np.testing.assert_allclose(oracle.rel_l2_f32(y, ref), oracle.rel_l2(y, ref), rtol=1e-12)

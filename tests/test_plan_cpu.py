@@ -2,6 +2,7 @@
 fft_plan_dry, the override hook, and the tuning-cache file (valid entry used,
 corrupt file ignored, FFT_F_NO_AUTOTUNE honoured)."""
 import json
+import re
 import os
 import subprocess
 import sys
@@ -89,15 +90,42 @@ def test_override_env_changes_the_kernel():
     assert "C=2" in out and 'override="c0=2"' in out
 
 
+def _tune_key() -> str:
+    out = _run(CODE.format(flags=0), {})
+    key = re.search(r"tune_key=(\S+)", out).group(1)
+    # the key names the architecture and a digest of the compiled kernel registry
+    assert key.startswith("gfx950|k=") and "|n=4096|b=2^6|fp32" in key
+    return key
+
+
 def test_tune_cache_file_is_used(tmp_path):
     path = tmp_path / "tune.json"
-    path.write_text(json.dumps({"dpfft_tune_cache": 1,
-                                "entries": {"gfx950|r1|n=4096|b=2^6|fp32": "c0=2 p0=0"}}))
+    path.write_text(json.dumps({"dpfft_tune_cache": 1, "entries": {_tune_key(): "c0=2 p0=0"}}))
     out = _run(CODE.format(flags=0), {"DPFFT_TUNE_CACHE": str(path)})
     assert "C=2" in out
     # FFT_F_NO_AUTOTUNE ignores the cache
     out = _run(CODE.format(flags=2), {"DPFFT_TUNE_CACHE": str(path)})
     assert "C=1" in out and "override" not in out
+
+
+def test_tune_cache_entry_of_another_build_is_ignored(tmp_path):
+    """An entry keyed without the current registry digest (written by a build
+    with other kernels) is not applied."""
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"dpfft_tune_cache": 1,
+                                "entries": {"gfx950|r1|n=4096|b=2^6|fp32": "c0=2 p0=0"}}))
+    out = _run(CODE.format(flags=0), {"DPFFT_TUNE_CACHE": str(path)})
+    assert "C=1" in out and "override" not in out
+
+
+def test_tune_cache_entry_naming_a_missing_kernel_falls_back(tmp_path):
+    """A cached choice that no compiled instance satisfies (here 3 lines per
+    tile) does not make a supported size fail: the plan is built again with
+    the heuristic choices."""
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"dpfft_tune_cache": 1, "entries": {_tune_key(): "c0=3"}}))
+    out = _run(CODE.format(flags=0), {"DPFFT_TUNE_CACHE": str(path)})
+    assert "variant=single-pass" in out and "C=1" in out and "override" not in out
 
 
 @pytest.mark.parametrize("content", ["not json at all", '{"dpfft_tune_cache": 1, "entries": {"k": ',
