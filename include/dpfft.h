@@ -77,6 +77,7 @@ typedef enum {
 #define FFT_F_GRAPH 4u       /* ragged plans: replay the launches as a HIP graph */
 #define FFT_F_PER_SIZE 8u    /* ragged plans: one launch per distinct length instead of
                                 the two persistent launches (the comparison baseline) */
+#define FFT_F_REAL 16u       /* real samples (see "Real-input transforms" below) */
 
 typedef struct {
   int32_t rank;     /* 1: batched 1D signals; 2: batched images */
@@ -92,6 +93,28 @@ typedef struct {
   int32_t precision; /* fft_precision_t */
   uint32_t flags;    /* FFT_F_* */
 } fft_desc_t;
+
+/*
+ * Real-input transforms (FFT_F_REAL).  The paper's image workload (section
+ * III-B) transforms real greyscale pictures; a real signal's spectrum is
+ * Hermitian, X[N-k] = conj X[k], so bins 0..N/2 determine it.
+ *   forward: in  = N float32 samples per signal (rank 2: ny rows of nx),
+ *            out = N/2 + 1 complex64 bins per signal (rank 2: ny rows of
+ *                  nx/2 + 1 bins), X[k] as defined above, k = 0..N/2;
+ *   inverse: in  = N/2 + 1 bins per signal (rank 2: ny x (nx/2 + 1)) of a
+ *                  Hermitian spectrum, out = N float32 samples, scaled by 1/N
+ *                  (rank 2: 1/(ny nx)).  Bins 0 and N/2 of a Hermitian
+ *                  spectrum are real, and their imaginary parts are ignored
+ *                  (rank 2: those of columns 0 and nx/2 once the column
+ *                  transforms have been inverted, which are real for a
+ *                  Hermitian 2D spectrum).
+ * Signals (images) are packed back to back on both sides: dist must be 0.
+ * Supported: FFT_FP32, rank 1 with N a power of two in [2, 32768] (one
+ * launch per direction), rank 2 with nx a power of two in [2, 32768] and ny a
+ * power of two in [1, 16384] (two launches per direction; the inverse needs a
+ * workspace of batch * ny * (nx/2 + 1) complex64).  in != out.  Both
+ * buffers are device pointers owned by the caller, 8-byte aligned.
+ */
 
 /*
  * Create a plan.  Validates *desc, factors each length into radices

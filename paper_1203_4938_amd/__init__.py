@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libdpfft.so")
 
 FFT_OK, FFT_E_INVALID, FFT_E_UNSUPPORTED, FFT_E_NOMEM, FFT_E_DEVICE, FFT_E_INTERNAL = range(6)
 FFT_FORWARD, FFT_INVERSE = -1, +1
-FFT_F_INPLACE, FFT_F_NO_AUTOTUNE, FFT_F_GRAPH, FFT_F_PER_SIZE = 1, 2, 4, 8
+FFT_F_INPLACE, FFT_F_NO_AUTOTUNE, FFT_F_GRAPH, FFT_F_PER_SIZE, FFT_F_REAL = 1, 2, 4, 8, 16
 PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4, "bf16_split3": 5}
 
 #: names of every C entry point declared in include/dpfft.h
@@ -183,15 +183,20 @@ class Plan:
 
     ``Plan(n, batch)`` -- batch of length-n signals (last axis);
     ``Plan(shape=(ny, nx), batch=b, rank=2)`` -- batch of images;
-    ``Plan(ragged_sizes=[...])`` -- ragged batch packed back to back.
+    ``Plan(ragged_sizes=[...])`` -- ragged batch packed back to back;
+    ``real=True`` -- real samples: the forward transform takes float32
+    samples and returns the n//2 + 1 bins (rank 2: ny x (nx//2 + 1)) as
+    complex64, the inverse takes those bins and returns float32 samples.
     """
 
     def __init__(self, n: Optional[int] = None, batch: int = 1, *, rank: int = 1, shape=None,
                  dist: int = 0, ragged_sizes=None, ragged_offsets=None, precision: str = "fp32",
                  inplace: bool = False, graph: bool = False, per_size: bool = False,
-                 autotune: bool = True, stream=None):
+                 autotune: bool = True, real: bool = False, stream=None):
         flags = (FFT_F_INPLACE if inplace else 0) | (FFT_F_GRAPH if graph else 0) | \
-                (FFT_F_PER_SIZE if per_size else 0) | (0 if autotune else FFT_F_NO_AUTOTUNE)
+                (FFT_F_PER_SIZE if per_size else 0) | (0 if autotune else FFT_F_NO_AUTOTUNE) | \
+                (FFT_F_REAL if real else 0)
+        self.real = bool(real)
         self.desc, self._keep = make_desc(n, batch, rank=rank, shape=shape, dist=dist,
                                           ragged_sizes=ragged_sizes, ragged_offsets=ragged_offsets,
                                           precision=precision, flags=flags)
@@ -209,6 +214,15 @@ class Plan:
                 offs = [int(v) for v in ragged_offsets]
             self.sizes, self.offsets = sizes, offs
             self.numel = max((o + s for o, s in zip(offs, sizes)), default=0)
+        elif self.real:
+            rows = int(self.desc.n[0]) if rank == 2 else 1
+            nr = int(self.desc.n[1]) if rank == 2 else int(self.desc.n[0])
+            #: float32 samples of the real side, complex64 bins of the spectrum side
+            self.real_numel = self.batch * rows * nr
+            self.cplx_numel = self.batch * rows * (nr // 2 + 1)
+            self.real_shape = (rows, nr) if rank == 2 else (nr,)
+            self.cplx_shape = (rows, nr // 2 + 1) if rank == 2 else (nr // 2 + 1,)
+            self.numel = self.cplx_numel
         else:
             per = int(self.desc.n[0]) * (int(self.desc.n[1]) if rank == 2 else 1)
             d = int(dist) if dist else per
@@ -233,11 +247,34 @@ class Plan:
 
     def exec(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, inverse: bool = False,
              stream=None) -> torch.Tensor:
+        if self.real:
+            return self._exec_real(x, out, inverse, stream)
         _check_tensor(x, self.numel, "x")
         if out is None:
             out = torch.empty_like(x)
         else:
             _check_tensor(out, self.numel, "out")
+        ws = self.workspace(x.device)
+        st = fft_exec(self.handle, x.data_ptr(), out.data_ptr(),
+                      FFT_INVERSE if inverse else FFT_FORWARD,
+                      ws.data_ptr() if ws is not None else 0, _stream_handle(stream))
+        if st != FFT_OK:
+            raise FftError(st, "fft_exec", fft_last_error())
+        return out
+
+    def _exec_real(self, x, out, inverse, stream):
+        if not inverse:
+            _check_tensor(x, self.real_numel, "x", torch.float32)
+            if out is None:
+                out = torch.empty((self.batch, *self.cplx_shape), dtype=torch.complex64,
+                                  device=x.device)
+            _check_tensor(out, self.cplx_numel, "out")
+        else:
+            _check_tensor(x, self.cplx_numel, "x")
+            if out is None:
+                out = torch.empty((self.batch, *self.real_shape), dtype=torch.float32,
+                                  device=x.device)
+            _check_tensor(out, self.real_numel, "out", torch.float32)
         ws = self.workspace(x.device)
         st = fft_exec(self.handle, x.data_ptr(), out.data_ptr(),
                       FFT_INVERSE if inverse else FFT_FORWARD,
@@ -281,11 +318,11 @@ def _stream_handle(stream) -> int:
     return int(getattr(stream, "cuda_stream", stream))
 
 
-def _check_tensor(t: torch.Tensor, numel: int, name: str):
+def _check_tensor(t: torch.Tensor, numel: int, name: str, dtype=torch.complex64):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if t.dtype != torch.complex64:
-        raise TypeError(f"{name} must be complex64, got {t.dtype}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must be on a GPU")
     if not t.is_contiguous():

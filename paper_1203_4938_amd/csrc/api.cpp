@@ -271,6 +271,42 @@ std::string MfmaStep::describe() const {
   return o.str();
 }
 
+// ---- real-input steps ----
+void RealStep::bind(const float2 *tables) {
+  a.tw = tables + tw_off;
+  a.tw2 = tables + tw2_off;
+  a.tw4_lo = tables + wn_off;
+}
+
+hipError_t RealStep::launch(const ExecCtx &ctx) const {
+  const float2 *s = buf_c(ctx, src, 0);
+  float2 *d = buf_m(ctx, dst, 0);
+  LineArgs args = a;
+  void *kargs[] = {(void *)&s, (void *)&d, (void *)&args};
+  return hipLaunchKernel(inv ? k.inv : k.fwd, grid, dim3(k.threads), kargs, 0, ctx.stream);
+}
+
+void RealStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const {
+  const int64_t nb = (int64_t)grid.x / a.tiles_per_batch;
+  const int64_t last_line = a.lines - 1;
+  // the spectrum side holds L + 1 elements per line, the real side L pairs
+  max_in = (nb - 1) * a.in_b + last_line * a.in_l + (inv ? L : L - 1);
+  max_out = (nb - 1) * a.out_b + last_line * a.out_l + (inv ? L - 1 : L);
+  src_id = src;
+  dst_id = dst;
+}
+
+bool RealStep::valid() const {
+  return k.fwd && k.inv && (int64_t)grid.x == a.tiles_per_batch * (grid.x / a.tiles_per_batch);
+}
+
+std::string RealStep::describe() const {
+  std::ostringstream o;
+  o << name << ": N=" << 2 * L << " (" << L << "-point complex core) C=" << k.lines
+    << " threads=" << k.threads << " grid=" << grid.x << " lds=" << k.lds_bytes << "B";
+  return o.str();
+}
+
 }  // namespace dpfft
 
 dpfft_plan_s::~dpfft_plan_s() {
@@ -718,6 +754,104 @@ fft_status_t plan_mfma_1d(dpfft_plan_s *P) {
   return FFT_OK;
 }
 
+// Real-input row step: lines of N = 2L reals <-> L + 1 bins.  `rows` lines per
+// batch item, items `real_b` float pairs apart on the real side and `cplx_b`
+// complex elements apart on the spectrum side.
+std::unique_ptr<RealStep> make_real(dpfft_plan_s *P, const char *name, int64_t N, bool inv,
+                                    int64_t rows, int64_t real_b, int64_t cplx_b) {
+  auto s = std::make_unique<RealStep>();
+  const int L = (int)(N / 2);
+  if (!real_kernel(L, &s->k)) return nullptr;
+  s->L = L;
+  s->inv = inv;
+  s->name = name;
+  s->tw_off = P->tables.add(stockham_table_pow2(L, 16));
+  {
+    std::vector<std::complex<double>> lo, hi;
+    fourstep_tables(L, tw2_shift(ilog2(L)), lo, hi);
+    lo.insert(lo.end(), hi.begin(), hi.end());
+    s->tw2_off = P->tables.add(lo);
+  }
+  std::vector<std::complex<double>> wn((size_t)L);
+  for (int k = 0; k < L; ++k) wn[(size_t)k] = omega(N, k);
+  s->wn_off = P->tables.add(wn);
+  const int C = s->k.lines;
+  if (!inv) {
+    s->a.in_b = real_b;
+    s->a.in_l = L;
+    s->a.out_b = cplx_b;
+    s->a.out_l = L + 1;
+  } else {
+    s->a.in_b = cplx_b;
+    s->a.in_l = L + 1;
+    s->a.out_b = real_b;
+    s->a.out_l = L;
+  }
+  s->a.in_e = s->a.out_e = 1;
+  s->a.lines = rows;
+  s->a.tiles_per_batch = (rows + C - 1) / C;
+  s->grid = dim3((unsigned)(P->batch * s->a.tiles_per_batch));
+  s->a.ntiles = s->grid.x;
+  s->a.scale = inv ? (float)(1.0 / (double)N) : 1.0f;
+  return s;
+}
+
+// Real-input batch of 1D signals: one launch per direction.
+fft_status_t plan_real_1d(dpfft_plan_s *P) {
+  const int64_t N = P->n, B = P->batch;
+  auto f = make_real(P, "real_forward", N, false, B, 0, 0);
+  auto i = make_real(P, "real_inverse", N, true, B, 0, 0);
+  if (!f || !i) return fail(FFT_E_UNSUPPORTED, "no real-input kernel for N=" + std::to_string(N));
+  P->steps.push_back(std::move(f));
+  P->isteps.push_back(std::move(i));
+  P->variant = "real single-pass";
+  return FFT_OK;
+}
+
+// Real-input images: forward = real rows -> ny x (nx/2 + 1) bins in `out`,
+// then the column transforms in place on `out`; inverse = column transforms
+// of `in` into the workspace (scale 1/ny), then the complex-to-real rows from
+// the workspace into `out` (scale 1/nx).
+fft_status_t plan_real_2d(dpfft_plan_s *P) {
+  const int64_t NY = P->ny, NX = P->nx, B = P->batch;
+  const int64_t W = NX / 2 + 1;  // bins per row
+  const Override ov = read_override();
+  auto rf = make_real(P, "real_rows", NX, false, NY, NY * NX / 2, NY * W);
+  auto ri = make_real(P, "real_rows_inverse", NX, true, NY, NY * NX / 2, NY * W);
+  if (!rf || !ri) return fail(FFT_E_UNSUPPORTED, "no real-input row kernel for nx=" + std::to_string(NX));
+  std::unique_ptr<LineStep> cf, ci;
+  if (NY > 1) {
+    cf = make_line(P, "columns", (int)NY, LINE_FAST, LINE_FAST, false, 64, 1, B * W, ov);
+    ci = make_line(P, "columns_inverse", (int)NY, LINE_FAST, LINE_FAST, false, 64, 0, B * W, ov);
+    if (!cf || !ci) return fail(FFT_E_UNSUPPORTED, "no column kernel for ny=" + std::to_string(NY));
+    for (LineStep *c : {cf.get(), ci.get()}) {
+      const int CC = c->k.lines;
+      c->a.in_b = c->a.out_b = NY * W;
+      c->a.in_l = c->a.out_l = 1;
+      c->a.in_e = c->a.out_e = W;
+      c->a.lines = W;
+      c->a.tiles_per_batch = (W + CC - 1) / CC;
+      c->a.flags = F_REMAP | F_ROUNDS;
+      c->grid = dim3((unsigned)(B * c->a.tiles_per_batch));
+      c->a.ntiles = c->grid.x;
+    }
+    cf->src = cf->dst = BUF_OUT;
+    ci->src = BUF_IN;
+    ci->dst = BUF_WS;
+    ci->first = ci->last = true;
+    ci->inv_scale = (float)(1.0 / (double)NY);
+    ri->src = BUF_WS;
+    ri->a.scale = (float)(1.0 / (double)NX);
+  }
+  P->steps.push_back(std::move(rf));
+  if (cf) P->steps.push_back(std::move(cf));
+  if (ci) P->isteps.push_back(std::move(ci));
+  P->isteps.push_back(std::move(ri));
+  P->ws_bytes = NY > 1 ? (size_t)B * (size_t)NY * (size_t)W * sizeof(float2) : 0;
+  P->variant = "real 2d rows+columns";
+  return FFT_OK;
+}
+
 fft_status_t validate_desc(const fft_desc_t *d) {
   if (!d) return fail(FFT_E_INVALID, "desc is NULL");
   if (d->rank != 1 && d->rank != 2) return fail(FFT_E_INVALID, "rank must be 1 or 2");
@@ -725,8 +859,20 @@ fft_status_t validate_desc(const fft_desc_t *d) {
   if (d->dist < 0) return fail(FFT_E_INVALID, "dist must be >= 0");
   if (d->precision < FFT_FP32 || d->precision > FFT_BF16_SPLIT3)
     return fail(FFT_E_INVALID, "unknown precision");
-  if (d->flags & ~(FFT_F_INPLACE | FFT_F_NO_AUTOTUNE | FFT_F_GRAPH | FFT_F_PER_SIZE))
+  if (d->flags & ~(FFT_F_INPLACE | FFT_F_NO_AUTOTUNE | FFT_F_GRAPH | FFT_F_PER_SIZE | FFT_F_REAL))
     return fail(FFT_E_INVALID, "unknown flag bits");
+  if (d->flags & FFT_F_REAL) {
+    if (d->ragged_sizes) return fail(FFT_E_UNSUPPORTED, "real-input plans are not ragged");
+    if (d->precision != FFT_FP32) return fail(FFT_E_UNSUPPORTED, "real-input plans are FFT_FP32");
+    if (d->flags & FFT_F_INPLACE) return fail(FFT_E_UNSUPPORTED, "real-input plans are out of place");
+    if (d->dist != 0) return fail(FFT_E_INVALID, "real-input plans are dense (dist must be 0)");
+    const int64_t nr = d->rank == 1 ? d->n[0] : d->n[1];
+    if (nr <= 0 || (d->rank == 2 && d->n[0] <= 0)) return fail(FFT_E_INVALID, "sizes must be >= 1");
+    if (!is_pow2(nr) || nr < 2 || nr > 2 * kSinglePassMax)
+      return fail(FFT_E_UNSUPPORTED, "real-input lengths are powers of two in [2, 32768]");
+    if (d->rank == 2 && (!is_pow2(d->n[0]) || d->n[0] > kSinglePassMax))
+      return fail(FFT_E_UNSUPPORTED, "real-input images need ny a power of two <= 16384");
+  }
   if (d->ragged_offsets && !d->ragged_sizes)
     return fail(FFT_E_INVALID, "ragged_offsets given without ragged_sizes");
   if (d->rank == 1) {
@@ -744,12 +890,14 @@ fft_status_t validate_desc(const fft_desc_t *d) {
     }
     const int64_t n = d->n[0];
     if (n <= 0) return fail(FFT_E_INVALID, "N must be >= 1");
+    if (d->flags & FFT_F_REAL) return FFT_OK;
     if (n > kMaxN) return fail(FFT_E_UNSUPPORTED, "N above 2^24");
     if (largest_prime_factor(n) > 7) return fail(FFT_E_UNSUPPORTED, "N has a prime factor above 7");
     if (d->dist != 0 && d->dist < n) return fail(FFT_E_INVALID, "dist must be 0 or >= N");
   } else {
     if (d->ragged_sizes) return fail(FFT_E_INVALID, "ragged batches are rank 1 only");
     if (d->n[0] <= 0 || d->n[1] <= 0) return fail(FFT_E_INVALID, "image sides must be >= 1");
+    if (d->flags & FFT_F_REAL) return FFT_OK;
     if (!is_pow2(d->n[0]) || !is_pow2(d->n[1]) || d->n[0] > kSinglePassMax ||
         d->n[1] > kSinglePassMax)
       return fail(FFT_E_UNSUPPORTED, "rank 2 needs power-of-two sides <= 16384");
@@ -809,7 +957,10 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
     ~Guard() { g_building = nullptr; }
   } guard(desc);
   const Override ov = read_override();
-  if (desc->rank == 1 && desc->ragged_sizes) {
+  P->real = (desc->flags & FFT_F_REAL) != 0;
+  if (P->real) {
+    st = desc->rank == 1 ? plan_real_1d(P.get()) : plan_real_2d(P.get());
+  } else if (desc->rank == 1 && desc->ragged_sizes) {
     st = plan_ragged(P.get(), desc->ragged_sizes, desc->ragged_offsets);
   } else if (desc->rank == 1) {
     if (desc->precision != FFT_FP32)
@@ -826,18 +977,33 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
     P->io_elems = P->batch == 0 ? 0
                   : P->rank == 1 ? (P->batch - 1) * P->dist + P->n
                                  : (P->batch - 1) * P->dist + P->ny * P->nx;
+  if (P->real) {
+    const int64_t per_real = P->rank == 1 ? P->n / 2 : P->ny * (P->nx / 2);
+    const int64_t per_cplx = P->rank == 1 ? P->n / 2 + 1 : P->ny * (P->nx / 2 + 1);
+    P->real_elems = P->batch * per_real;
+    P->cplx_elems = P->batch * per_cplx;
+    if (P->steps.size() != P->isteps.size())
+      return fail(FFT_E_INTERNAL, "real-input plan with unequal launch counts");
+  }
   if (P->batch > 0) {
-    for (auto &s : P->steps) {
-      int64_t mi, mo;
-      int si, di;
-      s->extent(mi, mo, si, di);
-      auto cap = [&](int id) -> int64_t {
-        return id == BUF_WS ? (int64_t)(P->ws_bytes / sizeof(float2)) : P->io_elems;
-      };
-      if (mi >= cap(si) || mo >= cap(di))
-        return fail(FFT_E_INTERNAL, "plan bounds check failed in " + s->describe());
-      if (!s->valid())
-        return fail(FFT_E_INTERNAL, "plan layout check failed in " + s->describe());
+    // both step lists; a real plan's buffers differ in size by direction
+    for (int dir = 0; dir < 2; ++dir) {
+      const auto &list = dir == 0 ? P->steps : P->isteps;
+      for (auto &s : list) {
+        int64_t mi, mo;
+        int si, di;
+        s->extent(mi, mo, si, di);
+        auto cap = [&](int id) -> int64_t {
+          if (id == BUF_WS) return (int64_t)(P->ws_bytes / sizeof(float2));
+          if (!P->real) return P->io_elems;
+          const bool real_side = (id == BUF_IN) == (dir == 0);
+          return real_side ? P->real_elems : P->cplx_elems;
+        };
+        if (mi >= cap(si) || mo >= cap(di))
+          return fail(FFT_E_INTERNAL, "plan bounds check failed in " + s->describe());
+        if (!s->valid())
+          return fail(FFT_E_INTERNAL, "plan layout check failed in " + s->describe());
+      }
     }
   }
 
@@ -855,7 +1021,12 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
     const std::string key = tune_key(desc);
     if (!key.empty()) o << " tune_key=" << key;
   }
+  if (P->real) o << " real-input";
   for (auto &s : P->steps) o << "\n  " << s->describe();
+  if (!P->isteps.empty()) {
+    o << "\n  inverse:";
+    for (auto &s : P->isteps) o << "\n  " << s->describe();
+  }
   P->text = o.str();
   out = std::move(P);
   return FFT_OK;
@@ -906,10 +1077,12 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
   if (st != FFT_OK) return st;
 
   // per-function launch attributes (dynamic LDS opt-in)
-  for (auto &s : P->steps) {
-    const hipError_t e = s->prepare();
-    if (e != hipSuccess)
-      return fail(FFT_E_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
+  for (const auto *list : {&P->steps, &P->isteps}) {
+    for (auto &s : *list) {
+      const hipError_t e = s->prepare();
+      if (e != hipSuccess)
+        return fail(FFT_E_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
+    }
   }
 
   // upload every table in one allocation
@@ -928,6 +1101,7 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
       return fail(FFT_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
   }
   for (auto &s : P->steps) s->bind(P->tables.dev);
+  for (auto &s : P->isteps) s->bind(P->tables.dev);
   if (getenv("DPFFT_LOG")) fprintf(stderr, "[dpfft] plan %s\n", P->text.c_str());
   *out = P.release();
   return FFT_OK;
@@ -948,8 +1122,9 @@ static fft_status_t exec_range(fft_plan_t plan, const void *in, void *out, int d
     return fail(FFT_E_INVALID, "in == out needs FFT_F_INPLACE");
   if (plan->ws_bytes && !workspace) return fail(FFT_E_INVALID, "plan needs a workspace");
   ExecCtx ctx{in, out, workspace, (hipStream_t)hip_stream, direction == FFT_INVERSE};
+  const auto &list = ctx.inverse && !plan->isteps.empty() ? plan->isteps : plan->steps;
   for (int i = first; i < first + count; ++i) {
-    hipError_t e = plan->steps[i]->launch(ctx);
+    hipError_t e = list[i]->launch(ctx);
     if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   }
   return FFT_OK;

@@ -143,7 +143,8 @@ void tune_cache_store(const std::string &key, const std::string &value) {
 using namespace dpfft;
 
 std::string tune_key(const fft_desc_t *d) {
-  if (!d || d->ragged_sizes || d->precision != FFT_FP32 || d->batch <= 0) return "";
+  if (!d || d->ragged_sizes || d->precision != FFT_FP32 || d->batch <= 0 || (d->flags & FFT_F_REAL))
+    return "";
   int bucket = 0;
   while ((int64_t(1) << (bucket + 1)) <= d->batch) ++bucket;
   std::ostringstream o;
@@ -247,7 +248,7 @@ extern "C" fft_status_t fft_autotune(const fft_desc_t *desc, void *hip_stream, i
     return st;
   };
   if (key.empty()) {
-    rep << "nothing to tune (ragged, precision form or empty batch)";
+    rep << "nothing to tune (ragged, precision form, real-input or empty batch)";
     return finish(FFT_OK);
   }
   const std::vector<std::string> cands = candidates(desc);

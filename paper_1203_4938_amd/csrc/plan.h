@@ -13,6 +13,7 @@
 #include "kernels.h"
 #include "mixed.h"
 #include "mfma.h"
+#include "real.h"
 
 namespace dpfft {
 
@@ -123,6 +124,25 @@ struct MfmaStep : Step {
   bool valid() const override;
 };
 
+// Real-input line kernel: N = 2L reals <-> L + 1 bins per line, one launch.
+// Forward plans run the R2C kernel, inverse plans the C2R kernel (each step
+// list is used for one direction only).
+struct RealStep : Step {
+  RealKernel k;
+  int L = 0;
+  bool inv = false;
+  dim3 grid;
+  int src = BUF_IN, dst = BUF_OUT;
+  LineArgs a{};
+  size_t tw_off = 0, tw2_off = 0, wn_off = 0;
+  std::string name;
+  void bind(const float2 *tables) override;
+  hipError_t launch(const ExecCtx &ctx) const override;
+  std::string describe() const override;
+  void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
+  bool valid() const override;
+};
+
 }  // namespace dpfft
 
 struct dpfft_plan_s {
@@ -134,7 +154,11 @@ struct dpfft_plan_s {
   int32_t precision = FFT_FP32;
   uint32_t flags = 0;
   std::vector<int64_t> rsizes, roffsets;  // ragged
-  std::vector<std::unique_ptr<dpfft::Step>> steps;
+  std::vector<std::unique_ptr<dpfft::Step>> steps;   // forward (and inverse, if isteps is empty)
+  std::vector<std::unique_ptr<dpfft::Step>> isteps;  // inverse launches where they differ
+  bool real = false;          // FFT_F_REAL: real samples <-> N/2 + 1 bins
+  int64_t real_elems = 0;     // real plans: float pairs of the real-side buffer
+  int64_t cplx_elems = 0;     // real plans: complex elements of the spectrum buffer
   dpfft::TableSet tables;
   size_t ws_bytes = 0;
   int64_t io_elems = 0;       // complex elements of `in` / `out` the plan touches

@@ -159,3 +159,45 @@ def test_plans_with_signals_far_apart():
     assert "variant=single-pass" in t and "C=16" in t and "persistent" in t
     t = _dry(n=1 << 16, batch=2, dist=1 << 28)
     assert "four-step" in t
+
+
+@pytest.mark.parametrize("n", [2, 4, 64, 2048, 32768])
+def test_real_1d_plans(n):
+    dp = _dp()
+    t = _dry(n=n, batch=5, flags=dp.FFT_F_REAL)
+    assert "variant=real single-pass" in t and "launches=1" in t and "workspace=0B" in t
+    assert f"real_forward: N={n} ({n // 2}-point complex core)" in t
+    assert f"real_inverse: N={n}" in t
+
+
+def test_real_2d_plan_layout():
+    """Forward: real rows then in-place columns over nx/2 + 1 columns; inverse:
+    columns into a workspace of batch * ny * (nx/2 + 1) complex64, then the
+    complex-to-real rows."""
+    dp = _dp()
+    t = _dry(rank=2, shape=(2048, 2048), batch=16, flags=dp.FFT_F_REAL)
+    assert "variant=real 2d rows+columns" in t and "launches=2" in t
+    assert f"workspace={16 * 2048 * 1025 * 8}B" in t
+    fwd, inv = t.split("\n  inverse:")
+    assert fwd.index("real_rows:") < fwd.index("columns:")
+    assert inv.index("columns_inverse:") < inv.index("real_rows_inverse:")
+    # 1025 columns in tiles of 8: 129 tiles per image
+    assert "grid=2064" in inv
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=64, batch=2, flags=16 | 1), "FFT_E_UNSUPPORTED"),      # in place
+    (dict(n=96, batch=2, flags=16), "FFT_E_UNSUPPORTED"),          # not a power of two
+    (dict(n=1, batch=2, flags=16), "FFT_E_UNSUPPORTED"),           # N = 1 has no pairs
+    (dict(n=65536, batch=2, flags=16), "FFT_E_UNSUPPORTED"),       # above one pass
+    (dict(n=64, batch=2, dist=64, flags=16), "FFT_E_INVALID"),     # dense only
+    (dict(n=64, batch=2, flags=16, precision="bf16"), "FFT_E_UNSUPPORTED"),
+    (dict(rank=2, shape=(3, 64), batch=1, flags=16), "FFT_E_UNSUPPORTED"),
+    (dict(rank=2, shape=(32768, 64), batch=1, flags=16), "FFT_E_UNSUPPORTED"),
+    (dict(ragged_sizes=[64, 128], flags=16), "FFT_E_UNSUPPORTED"),
+])
+def test_real_plans_rejected(kw, status):
+    dp = _dp()
+    d, keep = dp.make_desc(**kw)
+    st, msg = dp.fft_plan_dry(d)
+    assert dp.fft_status_str(st) == status, msg
