@@ -68,9 +68,10 @@ class OracleLib:
         lib.oracle_fft2d_f32.argtypes = [fp, dp, i64, i64, i64, ci, ci]
         lib.oracle_threads.argtypes = [ci]
         lib.oracle_rel_l2_f32.argtypes = [fp, dp, i64, i64, dp, dp, ci]
+        lib.oracle_circular_conv_f32.argtypes = [fp, fp, dp, i64, i64, i64, ci]
         for f in (lib.oracle_dft, lib.oracle_fft, lib.oracle_fft_batch_f32,
                   lib.oracle_fft_ragged_f32, lib.oracle_fft2d_f32, lib.oracle_threads,
-                  lib.oracle_rel_l2_f32):
+                  lib.oracle_rel_l2_f32, lib.oracle_circular_conv_f32):
             f.restype = ci
         self.lib = lib
         self.path = path
@@ -122,6 +123,24 @@ class OracleLib:
         y = np.empty(x.shape, dtype=np.complex128)
         _check(self.lib.oracle_fft2d_f32(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_double),
                                          ny, nx, batch, int(inverse), threads))
+        return y
+
+    def circular_conv(self, x, h, threads: int = 0) -> np.ndarray:
+        """Circular convolution over the last axis from its definition (O(N^2)
+        per signal): complex64 signals ``x`` (..., n) with filters ``h`` of
+        shape (n,) (one filter for all) or the shape of ``x`` (one per signal)
+        -> complex128."""
+        x = _c64(x)
+        h = _c64(h)
+        n = x.shape[-1]
+        batch = x.size // n if n else 0
+        if h.shape[-1] != n or h.size not in (n, x.size):
+            raise ValueError(f"filter shape {h.shape} does not fit signals {x.shape}")
+        h_dist = 0 if h.size == n else n
+        y = np.empty(x.shape, dtype=np.complex128)
+        _check(self.lib.oracle_circular_conv_f32(_ptr(x, ctypes.c_float), _ptr(h, ctypes.c_float),
+                                                 _ptr(y, ctypes.c_double), n, batch, h_dist,
+                                                 threads))
         return y
 
     def threads(self, requested: int = 0) -> int:
@@ -176,6 +195,10 @@ def fft_ragged(flat, sizes, offsets, inverse: bool = False, threads: int = 0) ->
 
 def fft2d(x, inverse: bool = False, threads: int = 0) -> np.ndarray:
     return default().fft2d(x, inverse, threads)
+
+
+def circular_conv(x, h, threads: int = 0) -> np.ndarray:
+    return default().circular_conv(x, h, threads)
 
 
 def threads(requested: int = 0) -> int:

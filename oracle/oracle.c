@@ -316,3 +316,36 @@ int oracle_rel_l2_f32(const float *y, const double *ref, int64_t n,
     }
     return 0;
 }
+
+/*
+ * Circular convolution, straight from its definition.  Section III-A names
+ * convolution and polynomial multiplication among the uses of the DFT; the
+ * convolution theorem makes DFT(x conv h) = DFT(x) * DFT(h) bin by bin, which
+ * is what a transform-based method computes.  Here no transform is used:
+ *     y_b[j] = sum_{m=0}^{n-1} x_b[m] * h_b[(j - m) mod n],   j = 0..n-1,
+ * accumulated in double, O(n^2) per signal.  h_b is filter b (h_dist complex
+ * elements apart) or the single filter h when h_dist == 0.
+ */
+int oracle_circular_conv_f32(const float *x, const float *h, double *y, int64_t n,
+                             int64_t batch, int64_t h_dist, int threads) {
+    if (!x || !h || !y || n <= 0 || batch < 0 || h_dist < 0) return -1;
+#pragma omp parallel for schedule(static) num_threads(oracle_threads(threads))
+    for (int64_t b = 0; b < batch; ++b) {
+        const float *xb = x + 2 * b * n;
+        const float *hb = h + 2 * b * h_dist;
+        double *yb = y + 2 * b * n;
+        for (int64_t j = 0; j < n; ++j) {
+            double sr = 0.0, si = 0.0;
+            for (int64_t m = 0; m < n; ++m) {
+                const int64_t t = ((j - m) % n + n) % n;
+                const double xr = xb[2 * m], xi = xb[2 * m + 1];
+                const double hr = hb[2 * t], hi = hb[2 * t + 1];
+                sr += xr * hr - xi * hi;
+                si += xr * hi + xi * hr;
+            }
+            yb[2 * j] = sr;
+            yb[2 * j + 1] = si;
+        }
+    }
+    return 0;
+}

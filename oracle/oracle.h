@@ -59,6 +59,14 @@ int oracle_rel_l2_f32(const float *y, const double *ref, int64_t n,
                       int64_t batch, double *err, double *ref_norm,
                       int threads);
 
+/* Circular convolution of `batch` signals of length n (consecutive signals n
+ * apart) with filters h, from the definition:
+ *   y_b[j] = sum_{m=0}^{n-1} x_b[m] h_b[(j - m) mod n]
+ * h_b starts h_dist complex elements after h_{b-1} (h_dist = 0: one filter
+ * for every signal).  x, h: float32 pairs; y: double pairs. */
+int oracle_circular_conv_f32(const float *x, const float *h, double *y, int64_t n,
+                             int64_t batch, int64_t h_dist, int threads);
+
 /* Number of OpenMP threads a parallel region will use with `threads`. */
 int oracle_threads(int threads);
 

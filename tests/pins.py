@@ -15,7 +15,10 @@ textbook definition X[k] = sum_j x[j] exp(-2 pi i j k / N)):
   * invariants: linearity, Parseval, shift theorem, round trip, Hermitian
     symmetry of real input (1D and 2D), exact integer DC bin of an image;
   * an independent library, numpy.fft (pocketfft), for batched, ragged and 2D
-    shapes.
+    shapes;
+  * circular convolution: delta and shifted delta, polynomial products with
+    exact binomial coefficients, numpy's linear convolution, and the
+    convolution theorem with the oracle's FFT.
 """
 from __future__ import annotations
 
@@ -273,9 +276,87 @@ def pin_image_2d(o, quick=False):
     return dc_ok and herm <= TOL, f"dc={X[0, 0]} vs {img.sum()}, hermitian rel {herm:.2e}"
 
 
+# ---------------------------------------------------------------------------
+# circular convolution (section III-A names convolution and polynomial
+# multiplication among the uses of the DFT): y[j] = sum_m x[m] h[(j - m) mod n]
+# ---------------------------------------------------------------------------
+def pin_conv_delta_and_shift(o, quick=False):
+    """h = delta[j - s] moves x by s places, exactly (s = 0: y = x)."""
+    rng = _rng(21)
+    ok = True
+    for n in (1, 2, 7, 16, 60):
+        x = _crand(rng, 3, n).astype(np.complex64)
+        for s in sorted({0, 1 % n, n - 1, n // 2}):
+            h = np.zeros(n, np.complex64)
+            h[s] = 1.0
+            y = o.circular_conv(x, h)
+            ok &= bool(np.array_equal(y, np.roll(x.astype(np.complex128), s, axis=-1)))
+    return ok, "delta and shifted delta"
+
+
+def pin_conv_polynomial(o, quick=False):
+    """Polynomial multiplication: (1 + z)^p (1 + z)^q = (1 + z)^(p+q), whose
+    coefficients are binomial numbers, exact in double; zero padding to
+    n > p + q makes the circular product the ordinary one.  Also (1 + i z)^p
+    times (1 - i z)^p = (1 + z^2)^p."""
+    from math import comb
+    ok = True
+    for p_, q_, n in ((3, 4, 8), (7, 9, 32), (12, 5, 18)):
+        a = np.zeros(n, np.complex64)
+        b = np.zeros(n, np.complex64)
+        a[: p_ + 1] = [comb(p_, k) for k in range(p_ + 1)]
+        b[: q_ + 1] = [comb(q_, k) for k in range(q_ + 1)]
+        want = np.zeros(n)
+        want[: p_ + q_ + 1] = [comb(p_ + q_, k) for k in range(p_ + q_ + 1)]
+        ok &= bool(np.array_equal(o.circular_conv(a, b), want.astype(np.complex128)))
+    p_, n = 6, 16
+    a = np.array([comb(p_, k) * (1j ** k) for k in range(p_ + 1)] + [0] * (n - p_ - 1), np.complex64)
+    b = np.array([comb(p_, k) * ((-1j) ** k) for k in range(p_ + 1)] + [0] * (n - p_ - 1),
+                 np.complex64)
+    want = np.zeros(n, np.complex128)
+    want[0: 2 * p_ + 1: 2] = [comb(p_, k) for k in range(p_ + 1)]
+    ok &= bool(np.array_equal(o.circular_conv(a, b), want))
+    return ok, "binomial products"
+
+
+def pin_conv_numpy(o, quick=False):
+    """Independent library: the circular convolution is the middle of numpy's
+    linear convolution of x with two periods of h (per-signal filters and one
+    shared filter)."""
+    rng = _rng(22)
+    worst = 0.0
+    for n in (5, 64, 210):
+        x = _crand(rng, 4, n).astype(np.complex64)
+        hs = _crand(rng, 4, n).astype(np.complex64)
+        y1 = o.circular_conv(x, hs)
+        y2 = o.circular_conv(x, hs[1])
+        for b in range(4):
+            xd = x[b].astype(np.complex128)
+            for y, h in ((y1[b], hs[b]), (y2[b], hs[1])):
+                hh = np.concatenate([h, h]).astype(np.complex128)
+                ref = np.convolve(xd, hh)[n:2 * n]
+                worst = max(worst, _rel(y, ref))
+    return worst <= TOL, f"max rel {worst:.2e}"
+
+
+def pin_conv_theorem(o, quick=False):
+    """Convolution theorem: DFT(x conv h) = DFT(x) DFT(h), with the oracle's
+    own recursive FFT on both sides."""
+    rng = _rng(23)
+    worst = 0.0
+    for n in (8, 45, 256):
+        x = _crand(rng, n).astype(np.complex64)
+        h = _crand(rng, n).astype(np.complex64)
+        lhs = o.fft(o.circular_conv(x, h))
+        rhs = o.fft(x.astype(np.complex128)) * o.fft(h.astype(np.complex128))
+        worst = max(worst, _rel(lhs, rhs))
+    return worst <= TOL, f"max rel {worst:.2e}"
+
+
 ALL_PINS = [pin_golden, pin_fft_vs_dft, pin_impulse, pin_constant, pin_tone, pin_geometric,
             pin_linearity, pin_parseval, pin_shift, pin_round_trip, pin_hermitian,
-            pin_numpy_batch, pin_numpy_ragged, pin_numpy_2d, pin_image_2d]
+            pin_numpy_batch, pin_numpy_ragged, pin_numpy_2d, pin_image_2d,
+            pin_conv_delta_and_shift, pin_conv_polynomial, pin_conv_numpy, pin_conv_theorem]
 
 
 def run_all(o, quick=True):

@@ -38,6 +38,12 @@ MUTANTS = [
     ("fft2d_column_gather_transposed", "col[r] = out[r * nx + c];", "col[r] = out[c * ny + r];", 0),
     ("fft2d_inverse_scale", "double s = 1.0 / ((double)nx * (double)ny);", "double s = 1.0 / (double)nx;", 0),
     ("fft2d_inverse_input_not_conjugated", "double sg = inverse ? -1.0 : 1.0;", "double sg = 1.0;", 0),
+    ("conv_index_sign", "const int64_t t = ((j - m) % n + n) % n;",
+     "const int64_t t = ((j + m) % n + n) % n;", 0),
+    ("conv_drops_cross_term", "sr += xr * hr - xi * hi;", "sr += xr * hr;", 0),
+    ("conv_imag_sign", "si += xr * hi + xi * hr;", "si += xr * hi - xi * hr;", 0),
+    ("conv_filter_dist_ignored", "const float *hb = h + 2 * b * h_dist;", "const float *hb = h;", 0),
+    ("conv_signal_stride", "const float *xb = x + 2 * b * n;", "const float *xb = x + b * n;", 0),
 ]
 
 
