@@ -45,6 +45,8 @@ def parse():
                     help="seconds of CPU oracle work for the baseline sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 1 GiB device copy (bandwidth reference)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c2: skip the comparison entries timed after the step")
     return ap.parse_args()
 
 
@@ -94,18 +96,47 @@ class Item:
         self.torch = torch
 
     def run(self, events=None):
-        """forward x -> y, inverse y -> x; one launch at a time when timing."""
+        """forward x -> y, inverse y -> x; one launch at a time when timing a
+        step item, each direction as a whole for a comparison item."""
         for inv, (src, dst) in ((False, (self.x, self.y)), (True, (self.y, self.x))):
             if events is None:
                 self.plan.exec(src, out=dst, inverse=inv)
-                continue
-            for s in range(self.nsteps):
-                e0 = self.torch.cuda.Event(enable_timing=True)
-                e1 = self.torch.cuda.Event(enable_timing=True)
-                e0.record()
-                self.plan.exec_steps(src, dst, s, 1, inverse=inv)
-                e1.record()
-                events.append((self.name, s, e0, e1))
+            elif self.compare:
+                timed(self.torch, events, self.name, -1, lambda: self.plan.exec(src, out=dst, inverse=inv))
+            else:
+                for s in range(self.nsteps):
+                    timed(self.torch, events, self.name, s,
+                          lambda: self.plan.exec_steps(src, dst, s, 1, inverse=inv))
+
+
+def timed(torch, events, name, s, fn):
+    """Run fn between two HIP events recorded on the current stream (the
+    stream every launch of this benchmark goes to)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    events.append((name, s, e0, e1))
+
+
+class MultiItem:
+    """A comparison entry made of several callables per direction (one plan per
+    distinct length, or forward + product + inverse); timed per direction as a
+    whole."""
+
+    def __init__(self, torch, name, fwd, inv, flop, alg_bytes, desc):
+        self.torch, self.name, self.fwd, self.inv = torch, name, fwd, inv
+        self.flop, self.alg_bytes, self.desc = flop, alg_bytes, desc
+        self.compare = True
+        self.nsteps = 1
+
+    def run(self, events=None):
+        for fn in (self.fwd, self.inv):
+            if events is None:
+                fn()
+            else:
+                timed(self.torch, events, self.name, -1, fn)
 
 
 def build_c2(dp, torch, synth, dev):
@@ -163,7 +194,8 @@ def build_c5(dp, torch, synth, dev):
     items = []
     for name, kw, cmp in (("ragged10000_persistent_graph", dict(graph=True), False),
                           ("ragged10000_persistent", dict(), True),
-                          ("ragged10000_per_length_launches", dict(per_size=True), True)):
+                          ("ragged10000_one_launch_per_length_runtime_radix", dict(per_size=True),
+                           True)):
         p = dp.Plan(ragged_sizes=sizes.tolist(), **kw)
         items.append(Item(dp, torch, name, p, x.clone(), torch.empty_like(x), fl,
                           16.0 * float(sizes.sum()), compare=cmp))
@@ -171,6 +203,98 @@ def build_c5(dp, torch, synth, dev):
                                "log-uniform; the step is the two persistent launches in a HIP "
                                "graph; the same launches without the graph and one launch per "
                                "distinct length are timed after it for comparison"}
+
+
+def build_c5_fair(dp, torch, synth, dev):
+    """Per-length baseline: the c5 signals grouped by length (the gather into
+    that order is not timed) and one batched plan per distinct length, each on
+    the library's compile-time kernels where the length is a power of two."""
+    import numpy as np
+    sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
+    order = np.argsort(sizes, kind="stable")
+    flat, offs = synth.uniform_ragged(synth.BASE_SEED + 5, sizes)
+    parts = [flat[offs[i]:offs[i] + sizes[i]] for i in order]
+    x = torch.from_numpy(np.concatenate(parts)).to(dev)
+    y = torch.empty_like(x)
+    plans, o = [], 0
+    for n in np.unique(sizes):
+        cnt = int((sizes == n).sum())
+        plans.append((dp.Plan(int(n), cnt), o, int(n) * cnt))
+        o += int(n) * cnt
+
+    def go(src, dst, inv):
+        for p, o0, m in plans:
+            p.exec(src[o0:o0 + m], out=dst[o0:o0 + m], inverse=inv)
+
+    fl = float(sum(flops(int(n), 1) for n in sizes))
+    return MultiItem(torch, "ragged10000_one_plan_per_length", lambda: go(x, y, False),
+                     lambda: go(y, x, True), fl, 16.0 * float(sizes.sum()),
+                     f"{len(plans)} batched plans, one per distinct length, signals grouped by length")
+
+
+def build_conv(dp, torch, synth, dev):
+    """Fused circular convolution against forward + product + inverse: N = 4096,
+    batch 32768 (1 GiB), one shared filter."""
+    n, b = 4096, 32768
+    x = synth.uniform_complex_torch(synth.BASE_SEED + 6, n, b, dev)
+    h = synth.uniform_complex_torch(synth.BASE_SEED + 6 + 7777, n, 1, dev)
+    p = dp.Plan(n, b, conv=True)
+    H = dp.Plan(n, 1).exec(h).reshape(-1)
+    y = torch.empty_like(x)
+    fl = b * (2 * 5.0 * n * math.log2(n) + 6.0 * n)
+    fused = MultiItem(torch, "conv4096_b32768_fused", lambda: p.conv(x, H, out=y),
+                      lambda: p.conv(y, H, out=x), fl, 16.0 * n * b,
+                      p.describe().splitlines()[-1].strip())
+    z = torch.empty_like(x)
+
+    def unfused_fwd():
+        p.exec(x, out=z)
+        z.mul_(H)
+        p.exec(z, out=y, inverse=True)
+
+    def unfused_inv():
+        p.exec(y, out=z)
+        z.mul_(H)
+        p.exec(z, out=x, inverse=True)
+
+    three = MultiItem(torch, "conv4096_b32768_unfused", unfused_fwd, unfused_inv, fl,
+                      16.0 * n * b, "fft_exec forward, torch mul_ by H, fft_exec inverse "
+                                    "(three HBM round trips)")
+    return [fused, three]
+
+
+def build_real(dp, torch, synth, dev):
+    """The c3 images as real input: 16 x 2048^2 float32 -> 16 x 2048 x 1025 bins."""
+    import numpy as np
+    imgs = np.stack([synth.smooth_noise_image(synth.BASE_SEED + 3, i) for i in range(16)])
+    x = torch.from_numpy(np.ascontiguousarray(imgs.astype(np.float32))).to(dev)
+    p = dp.Plan(shape=(2048, 2048), batch=16, rank=2, real=True)
+    spec = torch.empty((16, 2048, 1025), dtype=torch.complex64, device=dev)
+    n = 2048 * 2048
+    # real transforms: half the conventional complex flop count; bytes: 4 B per
+    # sample read plus 8 B per bin written (the inverse: the reverse)
+    alg = 16 * (4.0 * n + 8.0 * 2048 * 1025)
+    return MultiItem(torch, "img2048_b16_real", lambda: p.exec(x, out=spec),
+                     lambda: p.exec(spec, out=x, inverse=True), 0.5 * flops(n, 16), alg,
+                     p.describe().splitlines()[0])
+
+
+def build_extras(dp, torch, synth, dev):
+    """Comparison entries timed after the c2 step: the c4 precision forms, the
+    c5 ragged batch (graph, no graph, one plan per length, one launch per
+    length), the c3 images as complex and as real input, and the fused
+    convolution against its unfused chain."""
+    out = []
+    c4, _ = build_c4(dp, torch, synth, dev)
+    c5, _ = build_c5(dp, torch, synth, dev)
+    c3, _ = build_c3(dp, torch, synth, dev)
+    for it in c4 + c5 + c3:
+        it.compare = True
+        out.append(it)
+    out.append(build_c5_fair(dp, torch, synth, dev))
+    out.append(build_real(dp, torch, synth, dev))
+    out.extend(build_conv(dp, torch, synth, dev))
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -211,26 +335,55 @@ def cpu_baseline(budget_s: float):
         sample.append(f"N=2^{int(math.log2(n))}: {done_sig}/{b} signals")
         total_t += 2 * flops(n, b) / rate
         total_f += 2 * flops(n, b)
+    # one thread, one size (N = 2^14), about two seconds of work
+    n1, k1, t1s, f1 = 1 << 14, 0, 0.0, 0.0
+    while t1s < 2.0 and k1 < 4096:
+        x = synth.uniform_complex(seed, n1, 8, first=k1)
+        t0 = time.perf_counter()
+        oracle.fft_batch(x, inverse=False, threads=1)
+        t1s += time.perf_counter() - t0
+        f1 += flops(n1, 8)
+        k1 += 8
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(total_f / total_t / 1e9, 4), "unit": "GFLOP/s", "cores": thr,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_cpus_visible": os.cpu_count(),
+            "one_thread": {"value": round(f1 / t1s / 1e9, 4), "unit": "GFLOP/s",
+                           "sample": f"forward transforms of {k1} signals of N=2^14, 1 thread"},
             "sample": "forward+inverse of a prefix of each c2 batch (" + "; ".join(sample) +
                       "), each size's rate scaled to its full batch",
             "per_size_gflops": {f"2^{int(math.log2(n))}": round(r / 1e9, 4) for n, r in per.items()}}
 
 
 def copy_probe(torch, dev, reps=10):
+    """Two plain 1 GiB device-to-device passes of known traffic (1 GiB read,
+    1 GiB written each): torch's copy (a blit kernel) and an elementwise
+    float64 negation (8-byte loads and stores over the whole buffer).  Their
+    rates are a practical bandwidth reference; their FETCH_SIZE / WRITE_SIZE
+    readings calibrate the counters (two points)."""
     a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return 2 * a.numel() * 4 / (ms * 1e-3) / 1e9
+    a64, b64 = a.view(torch.float64), b.view(torch.float64)
+    res = {}
+    for name, fn in (("copy", lambda: b.copy_(a)), ("neg_f64", lambda: torch.neg(a64, out=b64))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    return res
 
 
 def main():
@@ -249,6 +402,9 @@ def main():
     builder = {"c1": build_c1, "c2": build_c2, "c3": build_c3, "c4": build_c4, "c5": build_c5}
     items, cfg = builder[args.config](dp, torch, synth, dev)
     print(f"# {cfg['workload']}", file=sys.stderr, flush=True)
+    if args.config == "c2" and not args.no_extras:
+        items += build_extras(dp, torch, synth, dev)
+        print(f"# {len(items)} entries planned", file=sys.stderr, flush=True)
 
     probe = copy_probe(torch, dev) if args.copy_probe else None
 
@@ -281,17 +437,23 @@ def main():
     value = step_flop / (ms_step * 1e-3) / 1e9
     breakdown = {}
     for it in items:
-        tot_ms = sum(sum(kern[(it.name, s)]) for s in range(it.nsteps)) / args.steps / 2
-        breakdown[it.name] = {
+        if it.compare:
+            tot_ms = sum(kern[(it.name, -1)]) / args.steps / 2
+        else:
+            tot_ms = sum(sum(kern[(it.name, s)]) for s in range(it.nsteps)) / args.steps / 2
+        ent = {
             "ms_per_transform": round(tot_ms, 4),
             "gflops": round(it.flop / (tot_ms * 1e-3) / 1e9, 1),
             "hbm_frac_alg": round(it.alg_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-            "kernels": [{"launch": s, "avg_ms": round(sum(kern[(it.name, s)]) / len(kern[(it.name, s)]), 4)}
-                        for s in range(it.nsteps)],
-            "plan": it.plan.describe().splitlines()[0],
         }
         if it.compare:
-            breakdown[it.name]["comparison_only"] = True
+            ent["comparison_only"] = True
+        else:
+            ent["kernels"] = [{"launch": s, "avg_ms": round(sum(kern[(it.name, s)]) /
+                                                            len(kern[(it.name, s)]), 4)}
+                              for s in range(it.nsteps)]
+        ent["plan"] = it.desc if isinstance(it, MultiItem) else it.plan.describe().splitlines()[0]
+        breakdown[it.name] = ent
     # dominant kernel: largest total time over the step
     step_names = {it.name for it in step_items}
     (dn, ds), dur = max(((k, v) for k, v in kern.items() if k[0] in step_names),
@@ -312,7 +474,7 @@ def main():
            "data": "synthetic (seeded SplitMix64 uniform[-1,1) complex64)",
            "config": cfg, "roofline": roof, "breakdown": breakdown}
     if probe is not None:
-        out["copy_probe_GBps"] = round(probe, 1)
+        out["copy_probe_GBps"] = probe
     if not args.no_cpu and args.config == "c2":
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     else:

@@ -78,6 +78,7 @@ typedef enum {
 #define FFT_F_PER_SIZE 8u    /* ragged plans: one launch per distinct length instead of
                                 the two persistent launches (the comparison baseline) */
 #define FFT_F_REAL 16u       /* real samples (see "Real-input transforms" below) */
+#define FFT_F_CONV 32u       /* the plan also runs fft_conv_exec (circular convolution) */
 
 typedef struct {
   int32_t rank;     /* 1: batched 1D signals; 2: batched images */
@@ -176,6 +177,37 @@ fft_status_t fft_plan_dry(const fft_desc_t *desc, char *buf, size_t len);
  * (FFT_OK, report says so). */
 fft_status_t fft_autotune(const fft_desc_t *desc, void *hip_stream, int reps, char *report,
                           size_t len);
+
+/*
+ * Fused circular convolution (plans made with FFT_F_CONV).  Section III-A of
+ * the paper names convolution and polynomial multiplication among the uses of
+ * the DFT, and section IV names the data movement between chained instances
+ * as the platform's inefficiency; this call chains forward transform,
+ * product and inverse transform on chip.  For every signal b of the batch:
+ *
+ *   out_b[j] = sum_{m=0}^{N-1} in_b[m] h_b[(j - m) mod N]
+ *            = IDFT( DFT(in_b) * H_b )[j]            (j = 0..N-1)
+ *
+ * where H_b = DFT(h_b) is the filter's spectrum in natural order, exactly as
+ * fft_exec(plan, h, H, FFT_FORWARD, ...) stores it.  Polynomial products are
+ * the special case of zero-padded coefficient vectors (N >= deg a + deg b + 1).
+ *   in, out      device pointers, interleaved complex64, the plan's layout
+ *                (dist); in == out requires FFT_F_INPLACE
+ *   filter       device pointer to the spectra H_b, complex64; spectrum b
+ *                starts filter_dist elements after spectrum b-1, and
+ *                filter_dist = 0 means one spectrum shared by every signal;
+ *                the caller guarantees (batch-1)*filter_dist + N elements
+ *   workspace    at least fft_workspace_bytes(plan) bytes (N > 16384 only)
+ * Supported: FFT_FP32, rank 1, N a power of two in [1, 2^24], not ragged,
+ * not real.  N <= 16384 runs as one launch (one HBM read of in and H, one
+ * write of out); longer N as three (the four-step column pass, a fused row
+ * launch, the inverse column pass).  Errors: FFT_E_INVALID for a plan made
+ * without FFT_F_CONV, NULL or misaligned pointers, a negative filter_dist or
+ * one below N (checked before any launch); FFT_E_DEVICE for a failed launch.
+ * Asynchronous on hip_stream, like fft_exec.
+ */
+fft_status_t fft_conv_exec(fft_plan_t plan, const void *in, const void *filter,
+                           int64_t filter_dist, void *out, void *workspace, void *hip_stream);
 
 /* Release a plan and its device tables.  fft_destroy(NULL) returns FFT_OK.
  * The caller must ensure no execution of the plan is still pending. */

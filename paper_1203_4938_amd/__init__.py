@@ -21,13 +21,14 @@ LIB_PATH = os.path.join(_HERE, "libdpfft.so")
 
 FFT_OK, FFT_E_INVALID, FFT_E_UNSUPPORTED, FFT_E_NOMEM, FFT_E_DEVICE, FFT_E_INTERNAL = range(6)
 FFT_FORWARD, FFT_INVERSE = -1, +1
-FFT_F_INPLACE, FFT_F_NO_AUTOTUNE, FFT_F_GRAPH, FFT_F_PER_SIZE, FFT_F_REAL = 1, 2, 4, 8, 16
+FFT_F_INPLACE, FFT_F_NO_AUTOTUNE, FFT_F_GRAPH, FFT_F_PER_SIZE, FFT_F_REAL, FFT_F_CONV = \
+    1, 2, 4, 8, 16, 32
 PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4, "bf16_split3": 5}
 
 #: names of every C entry point declared in include/dpfft.h
 EXPORTS = ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
            "fft_last_error", "fft_plan_describe", "fft_plan_num_steps", "fft_exec_steps",
-           "fft_plan_dry", "fft_autotune")
+           "fft_plan_dry", "fft_autotune", "fft_conv_exec")
 
 
 class FftError(RuntimeError):
@@ -72,6 +73,8 @@ def _load() -> ctypes.CDLL:
     lib.fft_autotune.argtypes = [ctypes.POINTER(FftDesc), vp, ctypes.c_int, ctypes.c_char_p,
                                  ctypes.c_size_t]
     lib.fft_autotune.restype = ctypes.c_int
+    lib.fft_conv_exec.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
+    lib.fft_conv_exec.restype = ctypes.c_int
     return lib
 
 
@@ -104,6 +107,14 @@ def fft_exec(handle: int, in_ptr: int, out_ptr: int, direction: int, workspace: 
              stream: int = 0) -> int:
     return _lib.fft_exec(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
                          direction, ctypes.c_void_p(workspace), ctypes.c_void_p(stream))
+
+
+def fft_conv_exec(handle: int, in_ptr: int, filter_ptr: int, filter_dist: int, out_ptr: int,
+                  workspace: int = 0, stream: int = 0) -> int:
+    return _lib.fft_conv_exec(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr),
+                              ctypes.c_void_p(filter_ptr), int(filter_dist),
+                              ctypes.c_void_p(out_ptr), ctypes.c_void_p(workspace),
+                              ctypes.c_void_p(stream))
 
 
 def fft_plan_num_steps(handle: Optional[int]) -> int:
@@ -186,16 +197,18 @@ class Plan:
     ``Plan(ragged_sizes=[...])`` -- ragged batch packed back to back;
     ``real=True`` -- real samples: the forward transform takes float32
     samples and returns the n//2 + 1 bins (rank 2: ny x (nx//2 + 1)) as
-    complex64, the inverse takes those bins and returns float32 samples.
+    complex64, the inverse takes those bins and returns float32 samples;
+    ``conv=True`` -- the plan also runs :meth:`conv` (fused circular
+    convolution with filter spectra).
     """
 
     def __init__(self, n: Optional[int] = None, batch: int = 1, *, rank: int = 1, shape=None,
                  dist: int = 0, ragged_sizes=None, ragged_offsets=None, precision: str = "fp32",
                  inplace: bool = False, graph: bool = False, per_size: bool = False,
-                 autotune: bool = True, real: bool = False, stream=None):
+                 autotune: bool = True, real: bool = False, conv: bool = False, stream=None):
         flags = (FFT_F_INPLACE if inplace else 0) | (FFT_F_GRAPH if graph else 0) | \
                 (FFT_F_PER_SIZE if per_size else 0) | (0 if autotune else FFT_F_NO_AUTOTUNE) | \
-                (FFT_F_REAL if real else 0)
+                (FFT_F_REAL if real else 0) | (FFT_F_CONV if conv else 0)
         self.real = bool(real)
         self.desc, self._keep = make_desc(n, batch, rank=rank, shape=shape, dist=dist,
                                           ragged_sizes=ragged_sizes, ragged_offsets=ragged_offsets,
@@ -260,6 +273,31 @@ class Plan:
                       ws.data_ptr() if ws is not None else 0, _stream_handle(stream))
         if st != FFT_OK:
             raise FftError(st, "fft_exec", fft_last_error())
+        return out
+
+    def conv(self, x: torch.Tensor, spec: torch.Tensor, out: Optional[torch.Tensor] = None,
+             stream=None) -> torch.Tensor:
+        """Circular convolution of every signal of x with the filter whose
+        spectrum (the forward transform of the filter, natural order) is
+        ``spec``: one spectrum (n elements) shared by every signal, or one per
+        signal laid out like x."""
+        _check_tensor(x, self.numel, "x")
+        n = int(self.desc.n[0])
+        if spec.numel() == n:
+            _check_tensor(spec, n, "spec")
+            fdist = 0
+        else:
+            _check_tensor(spec, self.numel, "spec")
+            fdist = int(self.desc.dist) if self.desc.dist else n
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            _check_tensor(out, self.numel, "out")
+        ws = self.workspace(x.device)
+        st = fft_conv_exec(self.handle, x.data_ptr(), spec.data_ptr(), fdist, out.data_ptr(),
+                           ws.data_ptr() if ws is not None else 0, _stream_handle(stream))
+        if st != FFT_OK:
+            raise FftError(st, "fft_conv_exec", fft_last_error())
         return out
 
     def _exec_real(self, x, out, inverse, stream):

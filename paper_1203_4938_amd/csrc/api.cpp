@@ -405,6 +405,16 @@ std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, in
   return s;
 }
 
+}  // namespace
+
+std::unique_ptr<LineStep> dpfft::make_line_step(dpfft_plan_s *P, const char *name, int L, int map,
+                                                int omap, bool tw4, int cmax, int step,
+                                                int64_t lines_total, const Override &ov) {
+  return make_line(P, name, L, map, omap, tw4, cmax, step, lines_total, ov);
+}
+
+namespace {
+
 // Two-pass plans over B transforms, `per` elements apart in the caller's
 // buffers: run the pair of launches chunk by chunk, `k` transforms at a time,
 // so the intermediate of a chunk (k transforms, reused by every chunk) can be
@@ -859,8 +869,15 @@ fft_status_t validate_desc(const fft_desc_t *d) {
   if (d->dist < 0) return fail(FFT_E_INVALID, "dist must be >= 0");
   if (d->precision < FFT_FP32 || d->precision > FFT_BF16_SPLIT3)
     return fail(FFT_E_INVALID, "unknown precision");
-  if (d->flags & ~(FFT_F_INPLACE | FFT_F_NO_AUTOTUNE | FFT_F_GRAPH | FFT_F_PER_SIZE | FFT_F_REAL))
+  if (d->flags &
+      ~(FFT_F_INPLACE | FFT_F_NO_AUTOTUNE | FFT_F_GRAPH | FFT_F_PER_SIZE | FFT_F_REAL | FFT_F_CONV))
     return fail(FFT_E_INVALID, "unknown flag bits");
+  if (d->flags & FFT_F_CONV) {
+    if (d->rank != 1 || d->ragged_sizes || (d->flags & FFT_F_REAL) || d->precision != FFT_FP32)
+      return fail(FFT_E_UNSUPPORTED, "convolution plans are rank 1, complex, FFT_FP32, not ragged");
+    if (!is_pow2(d->n[0]) || d->n[0] > kMaxN)
+      return fail(FFT_E_UNSUPPORTED, "convolution lengths are powers of two <= 2^24");
+  }
   if (d->flags & FFT_F_REAL) {
     if (d->ragged_sizes) return fail(FFT_E_UNSUPPORTED, "real-input plans are not ragged");
     if (d->precision != FFT_FP32) return fail(FFT_E_UNSUPPORTED, "real-input plans are FFT_FP32");
@@ -971,6 +988,10 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
     st = plan_pow2_2d(P.get());
   }
   if (st != FFT_OK) return st;
+  if (desc->flags & FFT_F_CONV) {
+    st = plan_conv(P.get());
+    if (st != FFT_OK) return st;
+  }
 
   // every index a kernel forms must stay inside its buffer
   if (P->rsizes.empty())
@@ -987,8 +1008,8 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
   }
   if (P->batch > 0) {
     // both step lists; a real plan's buffers differ in size by direction
-    for (int dir = 0; dir < 2; ++dir) {
-      const auto &list = dir == 0 ? P->steps : P->isteps;
+    for (int dir = 0; dir < 3; ++dir) {
+      const auto &list = dir == 0 ? P->steps : dir == 1 ? P->isteps : P->csteps;
       for (auto &s : list) {
         int64_t mi, mo;
         int si, di;
@@ -996,7 +1017,7 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
         auto cap = [&](int id) -> int64_t {
           if (id == BUF_WS) return (int64_t)(P->ws_bytes / sizeof(float2));
           if (!P->real) return P->io_elems;
-          const bool real_side = (id == BUF_IN) == (dir == 0);
+          const bool real_side = (id == BUF_IN) == (dir != 1);
           return real_side ? P->real_elems : P->cplx_elems;
         };
         if (mi >= cap(si) || mo >= cap(di))
@@ -1026,6 +1047,10 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
   if (!P->isteps.empty()) {
     o << "\n  inverse:";
     for (auto &s : P->isteps) o << "\n  " << s->describe();
+  }
+  if (!P->csteps.empty()) {
+    o << "\n  convolution:";
+    for (auto &s : P->csteps) o << "\n  " << s->describe();
   }
   P->text = o.str();
   out = std::move(P);
@@ -1077,7 +1102,7 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
   if (st != FFT_OK) return st;
 
   // per-function launch attributes (dynamic LDS opt-in)
-  for (const auto *list : {&P->steps, &P->isteps}) {
+  for (const auto *list : {&P->steps, &P->isteps, &P->csteps}) {
     for (auto &s : *list) {
       const hipError_t e = s->prepare();
       if (e != hipSuccess)
@@ -1102,6 +1127,7 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
   }
   for (auto &s : P->steps) s->bind(P->tables.dev);
   for (auto &s : P->isteps) s->bind(P->tables.dev);
+  for (auto &s : P->csteps) s->bind(P->tables.dev);
   if (getenv("DPFFT_LOG")) fprintf(stderr, "[dpfft] plan %s\n", P->text.c_str());
   *out = P.release();
   return FFT_OK;
@@ -1142,6 +1168,30 @@ fft_status_t fft_exec_steps(fft_plan_t plan, const void *in, void *out, int dire
 }
 
 int fft_plan_num_steps(fft_plan_t plan) { return plan ? (int)plan->steps.size() : 0; }
+
+fft_status_t fft_conv_exec(fft_plan_t plan, const void *in, const void *filter,
+                           int64_t filter_dist, void *out, void *workspace, void *hip_stream) {
+  if (!plan) return fail(FFT_E_INVALID, "plan is NULL");
+  if (!(plan->flags & FFT_F_CONV)) return fail(FFT_E_INVALID, "plan was made without FFT_F_CONV");
+  if (filter_dist < 0 || (filter_dist > 0 && filter_dist < plan->n))
+    return fail(FFT_E_INVALID, "filter_dist must be 0 or >= N");
+  if (plan->batch == 0) return FFT_OK;
+  if (!in || !out || !filter) return fail(FFT_E_INVALID, "in/out/filter is NULL");
+  if (((uintptr_t)in | (uintptr_t)out | (uintptr_t)filter) & 7u)
+    return fail(FFT_E_INVALID, "in/out/filter not 8-byte aligned");
+  if (in == out && !(plan->flags & FFT_F_INPLACE))
+    return fail(FFT_E_INVALID, "in == out needs FFT_F_INPLACE");
+  if (plan->ws_bytes && !workspace) return fail(FFT_E_INVALID, "plan needs a workspace");
+  ExecCtx ctx{in, out, workspace, (hipStream_t)hip_stream, false};
+  ctx.filt = (const float2 *)filter;
+  ctx.filt_dist = filter_dist;
+  for (size_t i = 0; i < plan->csteps.size(); ++i) {
+    ctx.inverse = plan->cinv[i];
+    hipError_t e = plan->csteps[i]->launch(ctx);
+    if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  }
+  return FFT_OK;
+}
 
 
 fft_status_t fft_destroy(fft_plan_t plan) {

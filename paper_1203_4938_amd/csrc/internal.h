@@ -2,9 +2,12 @@
 #pragma once
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 
 #include "../../include/dpfft.h"
+
+struct dpfft_plan_s;
 
 namespace dpfft {
 
@@ -61,9 +64,20 @@ const Override *tuner_override();
 bool tune_cache_lookup(const std::string &key, std::string *value);
 void tune_cache_store(const std::string &key, const std::string &value);
 
+struct LineStep;
+// A power-of-two line launch for (L, map, omap, tw4): the kernel choice (at
+// most `cmax` lines per tile unless an instance is the measured default of its
+// shape; `step` indexes the override), its Stockham and two-level pass tables
+// added to the plan; layout, grid and buffers are left to the caller.
+std::unique_ptr<LineStep> make_line_step(dpfft_plan_s *P, const char *name, int L, int map,
+                                         int omap, bool tw4, int cmax, int step,
+                                         int64_t lines_total, const Override &ov);
+
+// The launches of fft_conv_exec for a power-of-two FFT_F_CONV plan.
+fft_status_t plan_conv(dpfft_plan_s *P);
+
 }  // namespace dpfft
 
-struct dpfft_plan_s;
 // key of a plan in the tuning cache ("" = not tunable)
 std::string tune_key(const fft_desc_t *d);
 fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *offsets);

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/dpfft.h"
+#include "conv.h"
 #include "kernels.h"
 #include "mixed.h"
 #include "mfma.h"
@@ -25,6 +26,8 @@ struct ExecCtx {
   void *ws;
   hipStream_t stream;
   bool inverse;
+  const float2 *filt = nullptr;  // convolution launches: filter spectra
+  int64_t filt_dist = 0;         // elements between consecutive spectra (0 = shared)
 };
 
 inline const float2 *buf_c(const ExecCtx &c, int id, int64_t off) {
@@ -143,6 +146,23 @@ struct RealStep : Step {
   bool valid() const override;
 };
 
+// Fused convolution launch: a single-pass line (forward, product with the
+// filter spectrum, inverse) or the row launch of the four-step form.
+struct ConvStep : Step {
+  ConvKernel k;
+  int L = 0;
+  dim3 grid;
+  int src = BUF_IN, dst = BUF_OUT;
+  LineArgs a{};
+  size_t tw_off = 0, tw2_off = 0, tw4_lo_off = 0, tw4_hi_off = 0;
+  std::string name;
+  void bind(const float2 *tables) override;
+  hipError_t launch(const ExecCtx &ctx) const override;
+  std::string describe() const override;
+  void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
+  bool valid() const override;
+};
+
 }  // namespace dpfft
 
 struct dpfft_plan_s {
@@ -159,6 +179,9 @@ struct dpfft_plan_s {
   bool real = false;          // FFT_F_REAL: real samples <-> N/2 + 1 bins
   int64_t real_elems = 0;     // real plans: float pairs of the real-side buffer
   int64_t cplx_elems = 0;     // real plans: complex elements of the spectrum buffer
+  // FFT_F_CONV: the launches of fft_conv_exec, each with its direction
+  std::vector<std::unique_ptr<dpfft::Step>> csteps;
+  std::vector<bool> cinv;
   dpfft::TableSet tables;
   size_t ws_bytes = 0;
   int64_t io_elems = 0;       // complex elements of `in` / `out` the plan touches

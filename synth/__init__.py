@@ -205,7 +205,7 @@ def smooth_noise_image(seed: int, index: int, h: int = 2048, w: int = 2048,
     noise_c = base + np.uint64(1 << 32) + np.arange(h * w, dtype=np.uint64)
     u = (splitmix64_np(seed, noise_c) >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
     v = 40.0 + 160.0 * s + (-24.0 + 48.0 * u.reshape(h, w))
-    return np.clip(np.floor(v + 0.5), 0, 255).astype(np.uint8)
+    return np.ascontiguousarray(np.clip(np.floor(v + 0.5), 0, 255).astype(np.uint8))
 
 
 def images_complex(seed: int, count: int, h: int = 2048, w: int = 2048,

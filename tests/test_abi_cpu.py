@@ -90,6 +90,7 @@ def test_null_arguments():
     assert dp.fft_workspace_bytes(None) == 0
     assert dp.fft_plan_num_steps(None) == 0
     assert dp.fft_plan_describe(None) == ""
+    assert dp.fft_conv_exec(0, 0, 0, 0, 0) == dp.FFT_E_INVALID
 
 
 @pytest.mark.skipif(not _no_gpu(), reason="checks the no-device path")

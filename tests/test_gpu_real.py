@@ -137,7 +137,8 @@ def test_real_2d_c3_every_image():
     ny = nx = 2048
     b = 16
     w = nx // 2 + 1
-    imgs = np.stack([synth.smooth_noise_image(seed, i) for i in range(b)]).astype(np.float32)
+    imgs = np.ascontiguousarray(
+        np.stack([synth.smooth_noise_image(seed, i) for i in range(b)]).astype(np.float32))
     p = dp.Plan(shape=(ny, nx), batch=b, rank=2, real=True)
     say("[real c3]", p.describe().replace("\n", " | "))
     xd = torch.from_numpy(imgs).cuda()

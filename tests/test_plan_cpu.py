@@ -201,3 +201,40 @@ def test_real_plans_rejected(kw, status):
     d, keep = dp.make_desc(**kw)
     st, msg = dp.fft_plan_dry(d)
     assert dp.fft_status_str(st) == status, msg
+
+
+@pytest.mark.parametrize("n,launches", [(1, 1), (64, 1), (4096, 1), (16384, 1), (1 << 15, 3),
+                                        (1 << 18, 3), (1 << 22, 3), (1 << 24, 3)])
+def test_conv_plans(n, launches):
+    """FFT_F_CONV: one fused launch up to 16384 points, else the forward column
+    pass, the fused row launch and the inverse column pass (workspace of one
+    complex64 per point of the batch)."""
+    dp = _dp()
+    t = _dry(n=n, batch=3, flags=dp.FFT_F_CONV)
+    fwd, conv = t.split("\n  convolution:")
+    steps = [ln for ln in conv.splitlines() if ln.strip()]
+    assert len(steps) == launches, t
+    if launches == 1:
+        assert "conv_single_pass: L=%d " % n in conv
+    else:
+        lg = n.bit_length() - 1
+        n1, n2 = 1 << (lg // 2), 1 << (lg - lg // 2)
+        assert "conv_fourstep_columns: L=%d " % n1 in steps[0]
+        assert "conv_fourstep_rows: L=%d " % n2 in steps[1]
+        assert "conv_columns_inverse: L=%d " % n1 in steps[2]
+        assert "workspace=%dB" % (3 * n * 8) in t
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=96, batch=2, flags=32), "FFT_E_UNSUPPORTED"),                # not a power of two
+    (dict(n=64, batch=2, flags=32, precision="fp16"), "FFT_E_UNSUPPORTED"),
+    (dict(n=64, batch=2, flags=32 | 16), "FFT_E_UNSUPPORTED"),           # real
+    (dict(rank=2, shape=(64, 64), batch=1, flags=32), "FFT_E_UNSUPPORTED"),
+    (dict(ragged_sizes=[64, 128], flags=32), "FFT_E_UNSUPPORTED"),
+    (dict(n=1 << 25, batch=1, flags=32), "FFT_E_UNSUPPORTED"),
+])
+def test_conv_plans_rejected(kw, status):
+    dp = _dp()
+    d, keep = dp.make_desc(**kw)
+    st, msg = dp.fft_plan_dry(d)
+    assert dp.fft_status_str(st) == status, msg
