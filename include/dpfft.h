@@ -209,6 +209,24 @@ fft_status_t fft_autotune(const fft_desc_t *desc, void *hip_stream, int reps, ch
 fft_status_t fft_conv_exec(fft_plan_t plan, const void *in, const void *filter,
                            int64_t filter_dist, void *out, void *workspace, void *hip_stream);
 
+/*
+ * fft_exec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same launches, with the plan's workspace taken from a device array the
+ * library holds (64 MiB per GPU, kept until the process ends) instead of a
+ * caller buffer.  Graph plans (FFT_F_GRAPH) launch their kernels directly
+ * rather than instantiating a graph.  Calls no allocating routine.
+ *   in, out, direction, hip_stream   as for fft_exec
+ * Errors: as fft_exec, plus FFT_E_UNSUPPORTED when fft_workspace_bytes(plan)
+ * exceeds 64 MiB (checked before any launch) and FFT_E_DEVICE when the
+ * array's address cannot be looked up on the current device.  The array is
+ * shared by every call on a GPU and keeps the last call's contents (no kernel
+ * reads workspace it has not written in the same call); calls whose
+ * executions overlap on one GPU race on it.
+ */
+fft_status_t fft_exec_noalloc(fft_plan_t plan, const void *in, void *out, int direction,
+                              void *hip_stream);
+
 /* Release a plan and its device tables.  fft_destroy(NULL) returns FFT_OK.
  * The caller must ensure no execution of the plan is still pending. */
 fft_status_t fft_destroy(fft_plan_t plan);

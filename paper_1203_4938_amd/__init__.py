@@ -28,7 +28,7 @@ PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4,
 #: names of every C entry point declared in include/dpfft.h
 EXPORTS = ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
            "fft_last_error", "fft_plan_describe", "fft_plan_num_steps", "fft_exec_steps",
-           "fft_plan_dry", "fft_autotune", "fft_conv_exec")
+           "fft_plan_dry", "fft_autotune", "fft_conv_exec", "fft_exec_noalloc")
 
 
 class FftError(RuntimeError):
@@ -75,6 +75,8 @@ def _load() -> ctypes.CDLL:
     lib.fft_autotune.restype = ctypes.c_int
     lib.fft_conv_exec.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
     lib.fft_conv_exec.restype = ctypes.c_int
+    lib.fft_exec_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.fft_exec_noalloc.restype = ctypes.c_int
     return lib
 
 
@@ -115,6 +117,12 @@ def fft_conv_exec(handle: int, in_ptr: int, filter_ptr: int, filter_dist: int, o
                               ctypes.c_void_p(filter_ptr), int(filter_dist),
                               ctypes.c_void_p(out_ptr), ctypes.c_void_p(workspace),
                               ctypes.c_void_p(stream))
+
+
+def fft_exec_noalloc(handle: int, in_ptr: int, out_ptr: int, direction: int,
+                     stream: int = 0) -> int:
+    return _lib.fft_exec_noalloc(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr),
+                                 ctypes.c_void_p(out_ptr), direction, ctypes.c_void_p(stream))
 
 
 def fft_plan_num_steps(handle: Optional[int]) -> int:

@@ -1134,7 +1134,8 @@ fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream)
 }
 
 static fft_status_t exec_range(fft_plan_t plan, const void *in, void *out, int direction,
-                               void *workspace, void *hip_stream, int first, int count) {
+                               void *workspace, void *hip_stream, int first, int count,
+                               bool graphs = true) {
   if (!plan) return fail(FFT_E_INVALID, "plan is NULL");
   if (direction != FFT_FORWARD && direction != FFT_INVERSE)
     return fail(FFT_E_INVALID, "direction must be FFT_FORWARD or FFT_INVERSE");
@@ -1148,6 +1149,7 @@ static fft_status_t exec_range(fft_plan_t plan, const void *in, void *out, int d
     return fail(FFT_E_INVALID, "in == out needs FFT_F_INPLACE");
   if (plan->ws_bytes && !workspace) return fail(FFT_E_INVALID, "plan needs a workspace");
   ExecCtx ctx{in, out, workspace, (hipStream_t)hip_stream, direction == FFT_INVERSE};
+  ctx.graphs = graphs;
   const auto &list = ctx.inverse && !plan->isteps.empty() ? plan->isteps : plan->steps;
   for (int i = first; i < first + count; ++i) {
     hipError_t e = list[i]->launch(ctx);
@@ -1155,6 +1157,17 @@ static fft_status_t exec_range(fft_plan_t plan, const void *in, void *out, int d
   }
   return FFT_OK;
 }
+
+}  // extern "C"
+
+fft_status_t dpfft::exec_plan(fft_plan_t plan, const void *in, void *out, int direction,
+                              void *workspace, void *hip_stream, bool graphs) {
+  if (!plan) return fail(FFT_E_INVALID, "plan is NULL");
+  return exec_range(plan, in, out, direction, workspace, hip_stream, 0, (int)plan->steps.size(),
+                    graphs);
+}
+
+extern "C" {
 
 fft_status_t fft_exec(fft_plan_t plan, const void *in, void *out, int direction, void *workspace,
                       void *hip_stream) {

@@ -73,6 +73,11 @@ std::unique_ptr<LineStep> make_line_step(dpfft_plan_s *P, const char *name, int 
                                          int omap, bool tw4, int cmax, int step,
                                          int64_t lines_total, const Override &ov);
 
+// fft_exec with `workspace` as given; graphs = false launches the kernels of
+// graph plans directly instead of instantiating or replaying a HIP graph.
+fft_status_t exec_plan(dpfft_plan_s *plan, const void *in, void *out, int direction,
+                       void *workspace, void *hip_stream, bool graphs);
+
 // The launches of fft_conv_exec for a power-of-two FFT_F_CONV plan.
 fft_status_t plan_conv(dpfft_plan_s *P);
 

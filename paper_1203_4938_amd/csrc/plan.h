@@ -28,6 +28,7 @@ struct ExecCtx {
   bool inverse;
   const float2 *filt = nullptr;  // convolution launches: filter spectra
   int64_t filt_dist = 0;         // elements between consecutive spectra (0 = shared)
+  bool graphs = true;            // graph plans may instantiate and replay HIP graphs
 };
 
 inline const float2 *buf_c(const ExecCtx &c, int id, int64_t off) {

@@ -195,7 +195,7 @@ struct RaggedStep : Step {
   hipError_t launch(const ExecCtx &ctx) const override {
     if (nitems == 0) return hipSuccess;
     if (per_size) return launch_direct(ctx);
-    return graph ? launch_graph(ctx) : launch_persistent(ctx);
+    return graph && ctx.graphs ? launch_graph(ctx) : launch_persistent(ctx);
   }
 
   std::string describe() const override { return summary; }
