@@ -186,23 +186,33 @@ def build_c4(dp, torch, synth, dev):
 
 
 def build_c5(dp, torch, synth, dev):
-    import numpy as np
     sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
     flat, offs = synth.uniform_ragged(synth.BASE_SEED + 5, sizes)
     x = torch.from_numpy(flat).to(dev)
     fl = float(sum(flops(int(n), 1) for n in sizes))
+    # per-length choices from the autotuner (plan time, outside any timing)
+    d, keep = dp.make_desc(ragged_sizes=sizes.tolist())
+    t0 = time.perf_counter()
+    st, rep = dp.fft_autotune(d, reps=3)
+    tune_s = time.perf_counter() - t0
+    if st != dp.FFT_OK:
+        raise RuntimeError(f"ragged autotune failed: {rep}")
+    print(f"# c5 autotune ({tune_s:.1f} s): {rep.strip()}", file=sys.stderr, flush=True)
     items = []
     for name, kw, cmp in (("ragged10000_persistent_graph", dict(graph=True), False),
                           ("ragged10000_persistent", dict(), True),
+                          ("ragged10000_heuristic_graph", dict(graph=True, autotune=False), True),
                           ("ragged10000_one_launch_per_length_runtime_radix", dict(per_size=True),
                            True)):
         p = dp.Plan(ragged_sizes=sizes.tolist(), **kw)
         items.append(Item(dp, torch, name, p, x.clone(), torch.empty_like(x), fl,
                           16.0 * float(sizes.sum()), compare=cmp))
     return items, {"workload": "c5: ragged batch of 10000 7-smooth sizes in [64, 65536], "
-                               "log-uniform; the step is the two persistent launches in a HIP "
-                               "graph; the same launches without the graph and one launch per "
-                               "distinct length are timed after it for comparison"}
+                               "log-uniform; the step is the persistent launches in a HIP graph "
+                               "with autotuned per-length choices; the same launches without the "
+                               "graph, the untuned heuristic plan and one launch per distinct "
+                               "length are timed after it for comparison",
+                   "autotune_s": round(tune_s, 1), "autotune": rep.strip()}
 
 
 def build_c5_fair(dp, torch, synth, dev):

@@ -173,8 +173,12 @@ fft_status_t fft_plan_dry(const fft_desc_t *desc, char *buf, size_t len);
  * also written there as JSON and read back by later processes (a missing or
  * unreadable file is treated as empty).  A per-candidate report (one line per
  * candidate, then the choice) goes to `report` (may be NULL).  Synchronizes
- * the stream.  Ragged plans and MFMA precision forms have nothing to tune
- * (FFT_OK, report says so). */
+ * the stream.  MFMA precision forms have nothing to tune (FFT_OK, report says
+ * so).  Ragged descriptors are tuned per distinct length: radix order, single
+ * pass in a 256- or 1024-thread workgroup or four-step, and the four-step
+ * split, each timed on a batch of signals of that length alone (at least
+ * 2^21 points); the fastest is recorded for (architecture, length) and used
+ * by every later ragged plan containing that length. */
 fft_status_t fft_autotune(const fft_desc_t *desc, void *hip_stream, int reps, char *report,
                           size_t len);
 

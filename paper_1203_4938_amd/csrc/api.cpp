@@ -337,6 +337,26 @@ Override read_override() {
   return Override{};
 }
 
+}  // namespace
+
+// Choices for one length of a ragged batch: the autotuner's candidate while
+// it times candidates, else DPFFT_FORCE_PLAN, else the tuning-cache entry of
+// that length (unless FFT_F_NO_AUTOTUNE), else none (the heuristic).
+Override dpfft::read_ragged_override(int64_t L) {
+  if (const Override *t = tuner_override()) return *t;
+  if (const char *env = getenv("DPFFT_FORCE_PLAN")) return parse_override(env);
+  if (g_building && !g_skip_cache && !(g_building->flags & FFT_F_NO_AUTOTUNE)) {
+    std::string val;
+    if (tune_cache_lookup(ragged_tune_key(L), &val)) {
+      g_cache_used = true;
+      return parse_override(val);
+    }
+  }
+  return Override{};
+}
+
+namespace {
+
 // Workgroups of a persistent instance that stay resident on the device.
 int resident_workgroups(const KernelInfo &k) { return resident_for(k.lds_bytes, k.threads); }
 

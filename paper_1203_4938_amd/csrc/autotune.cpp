@@ -41,6 +41,10 @@ Override parse_override(const std::string &text) {
       o.chunk = val;
     } else if (sscanf(tok.c_str(), "s=%d", &val) == 1) {
       o.split = val;
+    } else if (sscanf(tok.c_str(), "f=%d", &val) == 1) {
+      o.form = val;
+    } else if (sscanf(tok.c_str(), "b=%d", &val) == 1) {
+      o.big = val;
     } else if (sscanf(tok.c_str(), "%c%d=%d", &kind, &idx, &val) == 3 && idx >= 0 && idx < 8) {
       if (kind == 'c') o.c[idx] = val;
       if (kind == 'p') o.p[idx] = val;
@@ -135,6 +139,13 @@ void tune_cache_store(const std::string &key, const std::string &value) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   if (!g_cache_loaded) load_cache_locked();
   g_cache[key] = value;
+  save_cache_locked();
+}
+
+void tune_cache_store_all(const std::vector<std::pair<std::string, std::string>> &kv) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (!g_cache_loaded) load_cache_locked();
+  for (const auto &e : kv) g_cache[e.first] = e.second;
   save_cache_locked();
 }
 
@@ -247,8 +258,14 @@ extern "C" fft_status_t fft_autotune(const fft_desc_t *desc, void *hip_stream, i
     }
     return st;
   };
+  if (desc->ragged_sizes && desc->precision == FFT_FP32 && desc->batch > 0) {
+    std::string r;
+    const fft_status_t st = autotune_ragged(desc, hip_stream, reps, &r);
+    rep << r;
+    return finish(st);
+  }
   if (key.empty()) {
-    rep << "nothing to tune (ragged, precision form, real-input or empty batch)";
+    rep << "nothing to tune (precision form, real-input or empty batch)";
     return finish(FFT_OK);
   }
   const std::vector<std::string> cands = candidates(desc);

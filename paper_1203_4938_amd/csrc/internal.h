@@ -4,6 +4,8 @@
 
 #include <memory>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/dpfft.h"
 
@@ -40,7 +42,13 @@ int resident_for(int lds_bytes, int threads);
 //   t<i>=<T>   threads per workgroup (instances differing in elements per thread)
 //   o=0|1      radix order of runtime-radix lengths: powers of two first / odd first
 //   k=<n>      two-pass plans: transforms per chunk (0 = the whole batch at once)
-//   s=<n>      power-of-two four-step: log2 of the column length N1
+//   s=<n>      power-of-two four-step: log2 of the column length N1; ragged
+//              lengths: the column length n1 itself
+//   f=<n>      ragged lengths: 0 single pass in a 256-thread workgroup, 1
+//              four-step, 2 single pass in a 1024-thread workgroup (a form
+//              that does not fit a length leaves that length to the heuristic)
+//   b=0|1      ragged lengths: the heuristic may not / may choose the
+//              1024-thread single pass
 // Sources, first match wins: the autotuner while it times candidates, the
 // DPFFT_FORCE_PLAN environment variable, the tuning cache entry of the plan.
 struct Override {
@@ -50,10 +58,28 @@ struct Override {
   int order = -1;
   int chunk = -1;
   int split = -1;
+  int form = -1;
+  int big = -1;
   std::string text;
   bool empty() const { return text.empty(); }
 };
 Override parse_override(const std::string &text);
+
+// The override in force for length L of the ragged batch being planned.
+Override read_ragged_override(int64_t L);
+
+// Tuning-cache key of one length of ragged batches.
+std::string ragged_tune_key(int64_t L);
+
+// Override strings the autotuner times for one ragged length.
+std::vector<std::string> ragged_candidates(int64_t L);
+
+// Autotune every distinct length of a ragged descriptor (see fft_autotune).
+fft_status_t autotune_ragged(const fft_desc_t *desc, void *hip_stream, int reps,
+                             std::string *report);
+
+// Store several tuning-cache entries (one write of the cache file).
+void tune_cache_store_all(const std::vector<std::pair<std::string, std::string>> &kv);
 
 // Thread-local override installed by the autotuner around candidate plans.
 void set_tuner_override(const Override *o);

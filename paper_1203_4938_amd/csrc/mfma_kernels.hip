@@ -99,41 +99,62 @@ __device__ __forceinline__ void split8(const float (&x)[8],
   }
 }
 
-// One DFT-16 stage: D = W X for the 16 vectors held in B layout.
-//
 // FP16 pieces have a 5-bit exponent: above 65504 they overflow, below 2^-14
-// they lose bits.  A stage's input grows with the transform (up to 4096 times
-// the signal amplitude before the last stage of a 2^16-point four-step), so
-// for the FP16 forms each vector (one B column: its 32 real values sit in
-// lanes col, col + 16, col + 32 and col + 48) is first scaled by an exact
-// power of two 2^-e that brings its largest magnitude into [1/2, 1), and the
-// FP32 products are scaled back by 2^e.  Both scalings are exact, so the
-// result is the same as with unbounded exponents and the error stays
-// relative to the vector's own magnitude, whatever the input range.  BF16
-// pieces share FP32's exponent range and need no scaling.
+// they lose bits, and a line's values can have any magnitude (the inputs of a
+// four-step's second pass are up to 256 times the signal's).  The FP16 forms
+// therefore scale each 256-point line by an exact power of two 2^-e that
+// brings its largest magnitude into [1/2, 1) before stage 1, so stage 1's
+// inputs are at most 1 and stage 2's (sums of 16 products with |w| <= 1)
+// at most 16, and scale the FP32 results back by 2^e when they leave the
+// registers.  Both scalings are exact, the pieces of every value at least
+// 2^-35 times the line's largest stay exact to the form's precision, and the
+// error stays relative to the line's own magnitude whatever the input range.
+// BF16 pieces share FP32's exponent range and need no scaling.
+//
+// e is the exponent of the largest magnitude among the wave's 512 values (its
+// line: the wave holds one line's B operand), the same in every lane: the
+// largest of a lane's eight, then within each row of 16 lanes through DPP
+// moves, then across the four rows through scalar reads.  Magnitudes are
+// compared as their bit patterns (non-negative floats order like unsigned
+// integers).
+__device__ __forceinline__ uint32_t dpp_max(uint32_t m, int ctrl_id) {
+  int v;
+  switch (ctrl_id) {
+    case 0: v = __builtin_amdgcn_mov_dpp((int)m, 0xB1, 0xF, 0xF, false); break;   // quad_perm 1,0,3,2
+    case 1: v = __builtin_amdgcn_mov_dpp((int)m, 0x4E, 0xF, 0xF, false); break;   // quad_perm 2,3,0,1
+    case 2: v = __builtin_amdgcn_mov_dpp((int)m, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+    default: v = __builtin_amdgcn_mov_dpp((int)m, 0x140, 0xF, 0xF, false); break; // row_mirror
+  }
+  return m > (uint32_t)v ? m : (uint32_t)v;
+}
+__device__ __forceinline__ int line_exponent(const float (&x)[8]) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const uint32_t b = __float_as_uint(x[t]) & 0x7fffffffu;
+    m = m > b ? m : b;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m = dpp_max(m, k);
+  uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)m, 0);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)m, 16 * row);
+    r = r > q ? r : q;
+  }
+  // frexp's exponent: m = f 2^e with f in [1/2, 1) (r = 0: no scaling)
+  return r ? (int)(r >> 23) - 126 : 0;
+}
+
+// One DFT-16 stage: D = W X for the 16 vectors held in B layout.
 template <int PREC>
 __device__ __forceinline__ void dft16_stage(const typename Piece<base_of<PREC>()>::vec (&are)[3],
                                             const typename Piece<base_of<PREC>()>::vec (&aim)[3],
                                             const float (&xv)[8], f32x4 &dre, f32x4 &dim) {
   constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
   constexpr float down = 1.0f / (float)(1 << mfma_piece_shift(PREC));
-  constexpr bool SCALED = B == MP_FP16;
   typename Piece<B>::vec xp[3];
-  int ex = 0;
-  if constexpr (SCALED) {
-    float m = __builtin_fabsf(xv[0]);
-#pragma unroll
-    for (int t = 1; t < 8; ++t) m = __builtin_fmaxf(m, __builtin_fabsf(xv[t]));
-    m = __builtin_fmaxf(m, __shfl_xor(m, 16));
-    m = __builtin_fmaxf(m, __shfl_xor(m, 32));
-    ex = __builtin_amdgcn_frexp_expf(m);  // m = f 2^ex, f in [1/2, 1); 0 for m = 0
-    float xs[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) xs[t] = __builtin_amdgcn_ldexpf(xv[t], -ex);
-    split8<PREC>(xs, xp);
-  } else {
-    split8<PREC>(xv, xp);
-  }
+  split8<PREC>(xv, xp);
   const f32x4 z = {0.f, 0.f, 0.f, 0.f};
   f32x4 r0 = mfma<B>(are[0], xp[0], z);
   f32x4 i0 = mfma<B>(aim[0], xp[0], z);
@@ -155,13 +176,6 @@ __device__ __forceinline__ void dft16_stage(const typename Piece<base_of<PREC>()
     r0 = r0 + r1 * down;
     i0 = i0 + i1 * down;
   }
-  if constexpr (SCALED) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      r0[t] = __builtin_amdgcn_ldexpf(r0[t], ex);
-      i0[t] = __builtin_amdgcn_ldexpf(i0[t], ex);
-    }
-  }
   dre = r0;
   dim = i0;
 }
@@ -182,6 +196,7 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
                                                           cf *__restrict__ out, MfmaArgs a) {
   constexpr int B = base_of<PREC>(), NPC = mfma_pieces(PREC);
   constexpr int C = kMfmaLines;
+  constexpr bool SCALED = B == MP_FP16;  // per-line power-of-two scaling
   __shared__ cf tile[C * kPitch];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -265,6 +280,12 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
       const cf v = tile[tidx(c, col + 16 * (kb + t))];
       xv[t] = part ? v.y : v.x;
     }
+    int ex = 0;  // the line's scale 2^-ex (FP16 forms)
+    if constexpr (SCALED) {
+      ex = line_exponent(xv);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) xv[t] = __builtin_amdgcn_ldexpf(xv[t], -ex);
+    }
     f32x4 dre, dim;
     dft16_stage<PREC>(are, aim, xv, dre, dim);
     // D: column n2 = col, rows k1 = 4 g4 + t -> twiddle, to Y[k1][n2] at
@@ -290,20 +311,29 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
     cf y4[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) y4[t] = make_float2(dre[t], dim[t]);
+    // the line's scale 2^ex goes back in with the four-step twiddle, or with
+    // the inverse's 1/N, or on its own
     if constexpr (TW4) {
       // w_N^{line k}, k = col + 16 (4 g4 + t) = A S^t
       const cf S2 = cmul(S, S);
-      y4[0] = cmul(y4[0], A);
-      y4[1] = cmul(y4[1], cmul(A, S));
-      y4[2] = cmul(y4[2], cmul(A, S2));
-      y4[3] = cmul(y4[3], cmul(A, cmul(S2, S)));
+      cf As = A;
+      if constexpr (SCALED) As = make_float2(__builtin_amdgcn_ldexpf(A.x, ex), __builtin_amdgcn_ldexpf(A.y, ex));
+      y4[0] = cmul(y4[0], As);
+      y4[1] = cmul(y4[1], cmul(As, S));
+      y4[2] = cmul(y4[2], cmul(As, S2));
+      y4[3] = cmul(y4[3], cmul(As, cmul(S2, S)));
       A = cmul(A, Dw);  // the next line's bases
       S = cmul(S, Gw);
+    } else if constexpr (SCALED && !(SW & 2)) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        y4[t] = make_float2(__builtin_amdgcn_ldexpf(y4[t].x, ex), __builtin_amdgcn_ldexpf(y4[t].y, ex));
     }
+    const float osc = (SCALED && !TW4) ? __builtin_amdgcn_ldexpf(a.scale, ex) : a.scale;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       cf y = y4[t];
-      if (SW & 2) y = cswap(cscale(y, a.scale));
+      if (SW & 2) y = cswap(cscale(y, osc));
       tile[tidx(c, col + 16 * (4 * g4 + t))] = y;
     }
   }

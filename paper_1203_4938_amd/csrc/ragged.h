@@ -33,6 +33,9 @@ struct RaggedItem {
 
 constexpr int kRaggedThreads = 256;      // workgroup size of the ragged kernel
 constexpr int kRaggedLdsBytes = 39936;   // per workgroup: four fit in one CU's 160 KB
+// the instance for single-pass signals longer than a 256-thread workgroup takes
+constexpr int kRaggedBigThreads = 1024;
+constexpr int kRaggedBigLdsBytes = 160 * 1024;
 
 // Kernel arguments besides the buffers (in, out, workspace, item list, signal
 // offsets, table base), which the kernel takes as separate parameters; the
@@ -48,7 +51,7 @@ struct RaggedArgs {
   int32_t pad;
 };
 
-// Kernel instances: forward / inverse.
-const void *ragged_kernel(bool inverse);
+// Kernel instances: forward / inverse, 256 threads or (big) 1024 threads.
+const void *ragged_kernel(bool inverse, bool big = false);
 
 }  // namespace dpfft

@@ -12,6 +12,10 @@
 // launches back to back: the first over the single-pass items and column
 // tiles, the second over the row tiles.  The kernel boundary orders them.
 //
+// Single-pass signals too long for a 256-thread workgroup (up to 16384
+// points: 16 elements per thread, 1024 threads, up to 160 KB of LDS) run in a
+// launch of their own with the 1024-thread instance, before the other two.
+//
 // In direct mode the kernel runs item first_item + blockIdx.x and stops; the
 // per-length baseline launches it once per distinct length.
 #include "mixed_device.h"
@@ -19,7 +23,7 @@
 
 namespace dpfft {
 
-template <bool INV>
+template <bool INV, int NTH>
 __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__restrict__ out,
                                             const RaggedArgs &a, const RaggedItem &d, cf *lds) {
   const int tid = threadIdx.x;
@@ -39,7 +43,7 @@ __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__res
     t.line = 0;
     t.valid2 = false;
     sh.scale = 1.0f / (float)d.L;
-    mixed_tile<ELEM_FAST, ELEM_FAST, false, INV ? 3 : 0>(sh, t, lds, kRaggedThreads);
+    mixed_tile<ELEM_FAST, ELEM_FAST, false, INV ? 3 : 0>(sh, t, lds, NTH);
   } else if (d.kind == RK_COLUMNS) {
     sh.tw4_lo = a.tables + d.tw4_lo_off;
     sh.tw4_hi = a.tables + d.tw4_hi_off;
@@ -53,7 +57,7 @@ __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__res
     t.in_e = t.out_e = d.n2;
     t.line = n2;
     t.valid2 = false;
-    mixed_tile<LINE_FAST, LINE_FAST, true, INV ? 1 : 0>(sh, t, lds, kRaggedThreads);
+    mixed_tile<LINE_FAST, LINE_FAST, true, INV ? 1 : 0>(sh, t, lds, NTH);
   } else {
     t.c = tid / d.T;
     t.j = tid % d.T;
@@ -69,15 +73,15 @@ __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__res
     t.valid2 = in_tile;
     t.dst2 = out + d.off + d.first + t.c2;
     sh.scale = (float)(1.0 / ((double)d.n1 * (double)d.n2));
-    mixed_tile<ELEM_FAST, LINE_FAST, false, INV ? 2 : 0>(sh, t, lds, kRaggedThreads);
+    mixed_tile<ELEM_FAST, LINE_FAST, false, INV ? 2 : 0>(sh, t, lds, NTH);
   }
 }
 
 // The buffers are separate restrict-qualified parameters so the compiler knows
 // no store of the kernel reaches the item list, and reads the (uniform)
 // descriptors through the scalar cache.
-template <bool INV>
-__global__ void __launch_bounds__(kRaggedThreads, 4)
+template <bool INV, int NTH>
+__global__ void __launch_bounds__(NTH, NTH == kRaggedThreads ? 4 : 1)
     k_ragged(const cf *__restrict__ in, cf *__restrict__ out, cf *__restrict__ ws,
              const RaggedItem *__restrict__ item_list, const int64_t *__restrict__ sigoff,
              const cf *__restrict__ tables, RaggedArgs a) {
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(kRaggedThreads, 4)
   a.tables = tables;
   const RaggedItem *__restrict__ items = item_list + a.first_item;
   if (a.direct) {
-    ragged_item<INV>(in, out, a, items[blockIdx.x], lds);
+    ragged_item<INV, NTH>(in, out, a, items[blockIdx.x], lds);
     return;
   }
   int q = (int)blockIdx.x;
@@ -98,7 +102,7 @@ __global__ void __launch_bounds__(kRaggedThreads, 4)
     // the next descriptor is in flight while this item runs
     RaggedItem dn = d;
     if (qn < a.nitems) dn = items[qn];
-    ragged_item<INV>(in, out, a, d, lds);
+    ragged_item<INV, NTH>(in, out, a, d, lds);
     if (qn >= a.nitems) break;
     __syncthreads();  // the next item reuses the LDS
     d = dn;
@@ -106,8 +110,12 @@ __global__ void __launch_bounds__(kRaggedThreads, 4)
   }
 }
 
-const void *ragged_kernel(bool inverse) {
-  return inverse ? (const void *)&k_ragged<true> : (const void *)&k_ragged<false>;
+const void *ragged_kernel(bool inverse, bool big) {
+  if (big)
+    return inverse ? (const void *)&k_ragged<true, kRaggedBigThreads>
+                   : (const void *)&k_ragged<false, kRaggedBigThreads>;
+  return inverse ? (const void *)&k_ragged<true, kRaggedThreads>
+                 : (const void *)&k_ragged<false, kRaggedThreads>;
 }
 
 }  // namespace dpfft

@@ -1,4 +1,6 @@
 // Plan builder and launcher of ragged batches.
+#include <stdio.h>
+
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -40,12 +42,21 @@ struct RaggedStep : Step {
   RaggedArgs a{};
   size_t items_off = 0, sigoff_off = 0;
   int nitems = 0;
-  int n_phase1 = 0;  // items of the first launch; the rest belong to the second
+  // items [0, n_big): single-pass signals of the 1024-thread instance (first
+  // launch); [n_big, n_phase1): the other single-pass signals and the column
+  // tiles (second launch); [n_phase1, nitems): the row tiles (third launch)
+  int n_big = 0;
+  int n_phase1 = 0;
   int lds_bytes = 0, resident = 0;
+  int lds_big = 0, resident_big = 0;
   int64_t max_elem = -1;    // largest element index of in/out touched
   int64_t ws_elems = 0;     // workspace elements for four-step intermediates
   bool graph = false, per_size = false;
-  std::vector<std::pair<int, int>> ranges;  // per-size mode: (first item, count)
+  struct Range {
+    int first, count;
+    bool big;
+  };
+  std::vector<Range> ranges;  // per-size mode: one launch each
   std::string summary;
   mutable std::mutex mu;
   mutable std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
@@ -57,8 +68,11 @@ struct RaggedStep : Step {
   hipError_t prepare() const override {
     // dynamic LDS above the default 64 KB needs an explicit opt-in per function
     for (bool inv : {false, true}) {
-      const hipError_t e = hipFuncSetAttribute(ragged_kernel(inv),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+      hipError_t e = hipFuncSetAttribute(ragged_kernel(inv, false),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+      if (e == hipSuccess && n_big > 0)
+        e = hipFuncSetAttribute(ragged_kernel(inv, true),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_big);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -90,48 +104,53 @@ struct RaggedStep : Step {
   hipError_t launch_direct(const ExecCtx &ctx) const {
     RaggedArgs r = args_for(ctx);
     r.direct = 1;
-    const void *fn = ragged_kernel(ctx.inverse);
     for (const auto &rg : ranges) {
       r.first_item = rg.first;
-      r.nitems = rg.second;
+      r.nitems = rg.count;
       const float2 *s = (const float2 *)ctx.in;
       float2 *d = (float2 *)ctx.out;
       void *kargs[] = {(void *)&s, (void *)&d, (void *)&r.ws, (void *)&r.items, (void *)&r.sigoff,
                        (void *)&r.tables, (void *)&r};
-      hipError_t e = hipLaunchKernel(fn, dim3((unsigned)rg.second), dim3(kRaggedThreads), kargs,
-                                     (size_t)lds_bytes, ctx.stream);
+      hipError_t e = hipLaunchKernel(ragged_kernel(ctx.inverse, rg.big), dim3((unsigned)rg.count),
+                                     dim3(rg.big ? kRaggedBigThreads : kRaggedThreads), kargs,
+                                     (size_t)(rg.big ? lds_big : lds_bytes), ctx.stream);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
 
-  // the two persistent launches over items [0, n_phase1) and [n_phase1, nitems)
+  // the persistent launches: k = 0 over [0, n_big) with the 1024-thread
+  // instance, k = 1 over [n_big, n_phase1), k = 2 over [n_phase1, nitems)
   void phase(int k, RaggedArgs &r) const {
     r.direct = 0;
-    r.first_item = k == 0 ? 0 : n_phase1;
-    r.nitems = k == 0 ? n_phase1 : nitems - n_phase1;
+    r.first_item = k == 0 ? 0 : k == 1 ? n_big : n_phase1;
+    r.nitems = k == 0 ? n_big : k == 1 ? n_phase1 - n_big : nitems - n_phase1;
   }
-
-  unsigned grid_of(const RaggedArgs &r) const { return (unsigned)std::min(resident, r.nitems); }
+  static bool big_phase(int k) { return k == 0; }
+  unsigned grid_of(int k, const RaggedArgs &r) const {
+    return (unsigned)std::min(big_phase(k) ? resident_big : resident, r.nitems);
+  }
+  unsigned threads_of(int k) const { return big_phase(k) ? kRaggedBigThreads : kRaggedThreads; }
+  size_t lds_of(int k) const { return (size_t)(big_phase(k) ? lds_big : lds_bytes); }
 
   hipError_t launch_persistent(const ExecCtx &ctx) const {
     RaggedArgs r = args_for(ctx);
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
       phase(k, r);
       if (r.nitems == 0) continue;
       const float2 *s = (const float2 *)ctx.in;
       float2 *d = (float2 *)ctx.out;
       void *kargs[] = {(void *)&s, (void *)&d, (void *)&r.ws, (void *)&r.items, (void *)&r.sigoff,
                        (void *)&r.tables, (void *)&r};
-      e = hipLaunchKernel(ragged_kernel(ctx.inverse), dim3(grid_of(r)), dim3(kRaggedThreads), kargs,
-                          (size_t)lds_bytes, ctx.stream);
+      e = hipLaunchKernel(ragged_kernel(ctx.inverse, big_phase(k)), dim3(grid_of(k, r)),
+                          dim3(threads_of(k)), kargs, lds_of(k), ctx.stream);
     }
     return e;
   }
 
-  // The two persistent launches as a two-node graph, built once per (buffers,
-  // direction, stream).
+  // The persistent launches as a graph of up to three nodes in sequence,
+  // built once per (buffers, direction, stream).
   hipError_t launch_graph(const ExecCtx &ctx) const {
     GraphKey key{ctx.in, ctx.out, ctx.ws, ctx.inverse, ctx.stream};
     hipGraphExec_t exec = nullptr;
@@ -140,28 +159,27 @@ struct RaggedStep : Step {
       exec = find_graph_locked(key);
     }
     if (!exec) {
-      RaggedArgs r0 = args_for(ctx), r1 = args_for(ctx);
-      phase(0, r0);
-      phase(1, r1);
+      RaggedArgs rr[3] = {args_for(ctx), args_for(ctx), args_for(ctx)};
       const float2 *s = (const float2 *)ctx.in;
       float2 *d = (float2 *)ctx.out;
-      void *k0[] = {(void *)&s, (void *)&d, (void *)&r0.ws, (void *)&r0.items, (void *)&r0.sigoff,
-                    (void *)&r0.tables, (void *)&r0};
-      void *k1[] = {(void *)&s, (void *)&d, (void *)&r1.ws, (void *)&r1.items, (void *)&r1.sigoff,
-                    (void *)&r1.tables, (void *)&r1};
+      void *kp[3][7];
+      for (int k = 0; k < 3; ++k) {
+        phase(k, rr[k]);
+        void *v[7] = {(void *)&s, (void *)&d, (void *)&rr[k].ws, (void *)&rr[k].items,
+                      (void *)&rr[k].sigoff, (void *)&rr[k].tables, (void *)&rr[k]};
+        for (int i = 0; i < 7; ++i) kp[k][i] = v[i];
+      }
       hipGraph_t g = nullptr;
       hipError_t e = hipGraphCreate(&g, 0);
       if (e != hipSuccess) return e;
       hipGraphNode_t prev = nullptr;
-      void **kp[2] = {k0, k1};
-      const RaggedArgs *rp[2] = {&r0, &r1};
-      for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-        if (rp[k]->nitems == 0) continue;
+      for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        if (rr[k].nitems == 0) continue;
         hipKernelNodeParams p{};
-        p.func = const_cast<void *>(ragged_kernel(ctx.inverse));
-        p.gridDim = dim3(grid_of(*rp[k]));
-        p.blockDim = dim3(kRaggedThreads);
-        p.sharedMemBytes = (unsigned)lds_bytes;
+        p.func = const_cast<void *>(ragged_kernel(ctx.inverse, big_phase(k)));
+        p.gridDim = dim3(grid_of(k, rr[k]));
+        p.blockDim = dim3(threads_of(k));
+        p.sharedMemBytes = (unsigned)lds_of(k);
         p.kernelParams = kp[k];
         hipGraphNode_t node = nullptr;
         e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
@@ -207,8 +225,8 @@ struct RaggedStep : Step {
   }
 
   bool valid() const override {
-    return lds_bytes <= kRaggedLdsBytes && resident > 0 && ragged_kernel(false) &&
-           ragged_kernel(true);
+    return lds_bytes <= kRaggedLdsBytes && resident > 0 && lds_big <= kRaggedBigLdsBytes &&
+           (n_big == 0 || resident_big > 0) && ragged_kernel(false) && ragged_kernel(true);
   }
 };
 
@@ -226,10 +244,15 @@ int64_t tw_elems(const MixedPlan &mp) {
 }
 
 constexpr int64_t kBudget = kRaggedLdsBytes / (int64_t)sizeof(float2);
+constexpr int64_t kBigBudget = kRaggedBigLdsBytes / (int64_t)sizeof(float2);
 
-// the largest length one ragged workgroup transforms in a single pass
+// the lengths one 256-thread ragged workgroup transforms in a single pass
 bool fits_single(const MixedPlan &mp) {
   return mp.T <= kRaggedThreads && tile_lds(mp, 1, ELEM_FAST) + tw_elems(mp) <= kBudget;
+}
+// ... and one 1024-thread workgroup
+bool fits_big(const MixedPlan &mp) {
+  return mp.T <= kRaggedBigThreads && tile_lds(mp, 1, ELEM_FAST) + tw_elems(mp) <= kBigBudget;
 }
 
 }  // namespace
@@ -237,6 +260,71 @@ bool fits_single(const MixedPlan &mp) {
 }  // namespace dpfft
 
 using namespace dpfft;
+
+std::string dpfft::ragged_tune_key(int64_t L) {
+  // the ragged kernels' shape constants and the version of the choice format
+  uint64_t h = 1469598103934665603ull;
+  for (int64_t v : {(int64_t)kRaggedThreads, (int64_t)kRaggedLdsBytes, (int64_t)kRaggedBigThreads,
+                    (int64_t)kRaggedBigLdsBytes, (int64_t)sizeof(RaggedItem), (int64_t)2}) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  }
+  char reg[20];
+  snprintf(reg, sizeof reg, "%016llx", (unsigned long long)h);
+  return std::string("gfx950|k=") + reg + "|ragged|n=" + std::to_string(L);
+}
+
+// Column lengths n1 of the four-step splits of L whose two factors both fit
+// one 256-thread ragged workgroup, nearest to sqrt(L) first (at most `max`).
+static std::vector<int64_t> ragged_splits(int64_t L, int order, int max) {
+  std::vector<std::pair<double, int64_t>> c;
+  for (int64_t d = 2; d * 2 <= L; ++d) {
+    if (L % d) continue;
+    MixedPlan a{}, b{};
+    if (!mixed_radices(d, &a, order) || !mixed_radices(L / d, &b, order)) continue;
+    if (!fits_single(a) || !fits_single(b)) continue;
+    c.push_back({std::fabs(std::log((double)d) - 0.5 * std::log((double)L)), d});
+  }
+  std::stable_sort(c.begin(), c.end());
+  std::vector<int64_t> out;
+  for (const auto &e : c) {
+    if ((int)out.size() >= max) break;
+    out.push_back(e.second);
+  }
+  return out;
+}
+
+// Forms of a ragged length that a choice may name: single pass in a 256- or
+// a 1024-thread workgroup, four-step.
+static bool ragged_form_fits(int64_t L, int order, int form) {
+  MixedPlan mp{};
+  if (!mixed_radices(L, &mp, order)) return false;
+  if (form == 0) return fits_single(mp);
+  if (form == 2) return fits_big(mp) && !fits_single(mp);
+  return !ragged_splits(L, order, 1).empty();
+}
+
+// Choices worth timing for one ragged length: each radix order (the second
+// only where it differs), each form that fits, and for the four-step the
+// three splits nearest sqrt(L).
+std::vector<std::string> dpfft::ragged_candidates(int64_t L) {
+  std::vector<std::string> out;
+  uint64_t codes0 = 0;
+  for (int order : {0, 1}) {
+    MixedPlan mp{};
+    if (!mixed_radices(L, &mp, order)) continue;
+    if (order == 0) codes0 = mp.codes;
+    else if (mp.codes == codes0) continue;
+    const std::string o = "o=" + std::to_string(order);
+    if (ragged_form_fits(L, order, 0)) out.push_back(o + " f=0");
+    if (ragged_form_fits(L, order, 2)) out.push_back(o + " f=2");
+    for (int64_t n1 : ragged_splits(L, order, 3))
+      out.push_back(o + " f=1 s=" + std::to_string(n1));
+  }
+  return out;
+}
 
 fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *offsets) {
   const int64_t count = P->batch;
@@ -261,17 +349,17 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
     MixedPlan mp;
     int64_t tw2_off;
   };
-  std::map<int64_t, LineInfo> lines;
-  auto line_of = [&](int64_t L) -> const LineInfo * {
-    auto it = lines.find(L);
+  std::map<std::pair<int64_t, int>, LineInfo> lines;
+  auto line_of = [&](int64_t L, int order) -> const LineInfo * {
+    auto it = lines.find({L, order});
     if (it != lines.end()) return &it->second;
     MixedPlan mp{};
-    if (!mixed_radices(L, &mp)) return nullptr;
+    if (!mixed_radices(L, &mp, order)) return nullptr;
     std::vector<std::complex<double>> lo, hi;
     fourstep_tables(L, mp.tw2_shift, lo, hi);
     lo.insert(lo.end(), hi.begin(), hi.end());
     LineInfo li{mp, (int64_t)P->tables.add(lo)};
-    return &(lines[L] = li);
+    return &(lines[{L, order}] = li);
   };
   auto item_for = [](int32_t kind, const LineInfo &li, int C, int64_t tw_lds) {
     RaggedItem it{};
@@ -292,23 +380,40 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
   for (int64_t i = 0; i < count; ++i) by_size[sizes[i]].push_back((int32_t)i);
 
   std::vector<RaggedItem> items;
+  std::vector<char> isbig;
   std::vector<int64_t> sigoff;
   std::vector<int64_t> cost;
-  int64_t lds_need = 1, ws = 0;
-  int nbig_sizes = 0, nsingle_sizes = 0;
+  int64_t lds_need = 1, lds_need_big = 1, ws = 0;
+  int nbig_sizes = 0, nsingle_sizes = 0, nlarge_sizes = 0, ntuned = 0;
   auto lg = [](int64_t L) { return std::max(1.0, std::log2((double)L)); };
 
   for (const auto &kv : by_size) {
     const int64_t L = kv.first;
     const auto &sigs = kv.second;
+    // per-length choices: the tuner's candidate, a forced plan, the tuning
+    // cache, else the heuristic (256-thread single pass where it fits, then
+    // the 1024-thread single pass, then the four-step with the split nearest
+    // sqrt(L))
+    const Override ov = read_ragged_override(L);
+    if (!ov.empty()) ++ntuned;
+    const int order = ov.order >= 0 ? ov.order : 0;
     MixedPlan probe{};
-    if (!mixed_radices(L, &probe))
+    if (!mixed_radices(L, &probe, order))
       return fail(FFT_E_UNSUPPORTED, "no radix plan for ragged size " + std::to_string(L));
-    if (fits_single(probe)) {
-      const LineInfo &li = *line_of(L);
+    int form = ov.form;
+    if (form < 0 || !ragged_form_fits(L, order, form))
+      form = fits_single(probe) ? 0 : (ov.big != 0 && fits_big(probe)) ? 2 : 1;
+    if (!ragged_form_fits(L, order, form))
+      return fail(FFT_E_UNSUPPORTED, "ragged size " + std::to_string(L) + " fits no form");
+    if (form == 0 || form == 2) {
+      const bool big = form == 2;
+      const LineInfo &li = *line_of(L, order);
       const MixedPlan &mp = li.mp;
-      int C = std::max(1, kRaggedThreads / mp.T);
-      while (C > 1 && tile_lds(mp, C, ELEM_FAST) + tw_elems(mp) > kBudget) --C;
+      const int nth = big ? kRaggedBigThreads : kRaggedThreads;
+      const int64_t budget = big ? kBigBudget : kBudget;
+      int C = std::max(1, nth / mp.T);
+      if (ov.c[0] > 0) C = std::min(C, ov.c[0]);
+      while (C > 1 && tile_lds(mp, C, ELEM_FAST) + tw_elems(mp) > budget) --C;
       const int first = (int)items.size();
       for (size_t s0 = 0; s0 < sigs.size(); s0 += C) {
         const int c = (int)std::min<size_t>(C, sigs.size() - s0);
@@ -317,21 +422,27 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
         it.off = (int64_t)sigoff.size();
         for (int k = 0; k < c; ++k) sigoff.push_back(P->roffsets[sigs[s0 + k]]);
         items.push_back(it);
+        isbig.push_back(big);
         cost.push_back((int64_t)(c * L * lg(L)));
-        lds_need = std::max(lds_need, data + tw_elems(mp));
+        (big ? lds_need_big : lds_need) = std::max(big ? lds_need_big : lds_need, data + tw_elems(mp));
       }
-      st->ranges.push_back({first, (int)items.size() - first});
-      ++nsingle_sizes;
+      st->ranges.push_back({first, (int)items.size() - first, big});
+      ++(big ? nlarge_sizes : nsingle_sizes);
       continue;
     }
     // four-step: L = n1 * n2
-    const int64_t n1 = split_factor(L), n2 = L / n1;
-    const LineInfo *l1 = line_of(n1), *l2 = line_of(n2);
+    // the named split where it fits this length, else the one nearest sqrt(L)
+    int64_t n1 = ragged_splits(L, order, 1)[0];
+    if (ov.split > 0)
+      for (int64_t d : ragged_splits(L, order, 64))
+        if (d == ov.split) n1 = d;
+    const int64_t n2 = L / n1;
+    const LineInfo *l1 = line_of(n1, order), *l2 = line_of(n2, order);
     if (!l1 || !l2) return fail(FFT_E_UNSUPPORTED, "no radix plan for ragged size " + std::to_string(L));
     const MixedPlan &m1 = l1->mp, &m2 = l2->mp;
-    if (!fits_single(m1) || !fits_single(m2))
-      return fail(FFT_E_UNSUPPORTED, "ragged size too long for two passes: " + std::to_string(L));
     int CA = std::max(1, kRaggedThreads / m1.T), CB = std::max(1, kRaggedThreads / m2.T);
+    if (ov.c[0] > 0) CA = std::min(CA, ov.c[0]);
+    if (ov.c[1] > 0) CB = std::min(CB, ov.c[1]);
     while (CA > 1 && tile_lds(m1, CA, LINE_FAST) + tw_elems(m1) > kBudget) --CA;
     auto rows_lds = [&](int c) { return std::max(tile_lds(m2, c, ELEM_FAST), tile_lds(m2, c, LINE_FAST)); };
     while (CB > 1 && rows_lds(CB) + tw_elems(m2) > kBudget) --CB;
@@ -341,7 +452,7 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
     const int shift = (lgL + 1) / 2;
     fourstep_tables(L, shift, lo, hi);
     const int64_t lo_off = (int64_t)P->tables.add(lo), hi_off = (int64_t)P->tables.add(hi);
-    auto big = [&](RaggedItem it, int32_t s, int64_t ws_off, int64_t f) {
+    auto four = [&](RaggedItem it, int32_t s, int64_t ws_off, int64_t f) {
       it.first = (int32_t)f;
       it.n1 = (int32_t)n1;
       it.n2 = (int32_t)n2;
@@ -359,40 +470,47 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
       for (int64_t f = 0; f < n2; f += CA) {
         const int c = (int)std::min<int64_t>(CA, n2 - f);
         const int64_t data = tile_lds(m1, c, LINE_FAST);
-        items.push_back(big(item_for(RK_COLUMNS, *l1, c, data), s, ws, f));
+        items.push_back(four(item_for(RK_COLUMNS, *l1, c, data), s, ws, f));
+        isbig.push_back(0);
         cost.push_back((int64_t)(c * n1 * lg(n1)));
         lds_need = std::max(lds_need, data + tw_elems(m1));
       }
       ws += L;
     }
-    st->ranges.push_back({first_cols, (int)items.size() - first_cols});
+    st->ranges.push_back({first_cols, (int)items.size() - first_cols, false});
     const int first_rows = (int)items.size();
     for (size_t k = 0; k < sigs.size(); ++k) {
       for (int64_t f = 0; f < n1; f += CB) {
         const int c = (int)std::min<int64_t>(CB, n1 - f);
         const int64_t data = rows_lds(c);
-        items.push_back(big(item_for(RK_ROWS, *l2, c, data), sigs[k], ws_of[k], f));
+        items.push_back(four(item_for(RK_ROWS, *l2, c, data), sigs[k], ws_of[k], f));
+        isbig.push_back(0);
         cost.push_back((int64_t)(c * n2 * lg(n2)));
         lds_need = std::max(lds_need, data + tw_elems(m2));
       }
     }
-    st->ranges.push_back({first_rows, (int)items.size() - first_rows});
+    st->ranges.push_back({first_rows, (int)items.size() - first_rows, false});
     ++nbig_sizes;
   }
 
   st->nitems = (int)items.size();
+  st->n_big = 0;
   st->n_phase1 = 0;
-  for (const auto &it : items)
-    if (it.kind != RK_ROWS) ++st->n_phase1;
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (isbig[i]) ++st->n_big;
+    if (items[i].kind != RK_ROWS) ++st->n_phase1;
+  }
   if (!st->per_size) {
-    // execution order of the persistent launches: single-pass and column
-    // items first, then the row items, each largest first (the static stride
-    // then hands every workgroup a similar share and keeps the tail short)
+    // execution order of the persistent launches: the 1024-thread single-pass
+    // items, then the other single-pass and the column items, then the row
+    // items, each group largest first (the static stride then hands every
+    // workgroup a similar share and keeps the tail short)
+    auto phase_of = [&](int32_t x) { return isbig[x] ? 0 : items[x].kind == RK_ROWS ? 2 : 1; };
     std::vector<int32_t> order(items.size());
     for (size_t i = 0; i < items.size(); ++i) order[i] = (int32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-      const bool rx = items[x].kind == RK_ROWS, ry = items[y].kind == RK_ROWS;
-      if (rx != ry) return !rx;
+      const int px = phase_of(x), py = phase_of(y);
+      if (px != py) return px < py;
       return cost[x] > cost[y];
     });
     std::vector<RaggedItem> sorted;
@@ -402,8 +520,11 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
   }
   st->lds_bytes = (int)(lds_need * (int64_t)sizeof(float2));
   st->resident = resident_for(st->lds_bytes, kRaggedThreads);
+  st->lds_big = st->n_big ? (int)(lds_need_big * (int64_t)sizeof(float2)) : 0;
+  st->resident_big = st->n_big ? resident_for(st->lds_big, kRaggedBigThreads) : 0;
   if (items.empty()) items.push_back(RaggedItem{});
-  if (lds_need * (int64_t)sizeof(float2) > kRaggedLdsBytes)
+  if (lds_need * (int64_t)sizeof(float2) > kRaggedLdsBytes ||
+      (st->n_big && lds_need_big * (int64_t)sizeof(float2) > kRaggedBigLdsBytes))
     return fail(FFT_E_INTERNAL, "ragged plan exceeds its LDS budget");
   if (sigoff.empty()) sigoff.push_back(0);
   st->items_off = P->tables.add_bytes(items.data(), items.size() * sizeof(RaggedItem));
@@ -413,14 +534,19 @@ fft_status_t plan_ragged(dpfft_plan_s *P, const int64_t *sizes, const int64_t *o
 
 
   std::ostringstream o;
+  const int nl = (st->n_big > 0) + 1 + (st->nitems > st->n_phase1);
   o << "ragged: " << count << " signals, " << nsingle_sizes << " single-pass lengths, "
-    << nbig_sizes << " four-step lengths, " << st->nitems << " items, "
+    << nlarge_sizes << " single-pass lengths of 1024 threads, " << nbig_sizes
+    << " four-step lengths, " << ntuned << " lengths with tuned choices, " << st->nitems
+    << " items, "
     << (st->per_size ? "one launch per length (" + std::to_string(st->ranges.size()) + " launches)"
-                     : std::string("two persistent launches (") + std::to_string(st->n_phase1) + " + " +
+                     : std::to_string(nl) + " persistent launches (" + std::to_string(st->n_big) +
+                           " + " + std::to_string(st->n_phase1 - st->n_big) + " + " +
                            std::to_string(st->nitems - st->n_phase1) + " items), grid=" +
+                           std::to_string(std::min(st->resident_big, st->n_big)) + "/" +
                            std::to_string(std::min(st->resident, st->nitems)))
-    << (st->graph && !st->per_size ? " in a HIP graph" : "") << " threads=" << kRaggedThreads
-    << " lds=" << st->lds_bytes << "B";
+    << (st->graph && !st->per_size ? " in a HIP graph" : "") << " threads=" << kRaggedBigThreads
+    << "/" << kRaggedThreads << " lds=" << st->lds_big << "/" << st->lds_bytes << "B";
   st->summary = o.str();
   P->variant = st->per_size ? "ragged per-length launches" : "ragged persistent";
   P->steps.push_back(std::move(st));

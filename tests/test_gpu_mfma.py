@@ -6,10 +6,10 @@ BF16 keeps only 8 significant bits per operand; it is held to the same 2e-3
 and marked as an expected failure when it misses, with the measured error in
 the reason (it is never passed at a looser bound).
 
-The input-range cases (amplitudes 1e3 and 1e-6, a constant of 16, and the
-inverse of a full-amplitude spectrum) pin the FP16 forms' per-vector
-power-of-two scaling: without it the FP16 pieces overflow or lose their low
-bits."""
+The input-range cases (amplitudes 1e3 and 1e-6, signals of very different
+amplitudes in one batch, a constant of 16, and the inverse of a
+full-amplitude spectrum) pin the FP16 forms' per-line power-of-two scaling:
+without it the FP16 pieces overflow or lose their low bits."""
 import numpy as np
 import pytest
 
@@ -69,6 +69,8 @@ RANGES = {
     "amp1e-6": lambda x: (x * np.float32(1e-6)).astype(np.complex64),
     # a constant 16: the whole energy lands in one bin, 16 * N at DC
     "const16": lambda x: np.full_like(x, 16.0 + 0.0j),
+    # one batch, four amplitudes: each line is scaled on its own
+    "mixed": lambda x: (x * np.array([1e-6, 1.0, 1e3, 1e-3], np.float32)[:, None]).astype(np.complex64),
 }
 
 

@@ -1,9 +1,10 @@
 """GPU parity of ragged batches (packed signals of mixed 7-smooth lengths)
-against the FP64 oracle: the two persistent launches, the same launches replayed
+against the FP64 oracle: the persistent launches, the same launches replayed
 from a HIP graph (several replays with eager work between them, each checked),
 and the one-launch-per-length baseline; forward and inverse; lengths from 1 to
-65536 including four-step lengths above 16384; and the full 10,000-signal
-workload checked signal by signal."""
+65536 including four-step lengths above 16384; every per-length choice the
+autotuner can make; and the full 10,000-signal workload, tuned, checked
+signal by signal."""
 import numpy as np
 import pytest
 
@@ -80,14 +81,45 @@ def test_ragged_with_gaps_and_explicit_offsets():
     assert np.array_equal(y[:5], flat[:5]) and np.array_equal(y[107:200], flat[107:200])
 
 
+FORMS = ["f=0", "f=2", "f=1", "b=0", "o=1", "o=1 f=1", "f=1 c0=2 c1=2", "f=2 c0=1"]
+
+
+@pytest.mark.parametrize("force", FORMS)
+def test_ragged_forced_choices(force, monkeypatch):
+    """Every form a per-length choice can name (single pass in 256 or 1024
+    threads, four-step, no 1024-thread class, odd radices first, narrower
+    tiles), forced on every length where it fits, forward and inverse."""
+    import paper_1203_4938_amd as dp
+    sizes = [64, 1000, 4096, 4800, 6000, 7776, 10080, 16384, 15625, 17640, 65536, 2, 49152]
+    flat, offs = synth.uniform_ragged(synth.BASE_SEED + 803, sizes)
+    monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
+    p = dp.Plan(ragged_sizes=sizes)
+    say(f"[ragged {force}] {p.describe()}")
+    x = to_dev(flat)
+    for inv in (False, True):
+        y = p.exec(x, inverse=inv)
+        e = _ragged_errors(y.cpu().numpy(), flat, sizes, offs, inv)
+        assert e.max() <= TOL_FP32, (force, inv, e.max())
+
+
+def _tune_c5(dp, sizes):
+    d, keep = dp.make_desc(ragged_sizes=sizes.tolist())
+    st, rep = dp.fft_autotune(d, reps=3)
+    assert st == dp.FFT_OK, rep
+    say(f"[c5 tune] {rep.strip()}")
+
+
 def test_c5_full_workload_every_signal():
     """The 10,000-signal workload in the launch configuration the benchmark
-    times (persistent launches in a HIP graph), every signal against the oracle."""
+    times (per-length choices from the autotuner, persistent launches in a HIP
+    graph), every signal against the oracle."""
     import paper_1203_4938_amd as dp
     w = synth.workloads()["c5_ragged_10000"]
     sizes = synth.ragged_sizes(w.seed, w.count)
     flat, offs = synth.uniform_ragged(w.seed, sizes)
+    _tune_c5(dp, sizes)
     p = dp.Plan(ragged_sizes=sizes.tolist(), graph=True)
+    assert "578 lengths with tuned choices" in p.describe()
     say(f"[c5] {p.describe()}")
     x = to_dev(flat)
     for inv in (False, True):

@@ -64,9 +64,23 @@ def test_ragged_plan_counts():
     import synth
     sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
     t = _dry(ragged_sizes=sizes.tolist(), flags=4)
-    assert "10000 signals" in t and "HIP graph" in t and "two persistent launches" in t
+    assert "10000 signals" in t and "HIP graph" in t and "3 persistent launches" in t
+    m = re.search(r"(\d+) single-pass lengths, (\d+) single-pass lengths of 1024 threads, "
+                  r"(\d+) four-step lengths", t)
+    assert m and sum(int(v) for v in m.groups()) == len(set(sizes.tolist())), t
+    assert int(m.group(2)) > 0
     t2 = _dry(ragged_sizes=sizes.tolist(), flags=8)
     assert "one launch per length" in t2
+
+
+def test_ragged_override_without_the_1024_thread_class():
+    import synth
+    sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000).tolist()
+    code = ("import paper_1203_4938_amd as dp\n"
+            f"d, k = dp.make_desc(ragged_sizes={sizes!r}, flags=2)\n"
+            "print(dp.fft_plan_dry(d)[1])\n")
+    out = _run(code, {"DPFFT_FORCE_PLAN": "b=0"})
+    assert " 0 single-pass lengths of 1024 threads" in out and "2 persistent launches" in out, out
 
 
 def _run(code, env_extra):
@@ -148,6 +162,9 @@ def test_autotune_without_device_fails_cleanly():
     d, k = dp.make_desc(65536, 8, precision="fp16")
     st, msg = dp.fft_autotune(d)
     assert st == dp.FFT_OK and "nothing to tune" in msg
+    d, k = dp.make_desc(ragged_sizes=[64, 6000, 40000])
+    st, msg = dp.fft_autotune(d)
+    assert st == dp.FFT_E_DEVICE
 
 
 def test_plans_with_signals_far_apart():
