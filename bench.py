@@ -199,8 +199,8 @@ def build_c5(dp, torch, synth, dev):
         raise RuntimeError(f"ragged autotune failed: {rep}")
     print(f"# c5 autotune ({tune_s:.1f} s): {rep.strip()}", file=sys.stderr, flush=True)
     items = []
-    for name, kw, cmp in (("ragged10000_persistent_graph", dict(graph=True), False),
-                          ("ragged10000_persistent", dict(), True),
+    for name, kw, cmp in (("ragged10000_graph", dict(graph=True), False),
+                          ("ragged10000_no_graph", dict(), True),
                           ("ragged10000_heuristic_graph", dict(graph=True, autotune=False), True),
                           ("ragged10000_one_launch_per_length_runtime_radix", dict(per_size=True),
                            True)):
@@ -208,7 +208,7 @@ def build_c5(dp, torch, synth, dev):
         items.append(Item(dp, torch, name, p, x.clone(), torch.empty_like(x), fl,
                           16.0 * float(sizes.sum()), compare=cmp))
     return items, {"workload": "c5: ragged batch of 10000 7-smooth sizes in [64, 65536], "
-                               "log-uniform; the step is the persistent launches in a HIP graph "
+                               "log-uniform; the step is the ragged launches in a HIP graph "
                                "with autotuned per-length choices; the same launches without the "
                                "graph, the untuned heuristic plan and one launch per distinct "
                                "length are timed after it for comparison",

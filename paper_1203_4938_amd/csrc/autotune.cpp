@@ -45,6 +45,8 @@ Override parse_override(const std::string &text) {
       o.form = val;
     } else if (sscanf(tok.c_str(), "b=%d", &val) == 1) {
       o.big = val;
+    } else if (sscanf(tok.c_str(), "x=%d", &val) == 1) {
+      o.ct = val;
     } else if (sscanf(tok.c_str(), "%c%d=%d", &kind, &idx, &val) == 3 && idx >= 0 && idx < 8) {
       if (kind == 'c') o.c[idx] = val;
       if (kind == 'p') o.p[idx] = val;

@@ -49,6 +49,8 @@ int resident_for(int lds_bytes, int threads);
 //              that does not fit a length leaves that length to the heuristic)
 //   b=0|1      ragged lengths: the heuristic may not / may choose the
 //              1024-thread single pass
+//   x=0|1      ragged four-step lines: runtime-radix passes only / also the
+//              compile-time instances of common lengths
 // Sources, first match wins: the autotuner while it times candidates, the
 // DPFFT_FORCE_PLAN environment variable, the tuning cache entry of the plan.
 struct Override {
@@ -60,6 +62,7 @@ struct Override {
   int split = -1;
   int form = -1;
   int big = -1;
+  int ct = -1;
   std::string text;
   bool empty() const { return text.empty(); }
 };

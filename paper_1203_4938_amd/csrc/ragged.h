@@ -24,6 +24,9 @@ struct RaggedItem {
   int32_t tw_lds;      // LDS element offset of the pass-twiddle table (after the tile data)
   int32_t L, P, T, pitch, tw2_shift;  // line length of this item and its radix plan
   int32_t tw4_shift;
+  int32_t ct;          // 1: the line length has compile-time instances (tw2_off then
+                       // names its per-pass twiddle table instead of the two-level one)
+  int32_t pad;
   uint64_t codes;      // radices, 5 bits each
   int64_t tw2_off;     // two-level pass table of w_L in the table buffer
   int64_t off;         // RK_SINGLE: first index into sigoff; else: the signal's element offset

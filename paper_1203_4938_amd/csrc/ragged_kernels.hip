@@ -18,6 +18,7 @@
 //
 // In direct mode the kernel runs item first_item + blockIdx.x and stops; the
 // per-length baseline launches it once per distinct length.
+#include "mixed_ct.h"
 #include "mixed_device.h"
 #include "ragged.h"
 
@@ -45,6 +46,36 @@ __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__res
     sh.scale = 1.0f / (float)d.L;
     mixed_tile<ELEM_FAST, ELEM_FAST, false, INV ? 3 : 0>(sh, t, lds, NTH);
   } else if (d.kind == RK_COLUMNS) {
+    if constexpr (NTH == kRaggedThreads) {
+      if (d.ct) {
+        CtArgs ca{};
+        ca.C = d.C;
+        ca.c = tid % d.C;
+        ca.j = tid / d.C;
+        ca.valid = in_tile;
+        const int64_t n2 = d.first + ca.c;
+        ca.src = as_glb(in + d.off + n2);
+        ca.dst = as_glb(a.ws + d.ws_off + n2);
+        ca.in_e = ca.out_e = (uint32_t)d.n2;
+        ca.line = (uint32_t)n2;
+        ca.tw4_lo = as_glb(a.tables + d.tw4_lo_off);
+        ca.tw4_hi = as_glb(a.tables + d.tw4_hi_off);
+        ca.tw4_shift = d.tw4_shift;
+        ca.scale = 1.0f;
+        lcf *l = as_lds(lds);
+        switch (d.L) {
+#define CT_COL(LL)                                                                              \
+  case LL:                                                                                      \
+    ct_tile<LL, LINE_FAST, LINE_FAST, true, INV ? 1 : 0>(                                      \
+        ca.src, ca.dst, ca.dst2, ca.tw4_lo, ca.tw4_hi, ca.tw4_shift, ca.C, ca.c, ca.j, ca.c2,   \
+        ca.j2, ca.valid, ca.valid2, ca.in_e, ca.out_e, ca.line, ca.scale, l, l + d.tw_lds,     \
+        as_glb(a.tables + d.tw2_off), NTH);                                                    \
+    return;
+          DPFFT_CT_LENGTHS(CT_COL)
+#undef CT_COL
+        }
+      }
+    }
     sh.tw4_lo = a.tables + d.tw4_lo_off;
     sh.tw4_hi = a.tables + d.tw4_hi_off;
     sh.tw4_shift = d.tw4_shift;
@@ -59,6 +90,37 @@ __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__res
     t.valid2 = false;
     mixed_tile<LINE_FAST, LINE_FAST, true, INV ? 1 : 0>(sh, t, lds, NTH);
   } else {
+    if constexpr (NTH == kRaggedThreads) {
+      if (d.ct) {
+        CtArgs ca{};
+        ca.C = d.C;
+        ca.c = tid / d.T;
+        ca.j = tid % d.T;
+        ca.valid = in_tile;
+        const int64_t k1 = d.first + ca.c;
+        ca.src = as_glb(a.ws + d.ws_off + k1 * d.n2);
+        ca.in_e = 1;
+        ca.out_e = (uint32_t)d.n1;
+        ca.line = (uint32_t)k1;
+        ca.c2 = tid % d.C;
+        ca.j2 = tid / d.C;
+        ca.valid2 = in_tile;
+        ca.dst2 = as_glb(out + d.off + d.first + ca.c2);
+        ca.scale = (float)(1.0 / ((double)d.n1 * (double)d.n2));
+        lcf *l = as_lds(lds);
+        switch (d.L) {
+#define CT_ROW(LL)                                                                             \
+  case LL:                                                                                     \
+    ct_tile<LL, ELEM_FAST, LINE_FAST, false, INV ? 2 : 0>(                                    \
+        ca.src, ca.dst, ca.dst2, ca.tw4_lo, ca.tw4_hi, ca.tw4_shift, ca.C, ca.c, ca.j, ca.c2, \
+        ca.j2, ca.valid, ca.valid2, ca.in_e, ca.out_e, ca.line, ca.scale, l, l + d.tw_lds,   \
+        as_glb(a.tables + d.tw2_off), NTH);                                                  \
+    return;
+          DPFFT_CT_LENGTHS(CT_ROW)
+#undef CT_ROW
+        }
+      }
+    }
     t.c = tid / d.T;
     t.j = tid % d.T;
     t.valid = in_tile;

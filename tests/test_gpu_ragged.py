@@ -1,5 +1,6 @@
 """GPU parity of ragged batches (packed signals of mixed 7-smooth lengths)
-against the FP64 oracle: the persistent launches, the same launches replayed
+against the FP64 oracle: the launches (one workgroup per item, or resident
+workgroups walking the item lists), the same launches replayed
 from a HIP graph (several replays with eager work between them, each checked),
 and the one-launch-per-length baseline; forward and inverse; lengths from 1 to
 65536 including four-step lengths above 16384; every per-length choice the
@@ -81,7 +82,8 @@ def test_ragged_with_gaps_and_explicit_offsets():
     assert np.array_equal(y[:5], flat[:5]) and np.array_equal(y[107:200], flat[107:200])
 
 
-FORMS = ["f=0", "f=2", "f=1", "b=0", "o=1", "o=1 f=1", "f=1 c0=2 c1=2", "f=2 c0=1"]
+FORMS = ["f=0", "f=2", "f=1", "b=0", "o=1", "o=1 f=1", "f=1 c0=2 c1=2", "f=2 c0=1", "x=0", "x=0 f=1",
+         "p0=1", "p0=1 x=0"]
 
 
 @pytest.mark.parametrize("force", FORMS)
@@ -111,8 +113,8 @@ def _tune_c5(dp, sizes):
 
 def test_c5_full_workload_every_signal():
     """The 10,000-signal workload in the launch configuration the benchmark
-    times (per-length choices from the autotuner, persistent launches in a HIP
-    graph), every signal against the oracle."""
+    times (per-length choices from the autotuner, the launches in a HIP graph),
+    every signal against the oracle."""
     import paper_1203_4938_amd as dp
     w = synth.workloads()["c5_ragged_10000"]
     sizes = synth.ragged_sizes(w.seed, w.count)

@@ -64,7 +64,8 @@ def test_ragged_plan_counts():
     import synth
     sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
     t = _dry(ragged_sizes=sizes.tolist(), flags=4)
-    assert "10000 signals" in t and "HIP graph" in t and "3 persistent launches" in t
+    assert "10000 signals" in t and "HIP graph" in t and "3 launches" in t
+    assert "one workgroup per item" in t
     m = re.search(r"(\d+) single-pass lengths, (\d+) single-pass lengths of 1024 threads, "
                   r"(\d+) four-step lengths", t)
     assert m and sum(int(v) for v in m.groups()) == len(set(sizes.tolist())), t
@@ -80,7 +81,9 @@ def test_ragged_override_without_the_1024_thread_class():
             f"d, k = dp.make_desc(ragged_sizes={sizes!r}, flags=2)\n"
             "print(dp.fft_plan_dry(d)[1])\n")
     out = _run(code, {"DPFFT_FORCE_PLAN": "b=0"})
-    assert " 0 single-pass lengths of 1024 threads" in out and "2 persistent launches" in out, out
+    assert " 0 single-pass lengths of 1024 threads" in out and "2 launches" in out, out
+    out = _run(code, {"DPFFT_FORCE_PLAN": "p0=1"})
+    assert "3 persistent launches" in out and "grid=" in out, out
 
 
 def _run(code, env_extra):
