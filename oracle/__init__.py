@@ -69,9 +69,17 @@ class OracleLib:
         lib.oracle_threads.argtypes = [ci]
         lib.oracle_rel_l2_f32.argtypes = [fp, dp, i64, i64, dp, dp, ci]
         lib.oracle_circular_conv_f32.argtypes = [fp, fp, dp, i64, i64, i64, ci]
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        cd = ctypes.c_double
+        lib.oracle_img_ycc.argtypes = [u8p, i64, i64, dp, dp, dp]
+        lib.oracle_img_blocks.argtypes = [dp, i64, i64, dp, dp, dp]
+        lib.oracle_img_kmeans.argtypes = [dp, dp, i64, cd, ci, ci, dp, ip]
+        lib.oracle_img_encode.argtypes = [dp, dp, i64, cd, dp, ci, i32p, dp]
         for f in (lib.oracle_dft, lib.oracle_fft, lib.oracle_fft_batch_f32,
                   lib.oracle_fft_ragged_f32, lib.oracle_fft2d_f32, lib.oracle_threads,
-                  lib.oracle_rel_l2_f32, lib.oracle_circular_conv_f32):
+                  lib.oracle_rel_l2_f32, lib.oracle_circular_conv_f32, lib.oracle_img_ycc,
+                  lib.oracle_img_blocks, lib.oracle_img_kmeans, lib.oracle_img_encode):
             f.restype = ci
         self.lib = lib
         self.path = path
@@ -143,6 +151,56 @@ class OracleLib:
                                                  threads))
         return y
 
+    # ---- image block compression (section III-B) ----
+    def img_ycc(self, rgb):
+        """(a)+(b): rgb uint8 (h, w, 3) -> Y (h, w), Cb, Cr (h/2, w/2), float64."""
+        rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+        h, w = rgb.shape[:2]
+        y = np.empty((h, w))
+        cb = np.empty((h // 2, w // 2))
+        cr = np.empty((h // 2, w // 2))
+        _check(self.lib.oracle_img_ycc(_ptr(rgb, ctypes.c_uint8), h, w, _ptr(y, ctypes.c_double),
+                                       _ptr(cb, ctypes.c_double), _ptr(cr, ctypes.c_double)))
+        return y, cb, cr
+
+    def img_blocks(self, y):
+        """(c): Y (h, w) -> block means (h/4, w/4), activities (h/4, w/4),
+        deviations (h/4 * w/4, 16)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        h, w = y.shape
+        nb = (h // 4) * (w // 4)
+        mean = np.empty((h // 4, w // 4))
+        act = np.empty((h // 4, w // 4))
+        dev = np.empty((nb, 16))
+        _check(self.lib.oracle_img_blocks(_ptr(y, ctypes.c_double), h, w,
+                                          _ptr(mean, ctypes.c_double), _ptr(act, ctypes.c_double),
+                                          _ptr(dev, ctypes.c_double)))
+        return mean, act, dev
+
+    def img_kmeans(self, dev, act, tau: float, k: int, iters: int):
+        """(d): codebook (k, 16) and the number of pattern blocks."""
+        dev = np.ascontiguousarray(dev, dtype=np.float64).reshape(-1, 16)
+        act = np.ascontiguousarray(act, dtype=np.float64).reshape(-1)
+        cb = np.empty((k, 16))
+        npat = ctypes.c_int64(0)
+        _check(self.lib.oracle_img_kmeans(_ptr(dev, ctypes.c_double), _ptr(act, ctypes.c_double),
+                                          dev.shape[0], float(tau), int(k), int(iters),
+                                          _ptr(cb, ctypes.c_double), ctypes.byref(npat)))
+        return cb, int(npat.value)
+
+    def img_encode(self, dev, act, tau: float, codebook):
+        """(e): codes (int32, 0 = mean only) and decision margins per block."""
+        dev = np.ascontiguousarray(dev, dtype=np.float64).reshape(-1, 16)
+        act = np.ascontiguousarray(act, dtype=np.float64).reshape(-1)
+        cb = np.ascontiguousarray(codebook, dtype=np.float64).reshape(-1, 16)
+        code = np.empty(dev.shape[0], dtype=np.int32)
+        margin = np.empty(dev.shape[0])
+        _check(self.lib.oracle_img_encode(_ptr(dev, ctypes.c_double), _ptr(act, ctypes.c_double),
+                                          dev.shape[0], float(tau), _ptr(cb, ctypes.c_double),
+                                          cb.shape[0], _ptr(code, ctypes.c_int32),
+                                          _ptr(margin, ctypes.c_double)))
+        return code, margin
+
     def threads(self, requested: int = 0) -> int:
         return self.lib.oracle_threads(requested)
 
@@ -195,6 +253,22 @@ def fft_ragged(flat, sizes, offsets, inverse: bool = False, threads: int = 0) ->
 
 def fft2d(x, inverse: bool = False, threads: int = 0) -> np.ndarray:
     return default().fft2d(x, inverse, threads)
+
+
+def img_ycc(rgb):
+    return default().img_ycc(rgb)
+
+
+def img_blocks(y):
+    return default().img_blocks(y)
+
+
+def img_kmeans(dev, act, tau, k, iters):
+    return default().img_kmeans(dev, act, tau, k, iters)
+
+
+def img_encode(dev, act, tau, codebook):
+    return default().img_encode(dev, act, tau, codebook)
 
 
 def circular_conv(x, h, threads: int = 0) -> np.ndarray:

@@ -349,3 +349,162 @@ int oracle_circular_conv_f32(const float *x, const float *h, double *y, int64_t 
     }
     return 0;
 }
+
+/*
+ * Image block compression, section III-B of the paper: five steps, the first
+ * three and the last data-parallel, the codebook made from the returned data.
+ * The paper names the steps but prints no formula; the readings here are the
+ * textbook ones (listed with the library's design notes):
+ *
+ *  (a) chroma + luminance: full-range BT.601 as in JFIF,
+ *        Y  =       0.299    R + 0.587    G + 0.114    B
+ *        Cb = 128 - 0.168736 R - 0.331264 G + 0.5      B
+ *        Cr = 128 + 0.5      R - 0.418688 G - 0.081312 B
+ *  (b) chroma scaled to a quarter of the pixels: the mean of each 2x2 square;
+ *  (c) directional derivative of the luminance along its gradient, |grad Y|,
+ *      from central differences (edge pixels replicated outward), and per 4x4
+ *      block its mean (the block's activity), the block's mean luminance and
+ *      its 16 deviations from that mean (raster order);
+ *  (d) codebook: k-means (Lloyd's iteration) over the deviation vectors of
+ *      the blocks whose activity is at least tau, started from the deviation
+ *      vectors of the pattern blocks of rank floor(c P / k), c = 0..k-1 (P
+ *      pattern blocks in raster order); a codeword left without blocks keeps
+ *      its value; ties go to the lower codeword;
+ *  (e) encoding: a block of activity below tau keeps its mean only (code 0),
+ *      any other block its mean and 1 + the index of the nearest codeword in
+ *      squared Euclidean distance.
+ * Images are h x w pixels, h and w multiples of 4, RGB interleaved uint8.
+ */
+int oracle_img_ycc(const uint8_t *rgb, int64_t h, int64_t w, double *y, double *cb,
+                   double *cr) {
+    if (!rgb || !y || !cb || !cr || h <= 0 || w <= 0 || (h | w) & 1) return -1;
+    double *fcb = (double *)malloc(sizeof(double) * h * w);
+    double *fcr = (double *)malloc(sizeof(double) * h * w);
+    if (!fcb || !fcr) {
+        free(fcb);
+        free(fcr);
+        return -1;
+    }
+    for (int64_t i = 0; i < h * w; ++i) {
+        const double r = rgb[3 * i], g = rgb[3 * i + 1], b = rgb[3 * i + 2];
+        y[i] = 0.299 * r + 0.587 * g + 0.114 * b;
+        fcb[i] = 128.0 - 0.168736 * r - 0.331264 * g + 0.5 * b;
+        fcr[i] = 128.0 + 0.5 * r - 0.418688 * g - 0.081312 * b;
+    }
+    const int64_t h2 = h / 2, w2 = w / 2;
+    for (int64_t r = 0; r < h2; ++r)
+        for (int64_t c = 0; c < w2; ++c) {
+            const int64_t p = 2 * r * w + 2 * c;
+            cb[r * w2 + c] = 0.25 * (fcb[p] + fcb[p + 1] + fcb[p + w] + fcb[p + w + 1]);
+            cr[r * w2 + c] = 0.25 * (fcr[p] + fcr[p + 1] + fcr[p + w] + fcr[p + w + 1]);
+        }
+    free(fcb);
+    free(fcr);
+    return 0;
+}
+
+int oracle_img_blocks(const double *y, int64_t h, int64_t w, double *mean, double *act,
+                      double *dev) {
+    if (!y || !mean || !act || !dev || h <= 0 || w <= 0 || (h | w) & 3) return -1;
+    const int64_t bw = w / 4, bh = h / 4;
+    for (int64_t br = 0; br < bh; ++br)
+        for (int64_t bc = 0; bc < bw; ++bc) {
+            const int64_t b = br * bw + bc;
+            double s = 0.0, g = 0.0;
+            for (int64_t i = 0; i < 4; ++i)
+                for (int64_t j = 0; j < 4; ++j) {
+                    const int64_t r = 4 * br + i, c = 4 * bc + j;
+                    const int64_t cl = c > 0 ? c - 1 : 0, cr = c < w - 1 ? c + 1 : w - 1;
+                    const int64_t ru = r > 0 ? r - 1 : 0, rd = r < h - 1 ? r + 1 : h - 1;
+                    const double gx = 0.5 * (y[r * w + cr] - y[r * w + cl]);
+                    const double gy = 0.5 * (y[rd * w + c] - y[ru * w + c]);
+                    g += sqrt(gx * gx + gy * gy);
+                    s += y[r * w + c];
+                }
+            mean[b] = s / 16.0;
+            act[b] = g / 16.0;
+            for (int64_t i = 0; i < 4; ++i)
+                for (int64_t j = 0; j < 4; ++j)
+                    dev[16 * b + 4 * i + j] = y[(4 * br + i) * w + 4 * bc + j] - mean[b];
+        }
+    return 0;
+}
+
+/* index of the nearest codeword (ties to the lower index) and, if margin is
+ * not NULL, the gap between the second-nearest and the nearest distance */
+static int nearest_codeword(const double *v, const double *cb, int k, double *margin) {
+    int best = 0;
+    double d1 = INFINITY, d2 = INFINITY;
+    for (int c = 0; c < k; ++c) {
+        double d = 0.0;
+        for (int t = 0; t < 16; ++t) {
+            const double e = v[t] - cb[16 * c + t];
+            d += e * e;
+        }
+        if (d < d1) {
+            d2 = d1;
+            d1 = d;
+            best = c;
+        } else if (d < d2) {
+            d2 = d;
+        }
+    }
+    if (margin) *margin = d2 - d1;
+    return best;
+}
+
+int oracle_img_kmeans(const double *dev, const double *act, int64_t nb, double tau, int k,
+                      int iters, double *codebook, int64_t *npattern) {
+    if (!dev || !act || !codebook || nb < 0 || k <= 0 || iters < 0) return -1;
+    int64_t P = 0;
+    for (int64_t b = 0; b < nb; ++b) P += act[b] >= tau;
+    if (npattern) *npattern = P;
+    for (int64_t i = 0; i < 16 * (int64_t)k; ++i) codebook[i] = 0.0;
+    if (P == 0) return 0;
+    int64_t *pat = (int64_t *)malloc(sizeof(int64_t) * P);
+    double *sum = (double *)malloc(sizeof(double) * 16 * k);
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * k);
+    if (!pat || !sum || !cnt) {
+        free(pat);
+        free(sum);
+        free(cnt);
+        return -1;
+    }
+    for (int64_t b = 0, q = 0; b < nb; ++b)
+        if (act[b] >= tau) pat[q++] = b;
+    for (int c = 0; c < k; ++c) {
+        const int64_t src = pat[(int64_t)c * P / k];
+        for (int t = 0; t < 16; ++t) codebook[16 * c + t] = dev[16 * src + t];
+    }
+    for (int it = 0; it < iters; ++it) {
+        for (int64_t i = 0; i < 16 * (int64_t)k; ++i) sum[i] = 0.0;
+        for (int c = 0; c < k; ++c) cnt[c] = 0;
+        for (int64_t q = 0; q < P; ++q) {
+            const double *v = dev + 16 * pat[q];
+            const int c = nearest_codeword(v, codebook, k, NULL);
+            for (int t = 0; t < 16; ++t) sum[16 * c + t] += v[t];
+            cnt[c] += 1;
+        }
+        for (int c = 0; c < k; ++c)
+            if (cnt[c] > 0)
+                for (int t = 0; t < 16; ++t) codebook[16 * c + t] = sum[16 * c + t] / (double)cnt[c];
+    }
+    free(pat);
+    free(sum);
+    free(cnt);
+    return 0;
+}
+
+int oracle_img_encode(const double *dev, const double *act, int64_t nb, double tau,
+                      const double *codebook, int k, int32_t *code, double *margin) {
+    if (!dev || !act || !codebook || !code || nb < 0 || k <= 0) return -1;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (act[b] < tau) {
+            code[b] = 0;
+            if (margin) margin[b] = INFINITY;
+            continue;
+        }
+        code[b] = 1 + nearest_codeword(dev + 16 * b, codebook, k, margin ? margin + b : NULL);
+    }
+    return 0;
+}

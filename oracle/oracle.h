@@ -67,6 +67,29 @@ int oracle_rel_l2_f32(const float *y, const double *ref, int64_t n,
 int oracle_circular_conv_f32(const float *x, const float *h, double *y, int64_t n,
                              int64_t batch, int64_t h_dist, int threads);
 
+/* Image block compression (section III-B), steps a-e; images h x w pixels,
+ * RGB interleaved uint8, h and w multiples of 4 (see oracle.c for the
+ * formulas).
+ *   oracle_img_ycc:    Y (h x w), Cb and Cr averaged over 2x2 squares
+ *                      ((h/2) x (w/2) each)
+ *   oracle_img_blocks: per 4x4 block (raster order, (h/4) x (w/4) blocks):
+ *                      mean luminance, activity (mean |grad Y|), 16
+ *                      deviations from the mean
+ *   oracle_img_kmeans: k codewords of 16 values from the deviation vectors of
+ *                      the blocks with activity >= tau, after `iters` Lloyd
+ *                      iterations; *npattern (may be NULL) = pattern blocks
+ *   oracle_img_encode: code per block, 0 = mean only, else 1 + nearest
+ *                      codeword; margin (may be NULL): second-nearest minus
+ *                      nearest squared distance (infinity for code 0) */
+int oracle_img_ycc(const uint8_t *rgb, int64_t h, int64_t w, double *y, double *cb,
+                   double *cr);
+int oracle_img_blocks(const double *y, int64_t h, int64_t w, double *mean, double *act,
+                      double *dev);
+int oracle_img_kmeans(const double *dev, const double *act, int64_t nb, double tau, int k,
+                      int iters, double *codebook, int64_t *npattern);
+int oracle_img_encode(const double *dev, const double *act, int64_t nb, double tau,
+                      const double *codebook, int k, int32_t *code, double *margin);
+
 /* Number of OpenMP threads a parallel region will use with `threads`. */
 int oracle_threads(int threads);
 

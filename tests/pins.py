@@ -18,7 +18,12 @@ textbook definition X[k] = sum_j x[j] exp(-2 pi i j k / N)):
     shapes;
   * circular convolution: delta and shifted delta, polynomial products with
     exact binomial coefficients, numpy's linear convolution, and the
-    convolution theorem with the oracle's FFT.
+    convolution theorem with the oracle's FFT;
+  * image block compression (section III-B): grey levels and primaries of
+    the colour transform and the published JFIF inverse, 2x2 chroma squares
+    and sums, the gradient of a luminance ramp, block means and deviations,
+    exact recovery of well-separated clusters, the monotone k-means
+    objective, and brute-force nearest codewords.
 """
 from __future__ import annotations
 
@@ -353,10 +358,157 @@ def pin_conv_theorem(o, quick=False):
     return worst <= TOL, f"max rel {worst:.2e}"
 
 
+# ---------------------------------------------------------------------------
+# image block compression (section III-B, steps a-e)
+# ---------------------------------------------------------------------------
+def pin_img_ycc_values(o, quick=False):
+    """(a) White, black and every grey map to Y = the grey level and Cb = Cr =
+    128 exactly (each row of the transform sums to 1, 0, 0); the published
+    JFIF inverse, R = Y + 1.402 (Cr - 128), G = Y - 0.344136 (Cb - 128) -
+    0.714136 (Cr - 128), B = Y + 1.772 (Cb - 128), written independently,
+    recovers random colours; the pure primaries give the standard values."""
+    ok = True
+    for v in (0, 1, 128, 254, 255):
+        rgb = np.full((2, 2, 3), v, np.uint8)
+        y, cb, cr = o.img_ycc(rgb)
+        ok &= bool(np.allclose(y, v, rtol=0, atol=1e-12) and np.allclose(cb, 128, atol=1e-12)
+                   and np.allclose(cr, 128, atol=1e-12))
+    rng = _rng(31)
+    rgb = rng.integers(0, 256, (2, 200, 3)).astype(np.uint8)
+    # per-pixel values: undo the 2x2 averaging by using 2x2 constant squares
+    rgb4 = np.repeat(np.repeat(rgb[:1], 2, axis=0), 2, axis=1)
+    y, cb, cr = o.img_ycc(rgb4)
+    Y = y[0, ::2]
+    R = Y + 1.402 * (cr[0] - 128)
+    G = Y - 0.344136 * (cb[0] - 128) - 0.714136 * (cr[0] - 128)
+    B = Y + 1.772 * (cb[0] - 128)
+    err = np.max(np.abs(np.stack([R, G, B], -1) - rgb[0].astype(np.float64)))
+    ok &= bool(err < 2e-3)
+    red = np.zeros((2, 2, 3), np.uint8)
+    red[..., 0] = 255
+    y, cb, cr = o.img_ycc(red)
+    ok &= bool(abs(y[0, 0] - 76.245) < 1e-9 and abs(cb[0, 0] - (128 - 43.02768)) < 1e-9
+               and abs(cr[0, 0] - 255.5) < 1e-9)
+    return ok, f"inverse max err {err:.2e}"
+
+
+def pin_img_downscale(o, quick=False):
+    """(b) A chroma plane constant on each 2x2 square comes out as those
+    constants; any image keeps the chroma sum (4 x the downscaled sum)."""
+    rng = _rng(32)
+    small = rng.integers(0, 256, (5, 7, 3)).astype(np.uint8)
+    big = np.repeat(np.repeat(small, 2, axis=0), 2, axis=1)
+    _, cb, cr = o.img_ycc(big)
+    r, g, b = (small[..., i].astype(np.float64) for i in range(3))
+    want_cb = 128 - 0.168736 * r - 0.331264 * g + 0.5 * b
+    ok = bool(np.allclose(cb, want_cb, rtol=0, atol=1e-9))
+    img = rng.integers(0, 256, (12, 20, 3)).astype(np.uint8)
+    _, cb2, cr2 = o.img_ycc(img)
+    r, g, b = (img[..., i].astype(np.float64) for i in range(3))
+    full_cr = 128 + 0.5 * r - 0.418688 * g - 0.081312 * b
+    ok &= bool(abs(4 * cr2.sum() - full_cr.sum()) < 1e-7)
+    ok &= bool(np.allclose(cr2, full_cr.reshape(6, 2, 10, 2).mean(axis=(1, 3)), atol=1e-9))
+    return ok, "square constants and chroma sums"
+
+
+def pin_img_blocks(o, quick=False):
+    """(c) A luminance ramp Y = a x + b y has |grad Y| = sqrt(a^2 + b^2) at
+    every pixel off the edges (half that along an axis at the edges, where the
+    difference is one-sided over one pixel); a block's mean is the ramp at its
+    centre and its deviations sum to zero; a flat image has zero activity and
+    deviations."""
+    h, w = 16, 24
+    a, b = 3.0, -1.5
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    Y = a * xx + b * yy
+    mean, act, dev = o.img_blocks(Y)
+    inner = act[1:-1, 1:-1]
+    ok = bool(np.allclose(inner, np.hypot(a, b), rtol=0, atol=1e-12))
+    centres = a * (4 * np.arange(w // 4) + 1.5)[None, :] + b * (4 * np.arange(h // 4) + 1.5)[:, None]
+    ok &= bool(np.allclose(mean, centres, atol=1e-12))
+    ok &= bool(np.allclose(dev.sum(axis=1), 0, atol=1e-11))
+    ok &= bool(np.allclose(dev[0].reshape(4, 4), Y[:4, :4] - Y[:4, :4].mean(), atol=1e-12))
+    # corner block: edge pixels see one-sided differences
+    g = np.zeros((4, 4))
+    for i in range(4):
+        for j in range(4):
+            gx = 0.5 * (Y[i, min(j + 1, w - 1)] - Y[i, max(j - 1, 0)])
+            gy = 0.5 * (Y[min(i + 1, h - 1), j] - Y[max(i - 1, 0), j])
+            g[i, j] = np.hypot(gx, gy)
+    ok &= bool(abs(act[0, 0] - g.mean()) < 1e-12)
+    m2, a2, d2 = o.img_blocks(np.full((8, 8), 77.0))
+    ok &= bool(np.all(a2 == 0) and np.all(d2 == 0) and np.all(m2 == 77.0))
+    return ok, "ramp, corner and flat image"
+
+
+def pin_img_kmeans_clusters(o, quick=False):
+    """(d) K well-separated clusters of equal size, stored one cluster after
+    the other: the initial codewords (ranks floor(c P / K)) fall one in each
+    cluster, and one Lloyd iteration gives exactly the cluster means (numpy);
+    more iterations leave them there.  Blocks below tau take no part."""
+    rng = _rng(33)
+    K, per = 6, 40
+    centres = rng.normal(0, 50, (K, 16))
+    dev = np.concatenate([centres[c] + rng.normal(0, 0.5, (per, 16)) for c in range(K)])
+    act = np.full(K * per, 10.0)
+    extra = rng.normal(0, 50, (7, 16))       # uniform blocks, never clustered
+    dev_all = np.concatenate([dev[:100], extra, dev[100:]])
+    act_all = np.concatenate([act[:100], np.full(7, 0.5), act[100:]])
+    want = np.stack([dev[c * per:(c + 1) * per].mean(axis=0) for c in range(K)])
+    ok = True
+    for iters in (1, 4):
+        cb, P = o.img_kmeans(dev_all, act_all, 1.0, K, iters)
+        ok &= bool(P == K * per and np.allclose(cb, want, rtol=0, atol=1e-10))
+    cb0, _ = o.img_kmeans(dev_all, act_all, 1.0, K, 0)
+    ok &= bool(np.array_equal(cb0, dev[[c * per for c in range(K)]]))
+    return ok, "cluster means"
+
+
+def pin_img_kmeans_monotone(o, quick=False):
+    """(d) Lloyd's iteration never increases the within-cluster sum of
+    squares (each step is a minimisation), here on unclustered data."""
+    rng = _rng(34)
+    dev = rng.normal(0, 10, (500, 16))
+    act = np.full(500, 5.0)
+    prev = np.inf
+    ok = True
+    for it in range(6):
+        cb, _ = o.img_kmeans(dev, act, 1.0, 12, it)
+        d = ((dev[:, None, :] - cb[None]) ** 2).sum(-1).min(axis=1).sum()
+        ok &= bool(d <= prev * (1 + 1e-12))
+        prev = d
+    return ok, f"final sse {prev:.4g}"
+
+
+def pin_img_encode(o, quick=False):
+    """(e) Brute force with numpy: code 0 below tau, else 1 + the argmin of
+    the squared distances (first index on ties); margins are the gap to the
+    second-nearest."""
+    rng = _rng(35)
+    dev = rng.normal(0, 10, (300, 16))
+    act = rng.uniform(0, 10, 300)
+    cb = rng.normal(0, 10, (9, 16))
+    cb[4] = cb[2]                      # a tie: the lower index must win
+    dev[7] = cb[2]
+    act[7] = 6.0
+    act[5] = 4.0                       # activity exactly tau: a pattern block
+    code, margin = o.img_encode(dev, act, 4.0, cb)
+    d = ((dev[:, None, :] - cb[None]) ** 2).sum(-1)
+    want = np.where(act < 4.0, 0, 1 + np.argmin(d, axis=1))
+    srt = np.sort(d, axis=1)
+    ok = bool(np.array_equal(code, want))
+    pat = act >= 4.0
+    ok &= bool(np.allclose(margin[pat], (srt[:, 1] - srt[:, 0])[pat], rtol=1e-12, atol=1e-9))
+    ok &= bool(code[7] == 3 and code[5] != 0)
+    return ok, "brute-force codes"
+
+
 ALL_PINS = [pin_golden, pin_fft_vs_dft, pin_impulse, pin_constant, pin_tone, pin_geometric,
             pin_linearity, pin_parseval, pin_shift, pin_round_trip, pin_hermitian,
             pin_numpy_batch, pin_numpy_ragged, pin_numpy_2d, pin_image_2d,
-            pin_conv_delta_and_shift, pin_conv_polynomial, pin_conv_numpy, pin_conv_theorem]
+            pin_conv_delta_and_shift, pin_conv_polynomial, pin_conv_numpy, pin_conv_theorem,
+            pin_img_ycc_values, pin_img_downscale, pin_img_blocks, pin_img_kmeans_clusters,
+            pin_img_kmeans_monotone, pin_img_encode]
 
 
 def run_all(o, quick=True):

@@ -44,6 +44,14 @@ MUTANTS = [
     ("conv_imag_sign", "si += xr * hi + xi * hr;", "si += xr * hi - xi * hr;", 0),
     ("conv_filter_dist_ignored", "const float *hb = h + 2 * b * h_dist;", "const float *hb = h;", 0),
     ("conv_signal_stride", "const float *xb = x + 2 * b * n;", "const float *xb = x + b * n;", 0),
+    ("img_cb_sign", "- 0.331264 * g + 0.5 * b;", "+ 0.331264 * g + 0.5 * b;", 0),
+    ("img_downscale_offset", "fcb[p + w] + fcb[p + w + 1]", "fcb[p + w] + fcb[p + w - 1]", 0),
+    ("img_gradient_unhalved", "const double gx = 0.5 * (", "const double gx = (", 0),
+    ("img_gradient_edge", "ru = r > 0 ? r - 1 : 0", "ru = r > 0 ? r - 1 : 1", 0),
+    ("img_kmeans_init_rank", "pat[(int64_t)c * P / k]", "pat[(int64_t)c * P / k / 2]", 0),
+    ("img_kmeans_mean", "sum[16 * c + t] / (double)cnt[c]", "sum[16 * c + t] / (double)(cnt[c] + 1)", 0),
+    ("img_encode_tie", "        if (d < d1) {", "        if (d <= d1) {", 0),
+    ("img_encode_threshold", "        if (act[b] < tau) {", "        if (act[b] <= tau) {", 0),
 ]
 
 
