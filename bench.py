@@ -47,6 +47,8 @@ def parse():
                     help="also time a plain 1 GiB device copy (bandwidth reference)")
     ap.add_argument("--no-extras", action="store_true",
                     help="c2: skip the comparison entries timed after the step")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="c5: skip the ragged autotuning (plans read DPFFT_TUNE_CACHE if set)")
     return ap.parse_args()
 
 
@@ -185,7 +187,7 @@ def build_c4(dp, torch, synth, dev):
     return items, {"workload": "c4: N=2^16 batch 4096, precision forms"}
 
 
-def build_c5(dp, torch, synth, dev):
+def build_c5(dp, torch, synth, dev, tune=True):
     sizes = synth.ragged_sizes(synth.BASE_SEED + 5, 10000)
     flat, offs = synth.uniform_ragged(synth.BASE_SEED + 5, sizes)
     x = torch.from_numpy(flat).to(dev)
@@ -193,7 +195,7 @@ def build_c5(dp, torch, synth, dev):
     # per-length choices from the autotuner (plan time, outside any timing)
     d, keep = dp.make_desc(ragged_sizes=sizes.tolist())
     t0 = time.perf_counter()
-    st, rep = dp.fft_autotune(d, reps=3)
+    st, rep = dp.fft_autotune(d, reps=3) if tune else (dp.FFT_OK, "skipped (--no-tune)")
     tune_s = time.perf_counter() - t0
     if st != dp.FFT_OK:
         raise RuntimeError(f"ragged autotune failed: {rep}")
@@ -289,11 +291,40 @@ def build_real(dp, torch, synth, dev):
                      p.describe().splitlines()[0])
 
 
+def build_img(dp, torch, synth, dev):
+    """Image block compression (section III-B): 16 colour photographs of
+    2048 x 2048, k = 64 codewords, 8 Lloyd iterations, tau = 8.  Algorithmic
+    bytes per pixel: 3 read and 10.5 written by steps a-c, 0.5 for the pattern
+    counts, 4.25 per iteration and 4.5 for the codes (18.5 + 4.25 iters)."""
+    B, h, w, k, iters, tau = 16, 2048, 2048, 64, 8, 8.0
+    rgb = torch.from_numpy(synth.images_rgb(synth.BASE_SEED + 7, B, h, w)).to(dev)
+    first = dp.img_compress(rgb, k, iters, tau)
+    d = dp.ImgDesc(height=h, width=w, batch=B, k=k, iters=iters, tau=tau)
+    o = dp.ImgOut(*(first[n].data_ptr() for n in ("y", "cb", "cr", "mean", "act", "dev",
+                                                   "codebook", "code")))
+    ws = first["_workspace"]
+
+    def run():
+        st = dp._lib.img_compress(d, rgb.data_ptr(), o, ws.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+        if st != dp.FFT_OK:
+            raise dp.FftError(st, "img_compress", dp.fft_last_error())
+
+    npx = B * h * w
+    nb = npx // 16
+    item = MultiItem(torch, "img2048_b16_block_compress", run, run,
+                     float(nb * k * 48 * (iters + 1)), (18.5 + 4.25 * iters) * npx,
+                     f"img_compress: {B} RGB images {h}x{w}, k={k}, {iters} Lloyd iterations, "
+                     f"tau={tau}; GFLOP/s counts the codeword distances of every block")
+    item.keep = (rgb, first)
+    return item
+
+
 def build_extras(dp, torch, synth, dev):
     """Comparison entries timed after the c2 step: the c4 precision forms, the
     c5 ragged batch (graph, no graph, one plan per length, one launch per
-    length), the c3 images as complex and as real input, and the fused
-    convolution against its unfused chain."""
+    length), the c3 images as complex and as real input, the fused
+    convolution against its unfused chain, and the image block compression."""
     out = []
     c4, _ = build_c4(dp, torch, synth, dev)
     c5, _ = build_c5(dp, torch, synth, dev)
@@ -304,6 +335,7 @@ def build_extras(dp, torch, synth, dev):
     out.append(build_c5_fair(dp, torch, synth, dev))
     out.append(build_real(dp, torch, synth, dev))
     out.extend(build_conv(dp, torch, synth, dev))
+    out.append(build_img(dp, torch, synth, dev))
     return out
 
 
@@ -410,7 +442,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     builder = {"c1": build_c1, "c2": build_c2, "c3": build_c3, "c4": build_c4, "c5": build_c5}
-    items, cfg = builder[args.config](dp, torch, synth, dev)
+    if args.config == "c5":
+        items, cfg = build_c5(dp, torch, synth, dev, tune=not args.no_tune)
+    else:
+        items, cfg = builder[args.config](dp, torch, synth, dev)
     print(f"# {cfg['workload']}", file=sys.stderr, flush=True)
     if args.config == "c2" and not args.no_extras:
         items += build_extras(dp, torch, synth, dev)

@@ -231,6 +231,64 @@ fft_status_t fft_conv_exec(fft_plan_t plan, const void *in, const void *filter,
 fft_status_t fft_exec_noalloc(fft_plan_t plan, const void *in, void *out, int direction,
                               void *hip_stream);
 
+/*
+ * Image block compression, the paper's second workload (section III-B): a
+ * lossy coder in five steps, named there without formulas (the readings are
+ * the textbook ones):
+ *   (a) luminance and chroma, full-range BT.601 as in JFIF:
+ *         Y = 0.299 R + 0.587 G + 0.114 B,
+ *         Cb = 128 - 0.168736 R - 0.331264 G + 0.5 B,
+ *         Cr = 128 + 0.5 R - 0.418688 G - 0.081312 B;
+ *   (b) chroma at a quarter of the pixels: the mean of each 2x2 square;
+ *   (c) the directional derivative of the luminance along its gradient,
+ *       |grad Y| by central differences with the edge pixels replicated, and
+ *       per 4x4 block its mean (the block's activity), the block's mean
+ *       luminance and its 16 deviations from that mean (raster order);
+ *   (d) a codebook of k deviation vectors: Lloyd's k-means over the blocks of
+ *       activity >= tau ("pattern blocks"), started from the pattern blocks of
+ *       rank floor(c P / k), c = 0..k-1 (P pattern blocks in raster order), a
+ *       codeword without blocks keeping its value, ties to the lower index;
+ *   (e) codes: 0 for a block of activity below tau (its mean alone), else 1 +
+ *       the index of the nearest codeword in squared Euclidean distance.
+ * Every step runs on the GPU, independently per image of the batch.
+ */
+typedef struct {
+  int32_t height, width; /* pixels, positive multiples of 4, at most 2^30 per image */
+  int32_t batch;         /* images, 0..65535 */
+  int32_t k;             /* codewords, 1..256 */
+  int32_t iters;         /* Lloyd iterations, 0..10000 (0: the seeds) */
+  float tau;             /* activity threshold of pattern blocks */
+} img_desc_t;
+
+/* Outputs of img_compress: caller-owned device buffers, per image back to back.
+ *   y        batch x height x width          float32, 4-byte aligned
+ *   cb, cr   batch x height/2 x width/2      float32
+ *   mean,act batch x (height/4) x (width/4)  float32 (blocks in raster order)
+ *   dev      batch x blocks x 16             float32, 16-byte aligned
+ *   codebook batch x k x 16                  float32
+ *   code     batch x blocks                  int32 */
+typedef struct {
+  float *y, *cb, *cr, *mean, *act, *dev, *codebook;
+  int32_t *code;
+} img_out_t;
+
+/* Device workspace img_compress needs for *desc (0 if desc is invalid). */
+size_t img_workspace_bytes(const img_desc_t *desc);
+
+/* Steps (a)-(e) for `batch` RGB images (device pointer, interleaved uint8,
+ * batch x height x width x 3).  workspace: img_workspace_bytes(desc) bytes,
+ * 256-byte aligned, caller-owned.  Asynchronous on hip_stream.  Errors:
+ * FFT_E_INVALID for a bad descriptor, NULL or misaligned buffers (checked
+ * before any launch); FFT_E_UNSUPPORTED for images above 2^30 pixels;
+ * FFT_E_DEVICE for a failed launch. */
+fft_status_t img_compress(const img_desc_t *desc, const uint8_t *rgb, const img_out_t *out,
+                          void *workspace, void *hip_stream);
+
+/* Step (e) alone: codes of the blocks given their deviation vectors (dev,
+ * 16-byte aligned), activities and a codebook (layouts as in img_out_t). */
+fft_status_t img_encode(const img_desc_t *desc, const float *dev, const float *act,
+                        const float *codebook, int32_t *code, void *hip_stream);
+
 /* Release a plan and its device tables.  fft_destroy(NULL) returns FFT_OK.
  * The caller must ensure no execution of the plan is still pending. */
 fft_status_t fft_destroy(fft_plan_t plan);

@@ -28,7 +28,8 @@ PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16_split": 3, "bf16_split": 4,
 #: names of every C entry point declared in include/dpfft.h
 EXPORTS = ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
            "fft_last_error", "fft_plan_describe", "fft_plan_num_steps", "fft_exec_steps",
-           "fft_plan_dry", "fft_autotune", "fft_conv_exec", "fft_exec_noalloc")
+           "fft_plan_dry", "fft_autotune", "fft_conv_exec", "fft_exec_noalloc",
+           "img_workspace_bytes", "img_compress", "img_encode")
 
 
 class FftError(RuntimeError):
@@ -42,6 +43,19 @@ class FftDesc(ctypes.Structure):
                 ("dist", ctypes.c_int64), ("ragged_sizes", ctypes.POINTER(ctypes.c_int64)),
                 ("ragged_offsets", ctypes.POINTER(ctypes.c_int64)),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class ImgDesc(ctypes.Structure):
+    """img_desc_t: images height x width (multiples of 4), batch, codewords k,
+    Lloyd iterations, activity threshold tau."""
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("iters", ctypes.c_int32), ("tau", ctypes.c_float)]
+
+
+class ImgOut(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_void_p), ("cb", ctypes.c_void_p), ("cr", ctypes.c_void_p),
+                ("mean", ctypes.c_void_p), ("act", ctypes.c_void_p), ("dev", ctypes.c_void_p),
+                ("codebook", ctypes.c_void_p), ("code", ctypes.c_void_p)]
 
 
 def _load() -> ctypes.CDLL:
@@ -77,6 +91,12 @@ def _load() -> ctypes.CDLL:
     lib.fft_conv_exec.restype = ctypes.c_int
     lib.fft_exec_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.fft_exec_noalloc.restype = ctypes.c_int
+    lib.img_workspace_bytes.argtypes = [ctypes.POINTER(ImgDesc)]
+    lib.img_workspace_bytes.restype = ctypes.c_size_t
+    lib.img_compress.argtypes = [ctypes.POINTER(ImgDesc), vp, ctypes.POINTER(ImgOut), vp, vp]
+    lib.img_compress.restype = ctypes.c_int
+    lib.img_encode.argtypes = [ctypes.POINTER(ImgDesc), vp, vp, vp, vp, vp]
+    lib.img_encode.restype = ctypes.c_int
     return lib
 
 
@@ -123,6 +143,61 @@ def fft_exec_noalloc(handle: int, in_ptr: int, out_ptr: int, direction: int,
                      stream: int = 0) -> int:
     return _lib.fft_exec_noalloc(ctypes.c_void_p(handle), ctypes.c_void_p(in_ptr),
                                  ctypes.c_void_p(out_ptr), direction, ctypes.c_void_p(stream))
+
+
+def img_workspace_bytes(desc: ImgDesc) -> int:
+    return _lib.img_workspace_bytes(ctypes.byref(desc))
+
+
+def img_compress(rgb: torch.Tensor, k: int, iters: int, tau: float, stream=None) -> dict:
+    """Image block compression of a batch of RGB images (uint8 CUDA tensor of
+    shape (batch, height, width, 3) or (height, width, 3)): returns the
+    outputs of img_compress as tensors y, cb, cr, mean, act, dev, codebook,
+    code."""
+    if rgb.dim() == 3:
+        rgb = rgb.unsqueeze(0)
+    if rgb.dtype != torch.uint8 or rgb.device.type != "cuda" or not rgb.is_contiguous() or \
+            rgb.dim() != 4 or rgb.shape[-1] != 3:
+        raise ValueError("rgb must be a contiguous uint8 CUDA tensor (batch, height, width, 3)")
+    B, h, w = (int(v) for v in rgb.shape[:3])
+    d = ImgDesc(height=h, width=w, batch=B, k=int(k), iters=int(iters), tau=float(tau))
+    dev = rgb.device
+    f32 = dict(dtype=torch.float32, device=dev)
+    nb = (h // 4) * (w // 4)
+    res = {"y": torch.empty((B, h, w), **f32), "cb": torch.empty((B, h // 2, w // 2), **f32),
+           "cr": torch.empty((B, h // 2, w // 2), **f32),
+           "mean": torch.empty((B, h // 4, w // 4), **f32),
+           "act": torch.empty((B, h // 4, w // 4), **f32), "dev": torch.empty((B, nb, 16), **f32),
+           "codebook": torch.empty((B, int(k), 16), **f32),
+           "code": torch.empty((B, nb), dtype=torch.int32, device=dev)}
+    o = ImgOut(*(res[n].data_ptr() for n in ("y", "cb", "cr", "mean", "act", "dev", "codebook",
+                                             "code")))
+    wsb = _lib.img_workspace_bytes(ctypes.byref(d))
+    ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)
+    st = _lib.img_compress(ctypes.byref(d), ctypes.c_void_p(rgb.data_ptr()), ctypes.byref(o),
+                           ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(_stream_handle(stream)))
+    if st != FFT_OK:
+        raise FftError(st, "img_compress", fft_last_error())
+    res["_workspace"] = ws
+    return res
+
+
+def img_encode(dev: torch.Tensor, act: torch.Tensor, codebook: torch.Tensor, height: int,
+               width: int, tau: float, stream=None) -> torch.Tensor:
+    """Step (e) alone: codes (int32, (batch, blocks)) of deviation vectors
+    (batch, blocks, 16), activities (batch, blocks) and codebooks (batch, k, 16)."""
+    B, k = int(codebook.shape[0]), int(codebook.shape[1])
+    for t in (dev, act, codebook):
+        if t.dtype != torch.float32 or t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError("dev, act and codebook must be contiguous float32 CUDA tensors")
+    d = ImgDesc(height=int(height), width=int(width), batch=B, k=k, iters=0, tau=float(tau))
+    code = torch.empty((B, (height // 4) * (width // 4)), dtype=torch.int32, device=dev.device)
+    st = _lib.img_encode(ctypes.byref(d), ctypes.c_void_p(dev.data_ptr()),
+                         ctypes.c_void_p(act.data_ptr()), ctypes.c_void_p(codebook.data_ptr()),
+                         ctypes.c_void_p(code.data_ptr()), ctypes.c_void_p(_stream_handle(stream)))
+    if st != FFT_OK:
+        raise FftError(st, "img_encode", fft_last_error())
+    return code
 
 
 def fft_plan_num_steps(handle: Optional[int]) -> int:

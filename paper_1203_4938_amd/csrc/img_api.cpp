@@ -1,0 +1,142 @@
+// C ABI of the image block compression (section III-B): validation,
+// workspace layout and the launch sequence.
+#include <math.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/dpfft.h"
+#include "img.h"
+#include "internal.h"
+
+using namespace dpfft;
+
+namespace {
+
+struct WsLayout {
+  size_t wgcount = 0, npat = 0, part = 0, total = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int64_t groups_of(const img_desc_t *d) {
+  const int64_t nb = (int64_t)(d->height / 4) * (d->width / 4);
+  return (nb + kImgBlocksPerGroup - 1) / kImgBlocksPerGroup;
+}
+
+WsLayout layout(const img_desc_t *d) {
+  WsLayout L;
+  const int64_t g = groups_of(d), B = d->batch;
+  L.wgcount = 0;
+  L.npat = align256(L.wgcount + sizeof(int32_t) * B * g);
+  L.part = align256(L.npat + sizeof(int32_t) * B);
+  L.total = align256(L.part + sizeof(float) * B * g * d->k * 17);
+  return L;
+}
+
+fft_status_t check_desc(const img_desc_t *d) {
+  if (!d) return fail(FFT_E_INVALID, "desc is NULL");
+  if (d->height <= 0 || d->width <= 0 || (d->height % 4) || (d->width % 4))
+    return fail(FFT_E_INVALID, "image sides must be positive multiples of 4");
+  if ((int64_t)d->height * d->width > (int64_t(1) << 30))
+    return fail(FFT_E_UNSUPPORTED, "images above 2^30 pixels");
+  if (d->batch < 0 || d->batch > 65535) return fail(FFT_E_INVALID, "batch must be in [0, 65535]");
+  if (d->k < 1 || d->k > kImgMaxK) return fail(FFT_E_INVALID, "k must be in [1, 256]");
+  if (d->iters < 0 || d->iters > 10000) return fail(FFT_E_INVALID, "iters must be in [0, 10000]");
+  if (!isfinite(d->tau)) return fail(FFT_E_INVALID, "tau must be finite");
+  return FFT_OK;
+}
+
+bool misaligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) != 0; }
+
+ImgArgs args_of(const img_desc_t *d) {
+  ImgArgs a{};
+  a.h = d->height;
+  a.w = d->width;
+  a.nb = (a.h / 4) * (a.w / 4);
+  a.groups = (int32_t)groups_of(d);
+  a.k = d->k;
+  a.tau = d->tau;
+  return a;
+}
+
+hipError_t launch(const void *fn, dim3 grid, int threads, ImgArgs &a, hipStream_t s) {
+  void *kargs[] = {(void *)&a};
+  return hipLaunchKernel(fn, grid, dim3(threads), kargs, 0, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t img_workspace_bytes(const img_desc_t *desc) {
+  if (check_desc(desc) != FFT_OK) return 0;
+  return layout(desc).total;
+}
+
+fft_status_t img_compress(const img_desc_t *desc, const uint8_t *rgb, const img_out_t *out,
+                          void *workspace, void *hip_stream) {
+  fft_status_t st = check_desc(desc);
+  if (st != FFT_OK) return st;
+  if (!out) return fail(FFT_E_INVALID, "out is NULL");
+  if (desc->batch == 0) return FFT_OK;
+  if (!rgb || !out->y || !out->cb || !out->cr || !out->mean || !out->act || !out->dev ||
+      !out->codebook || !out->code || !workspace)
+    return fail(FFT_E_INVALID, "a buffer is NULL");
+  if (misaligned(out->y, 4) || misaligned(out->cb, 4) || misaligned(out->cr, 4) ||
+      misaligned(out->mean, 4) || misaligned(out->act, 4) || misaligned(out->dev, 16) ||
+      misaligned(out->codebook, 4) || misaligned(out->code, 4) || misaligned(workspace, 256))
+    return fail(FFT_E_INVALID, "misaligned buffer (dev 16 bytes, workspace 256, others 4)");
+  const WsLayout L = layout(desc);
+  ImgArgs a = args_of(desc);
+  a.rgb = rgb;
+  a.y = out->y;
+  a.cb = out->cb;
+  a.cr = out->cr;
+  a.mean = out->mean;
+  a.act = out->act;
+  a.dev = out->dev;
+  a.codebook = out->codebook;
+  a.code = out->code;
+  char *ws = (char *)workspace;
+  a.wgcount = (int32_t *)(ws + L.wgcount);
+  a.npat = (int32_t *)(ws + L.npat);
+  a.part = (float *)(ws + L.part);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const unsigned B = (unsigned)desc->batch;
+  const int64_t tiles = ((a.w + kImgTileW - 1) / kImgTileW) * ((a.h + kImgTileH - 1) / kImgTileH);
+  const dim3 gb((unsigned)a.groups, B);
+  hipError_t e = launch(img_kernel_front(), dim3((unsigned)tiles, B), kImgThreads, a, s);
+  if (e == hipSuccess) e = launch(img_kernel_count(), gb, kImgBlocksPerGroup, a, s);
+  if (e == hipSuccess) e = launch(img_kernel_scan(), dim3(B), 256, a, s);
+  if (e == hipSuccess) e = launch(img_kernel_seed(), gb, kImgBlocksPerGroup, a, s);
+  const dim3 gu((unsigned)((a.k * 16 + 255) / 256), B);
+  for (int it = 0; it < desc->iters && e == hipSuccess; ++it) {
+    e = launch(img_kernel_assign(true), gb, kImgBlocksPerGroup, a, s);
+    if (e == hipSuccess) e = launch(img_kernel_update(), gu, 256, a, s);
+  }
+  if (e == hipSuccess) e = launch(img_kernel_assign(false), gb, kImgBlocksPerGroup, a, s);
+  if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return FFT_OK;
+}
+
+fft_status_t img_encode(const img_desc_t *desc, const float *dev, const float *act,
+                        const float *codebook, int32_t *code, void *hip_stream) {
+  fft_status_t st = check_desc(desc);
+  if (st != FFT_OK) return st;
+  if (desc->batch == 0) return FFT_OK;
+  if (!dev || !act || !codebook || !code) return fail(FFT_E_INVALID, "a buffer is NULL");
+  if (misaligned(dev, 16) || misaligned(act, 4) || misaligned(codebook, 4) || misaligned(code, 4))
+    return fail(FFT_E_INVALID, "misaligned buffer (dev 16 bytes, others 4)");
+  ImgArgs a = args_of(desc);
+  a.dev = const_cast<float *>(dev);
+  a.act = const_cast<float *>(act);
+  a.codebook = const_cast<float *>(codebook);
+  a.code = code;
+  const hipError_t e = launch(img_kernel_assign(false), dim3((unsigned)a.groups, (unsigned)desc->batch),
+                              kImgBlocksPerGroup, a, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return FFT_OK;
+}
+
+}  // extern "C"

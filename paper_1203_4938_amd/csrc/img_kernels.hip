@@ -1,0 +1,268 @@
+// Image block compression (section III-B of the paper), five steps:
+//   (a) RGB -> luminance Y and chroma Cb, Cr (full-range BT.601 as in JFIF)
+//   (b) chroma at a quarter of the pixels (means of 2x2 squares)
+//   (c) |grad Y| (central differences, edges replicated) and per 4x4 block
+//       its mean (activity), the mean luminance and the 16 deviations
+//   (d) k-means codebook of the deviation vectors of blocks with activity
+//       >= tau (Lloyd's iteration from the pattern blocks of rank
+//       floor(c P / k))
+//   (e) per block: code 0 (mean only) or 1 + the nearest codeword.
+// The paper runs (a)-(c) and (e) as data-parallel programs and (d) on the
+// host; here every step is a kernel, so a batch of images is one sequence of
+// launches on one stream with no host round trip.
+//
+// (a)-(c) are one pass over the pixels (k_img_front): a 64 x 16 pixel tile
+// computes Y for itself and a one-pixel halo into LDS, writes Y and the
+// quarter-size chroma, then each of its 64 blocks reduces its 16 pixels.
+// The k-means and the encoding walk the blocks in groups of 256, one block
+// per thread, the codebook in LDS; the cluster sums of a group go through
+// LDS atomics into per-group partials that k_img_update adds up in a fixed
+// order.
+#include "fft_common.h"
+#include "img.h"
+
+namespace dpfft {
+
+namespace {
+
+__device__ __forceinline__ float luma(float r, float g, float b) {
+  return 0.299f * r + 0.587f * g + 0.114f * b;
+}
+__device__ __forceinline__ float chroma_b(float r, float g, float b) {
+  return 128.0f - 0.168736f * r - 0.331264f * g + 0.5f * b;
+}
+__device__ __forceinline__ float chroma_r(float r, float g, float b) {
+  return 128.0f + 0.5f * r - 0.418688f * g - 0.081312f * b;
+}
+
+constexpr int HW = kImgTileW + 2, HH = kImgTileH + 2;  // tile with its halo
+
+}  // namespace
+
+__global__ void __launch_bounds__(kImgThreads) k_img_front(ImgArgs a) {
+  __shared__ float ys[HH * HW];
+  const int64_t img = blockIdx.y;
+  const int64_t tiles_x = (a.w + kImgTileW - 1) / kImgTileW;
+  const int64_t tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int64_t x0 = tx * kImgTileW, y0 = ty * kImgTileH;
+  const uint8_t *rgb = a.rgb + img * a.h * a.w * 3;
+  float *Y = a.y + img * a.h * a.w;
+  const int tid = threadIdx.x;
+
+  // (a) luminance of the tile and its halo (coordinates clamped to the image:
+  // the replicated edge of the central differences)
+  for (int i = tid; i < HH * HW; i += kImgThreads) {
+    const int ly = i / HW, lx = i % HW;
+    int64_t gy = y0 + ly - 1, gx = x0 + lx - 1;
+    const bool inside = gy >= y0 && gy < y0 + kImgTileH && gx >= x0 && gx < x0 + kImgTileW &&
+                        gy < a.h && gx < a.w;
+    gy = gy < 0 ? 0 : (gy >= a.h ? a.h - 1 : gy);
+    gx = gx < 0 ? 0 : (gx >= a.w ? a.w - 1 : gx);
+    const uint8_t *p = rgb + (gy * a.w + gx) * 3;
+    const float v = luma((float)p[0], (float)p[1], (float)p[2]);
+    ys[i] = v;
+    if (inside) Y[gy * a.w + gx] = v;
+  }
+  // (b) chroma: one 2x2 square per thread
+  {
+    const int sy = tid / (kImgTileW / 2), sx = tid % (kImgTileW / 2);
+    const int64_t py = y0 + 2 * sy, px = x0 + 2 * sx;
+    if (sy < kImgTileH / 2 && py < a.h && px < a.w) {
+      float sb = 0.f, sr = 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint8_t *p = rgb + ((py + (q >> 1)) * a.w + px + (q & 1)) * 3;
+        const float r = p[0], g = p[1], b = p[2];
+        sb += chroma_b(r, g, b);
+        sr += chroma_r(r, g, b);
+      }
+      const int64_t w2 = a.w / 2, o = img * (a.h / 2) * w2 + (py / 2) * w2 + px / 2;
+      a.cb[o] = 0.25f * sb;
+      a.cr[o] = 0.25f * sr;
+    }
+  }
+  __syncthreads();
+  // (c) blocks: one per thread for the first 64 threads
+  if (tid < (kImgTileW / 4) * (kImgTileH / 4)) {
+    const int by = tid / (kImgTileW / 4), bx = tid % (kImgTileW / 4);
+    const int64_t gby = y0 / 4 + by, gbx = x0 / 4 + bx;
+    const int64_t bw = a.w / 4;
+    if (gby < a.h / 4 && gbx < bw) {
+      float v[16], s = 0.f, g = 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ly = 4 * by + i + 1, lx = 4 * bx + j + 1;
+          const float c = ys[ly * HW + lx];
+          const float gx = 0.5f * (ys[ly * HW + lx + 1] - ys[ly * HW + lx - 1]);
+          const float gyv = 0.5f * (ys[(ly + 1) * HW + lx] - ys[(ly - 1) * HW + lx]);
+          g += __builtin_sqrtf(gx * gx + gyv * gyv);
+          s += c;
+          v[4 * i + j] = c;
+        }
+      const float m = s * (1.0f / 16.0f);
+      const int64_t b = img * a.nb + gby * bw + gbx;
+      a.mean[b] = m;
+      a.act[b] = g * (1.0f / 16.0f);
+      float4 *d = reinterpret_cast<float4 *>(a.dev + 16 * b);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        d[q] = make_float4(v[4 * q] - m, v[4 * q + 1] - m, v[4 * q + 2] - m, v[4 * q + 3] - m);
+    }
+  }
+}
+
+// (d) pattern blocks per group of 256 blocks
+__global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_count(ImgArgs a) {
+  __shared__ int cnt;
+  const int64_t img = blockIdx.y;
+  const int64_t b = (int64_t)blockIdx.x * kImgBlocksPerGroup + threadIdx.x;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const bool pat = b < a.nb && a.act[img * a.nb + b] >= a.tau;
+  if (pat) atomicAdd(&cnt, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) a.wgcount[img * a.groups + blockIdx.x] = cnt;
+}
+
+// Exclusive offsets of the groups' pattern blocks (one workgroup per image,
+// sequential over chunks of 256 groups), the pattern count, and a zero
+// codebook (codewords with no seed stay zero when no block is a pattern).
+__global__ void __launch_bounds__(256) k_img_scan(ImgArgs a) {
+  __shared__ int s[256];
+  __shared__ int carry;
+  const int64_t img = blockIdx.x;
+  int32_t *wc = a.wgcount + img * a.groups;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < a.groups; base += 256) {
+    const int i = base + threadIdx.x;
+    const int v = i < a.groups ? wc[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d *= 2) {  // inclusive scan (Hillis-Steele)
+      const int t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < a.groups) wc[i] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry += s[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.npat[img] = carry;
+  for (int i = threadIdx.x; i < a.k * 16; i += 256) a.codebook[img * a.k * 16 + i] = 0.f;
+}
+
+// Seeds: codeword c takes the deviation vector of the pattern block of rank
+// floor(c P / k); a block of rank r seeds every c with that floor.
+__global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_seed(ImgArgs a) {
+  __shared__ int s[kImgBlocksPerGroup];
+  const int64_t img = blockIdx.y;
+  const int64_t b = (int64_t)blockIdx.x * kImgBlocksPerGroup + threadIdx.x;
+  const bool pat = b < a.nb && a.act[img * a.nb + b] >= a.tau;
+  s[threadIdx.x] = pat;
+  __syncthreads();
+  for (int d = 1; d < kImgBlocksPerGroup; d *= 2) {
+    const int t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (!pat) return;
+  const int64_t P = a.npat[img];
+  const int64_t rank = a.wgcount[img * a.groups + blockIdx.x] + s[threadIdx.x] - 1;
+  const int64_t k = a.k;
+  const int64_t c_lo = (rank * k + P - 1) / P, c_hi = ((rank + 1) * k + P - 1) / P;
+  const float *src = a.dev + 16 * (img * a.nb + b);
+  for (int64_t c = c_lo; c < c_hi && c < k; ++c)
+    for (int t = 0; t < 16; ++t) a.codebook[(img * k + c) * 16 + t] = src[t];
+}
+
+// Nearest codeword of every pattern block (ties to the lower index).
+// ACC: add the block to its cluster's sums (LDS atomics, then one partial
+// per group); otherwise write the codes of every block.
+template <bool ACC>
+__global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
+  __shared__ float cbk[kImgMaxK * 16];
+  __shared__ float acc[ACC ? kImgMaxK * 17 : 1];
+  const int64_t img = blockIdx.y;
+  const int k = a.k;
+  const float *gcb = a.codebook + img * (int64_t)k * 16;
+  for (int i = threadIdx.x; i < k * 16; i += kImgBlocksPerGroup) cbk[i] = gcb[i];
+  if constexpr (ACC)
+    for (int i = threadIdx.x; i < k * 17; i += kImgBlocksPerGroup) acc[i] = 0.f;
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * kImgBlocksPerGroup + threadIdx.x;
+  const int64_t gb = img * a.nb + b;
+  const bool in = b < a.nb;
+  const bool pat = in && a.act[gb] >= a.tau;
+  float v[16];
+  int best = 0;
+  if (pat) {
+    const float4 *d = reinterpret_cast<const float4 *>(a.dev + 16 * gb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 f = d[q];
+      v[4 * q] = f.x;
+      v[4 * q + 1] = f.y;
+      v[4 * q + 2] = f.z;
+      v[4 * q + 3] = f.w;
+    }
+    float bd = 3.4e38f;
+    for (int c = 0; c < k; ++c) {
+      float dist = 0.f;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const float e = v[t] - cbk[16 * c + t];
+        dist = __builtin_fmaf(e, e, dist);
+      }
+      if (dist < bd) {
+        bd = dist;
+        best = c;
+      }
+    }
+  }
+  if constexpr (ACC) {
+    if (pat) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) atomicAdd(&acc[17 * best + t], v[t]);
+      atomicAdd(&acc[17 * best + 16], 1.0f);
+    }
+    __syncthreads();
+    float *part = a.part + (img * a.groups + blockIdx.x) * (int64_t)k * 17;
+    for (int i = threadIdx.x; i < k * 17; i += kImgBlocksPerGroup) part[i] = acc[i];
+  } else {
+    if (in) a.code[gb] = pat ? best + 1 : 0;
+  }
+}
+
+// New codewords: the groups' partial sums added in group order; a codeword
+// without blocks keeps its value.  Thread t of image blockIdx.y handles
+// (codeword t / 16, component t % 16).
+__global__ void __launch_bounds__(256) k_img_update(ImgArgs a) {
+  const int64_t img = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.k * 16) return;
+  const int c = i / 16, t = i % 16;
+  const float *part = a.part + img * a.groups * (int64_t)a.k * 17;
+  float s = 0.f, n = 0.f;
+  for (int g = 0; g < a.groups; ++g) {
+    s += part[(int64_t)g * a.k * 17 + 17 * c + t];
+    n += part[(int64_t)g * a.k * 17 + 17 * c + 16];
+  }
+  if (n > 0.f) a.codebook[img * (int64_t)a.k * 16 + i] = s / n;
+}
+
+const void *img_kernel_front() { return (const void *)&k_img_front; }
+const void *img_kernel_count() { return (const void *)&k_img_count; }
+const void *img_kernel_scan() { return (const void *)&k_img_scan; }
+const void *img_kernel_seed() { return (const void *)&k_img_seed; }
+const void *img_kernel_assign(bool accumulate) {
+  return accumulate ? (const void *)&k_img_assign<true> : (const void *)&k_img_assign<false>;
+}
+const void *img_kernel_update() { return (const void *)&k_img_update; }
+
+}  // namespace dpfft

@@ -185,7 +185,7 @@ def smooth_noise_image(seed: int, index: int, h: int = 2048, w: int = 2048,
     Counters: lattice point (a, b) uses ``index*2**40 + a*(gw) + b``; the noise
     of pixel (y, x) uses ``index*2**40 + 2**32 + y*w + x``.
     """
-    gh, gw = h // cell + 1, w // cell + 1
+    gh, gw = (h + cell - 1) // cell + 1, (w + cell - 1) // cell + 1
     base = np.uint64(index) << np.uint64(40)
     lat_c = base + np.arange(gh * gw, dtype=np.uint64)
     lat = (splitmix64_np(seed, lat_c) >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
@@ -215,6 +215,38 @@ def images_complex(seed: int, count: int, h: int = 2048, w: int = 2048,
     for i in range(count):
         out[i].real = smooth_noise_image(seed, first + i, h, w)
     return out
+
+
+def images_rgb(seed: int, count: int, h: int = 2048, w: int = 2048, first: int = 0) -> np.ndarray:
+    """Colour images ``first..first+count-1``: three smooth-noise channels per
+    image (channel ch of image i is the greyscale image 3 i + ch of the stream),
+    uint8 of shape ``(count, h, w, 3)``."""
+    out = np.empty((count, h, w, 3), dtype=np.uint8)
+    for i in range(count):
+        for ch in range(3):
+            out[i, :, :, ch] = smooth_noise_image(seed, 3 * (first + i) + ch, h, w)
+    return out
+
+
+def pattern_set(seed: int, k: int) -> np.ndarray:
+    """``k`` random 4x4 integer patterns, values uniform in [28, 228), uint8
+    of shape ``(k, 4, 4)``."""
+    z = splitmix64_np(seed, np.arange(k * 16, dtype=np.uint64))
+    return (28 + (z >> np.uint64(40)) % np.uint64(200)).astype(np.uint8).reshape(k, 4, 4)
+
+
+def pattern_picks(seed: int, n: int, k: int) -> np.ndarray:
+    """``n`` uniform draws from ``range(k)`` (int64)."""
+    z = splitmix64_np(seed, np.arange(n, dtype=np.uint64))
+    return ((z >> np.uint64(40)) % np.uint64(k)).astype(np.int64)
+
+
+def blocks_to_grey_rgb(pats: np.ndarray, pick: np.ndarray) -> np.ndarray:
+    """Grey RGB images (R = G = B) whose 4x4 block (r, c) of image i is
+    ``pats[pick[i, r, c]]``; ``pick`` has shape ``(count, h/4, w/4)``."""
+    count, bh, bw = pick.shape
+    grey = pats[pick].transpose(0, 1, 3, 2, 4).reshape(count, 4 * bh, 4 * bw)
+    return np.ascontiguousarray(np.repeat(grey[..., None], 3, axis=3))
 
 
 # --------------------------------------------------------------------------

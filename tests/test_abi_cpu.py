@@ -20,13 +20,14 @@ def _dp():
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:fft_status_t|size_t|int|const char \*)\s*(fft_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:fft_status_t|size_t|int|const char \*)\s*((?:fft|img)_\w+)\s*\(",
                                  text, re.M)))
 
 
 def test_header_declares_the_entry_points():
     names = _declared()
-    for n in ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str"):
+    for n in ("fft_plan", "fft_exec", "fft_destroy", "fft_workspace_bytes", "fft_status_str",
+              "fft_conv_exec", "img_compress", "img_encode", "img_workspace_bytes"):
         assert n in names
 
 
@@ -106,3 +107,17 @@ def test_valid_plans_reach_the_device_step(kw):
     st, msg = _plan_status(**kw)
     assert st == 4, msg  # FFT_E_DEVICE: the first device call, after every host check
     assert "hipMalloc" in msg
+
+
+def test_img_descriptors_rejected_before_device():
+    dp = _dp()
+    ok = dict(height=64, width=64, batch=2, k=16, iters=3, tau=1.0)
+    assert dp.img_workspace_bytes(dp.ImgDesc(**ok)) > 0
+    for bad in (dict(height=62), dict(width=0), dict(batch=-1), dict(k=0), dict(k=257),
+                dict(iters=-1), dict(tau=float("nan"))):
+        d = dp.ImgDesc(**{**ok, **bad})
+        assert dp.img_workspace_bytes(d) == 0
+        assert dp._lib.img_compress(ctypes.byref(d), None, None, None, None) == dp.FFT_E_INVALID
+    d = dp.ImgDesc(**ok)
+    assert dp._lib.img_compress(ctypes.byref(d), None, None, None, None) == dp.FFT_E_INVALID
+    assert dp._lib.img_encode(ctypes.byref(d), None, None, None, None, None) == dp.FFT_E_INVALID
