@@ -410,7 +410,7 @@ std::unique_ptr<LineStep> make_line(dpfft_plan_s *P, const char *name, int L, in
   if (!choose_line(L, map, omap, tw4, cmax, step, lines_total, ov, &s->k)) return nullptr;
   s->L = L;
   s->name = name;
-  s->tw_off = P->tables.add(stockham_table_pow2(L, s->k.ept));
+  s->tw_off = P->tables.add(stockham_table_pow2(L / s->k.sub, s->k.ept));
   s->a.scale = 1.0f;
   // two-level table of w_L (pass twiddles rebuilt in LDS by the kernels whose
   // LDS holds no per-pass table)

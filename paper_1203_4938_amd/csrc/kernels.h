@@ -91,6 +91,8 @@ struct KernelInfo {
   bool persistent = false;  // loops over tiles; launch at most one grid of resident workgroups
   bool preferred = false;   // the planner's default for its shape (measured fastest)
   int ept = 16;             // elements per thread (sets the radix plan of the pass table)
+  int sub = 1;              // sub-lines per line: 2 for the split-first instances, whose
+                            // pass table is that of L / 2
 };
 
 // Power-of-two line kernels have compile-time length L and C lines per

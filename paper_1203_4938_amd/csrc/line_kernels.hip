@@ -304,6 +304,162 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 }
 
 // ---------------------------------------------------------------------------
+// Two sub-lines per line.  One radix-2 step in frequency (decimation in
+// frequency) splits a line of L points into a[n] = x[n] + x[n + L/2] and
+// b[n] = (x[n] - x[n + L/2]) w_L^n, n < L/2, whose L/2-point transforms are
+// the even and the odd outputs: X[2k] = A[k], X[2k + 1] = B[k].  The two
+// sub-lines then go through the Stockham passes one after the other, sharing
+// an LDS buffer of half a tile.  A tile of 8 lines of 2048 points needs
+// 76 KB of LDS instead of 152 KB, so two workgroups share a CU and overlap
+// each other's loads, barriers and butterflies, while every row piece the
+// tile reads or writes stays C x 8 bytes wide; the first sub-line's stores
+// drain while the second one is transformed.  Thread j of a line holds
+// elements j + T m (m < 32, T = L/32): the pairs (m, m + 16) are the split's
+// operands, and w_L^{j + T m} = w_L^j w_32^m.
+// ---------------------------------------------------------------------------
+template <int L, int C, int MAP, int OMAP>
+constexpr int half_tw_entries() {
+  using PT = PlainTw<L / 2, C, MAP, OMAP, 16, C * (L / 32)>;
+  return PT::MODE == 1 ? PT::NTW : 0;
+}
+template <int M>
+__device__ __forceinline__ void half_split_one(cf &x, cf &y, cf wj) {
+  const cf s = make_float2(x.x + y.x, x.y + y.y);
+  const cf d = make_float2(x.x - y.x, x.y - y.y);
+  x = s;
+  y = cmul(mulw32<32, M>(d), wj);
+}
+template <int... M>
+__device__ __forceinline__ void half_split(cf (&va)[16], cf (&vb)[16], cf wj,
+                                           std::integer_sequence<int, M...>) {
+  (half_split_one<M>(va[M], vb[M], wj), ...);
+}
+
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int NT>
+__global__ void __launch_bounds__(C * (L / 32)) __attribute__((amdgpu_waves_per_eu(4)))
+    k_lines_half(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
+  constexpr int H = L / 2;
+  using G = P2<H, 16>;
+  constexpr int E = G::E, T = G::T, NTH = C * T;
+  static_assert(E == 16 && T * 32 == L, "16 elements of each sub-line per thread");
+  static_assert(NTH <= 1024, "a workgroup holds at most 1024 threads");
+  using LO = Lds<H, C, OMAP, kPadShift>;
+  constexpr int NP = lds_pairs<H, C, MAP, OMAP>();
+  __shared__ __align__(16) cf lds[NP > 0 ? NP : 1];
+
+  const int tid = threadIdx.x;
+  int c, j;
+  lane_map<H, 16, C, MAP>(tid, c, j);
+  const uint32_t tile = !(a.flags & F_REMAP)  ? blockIdx.x
+                        : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x)
+                                               : xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t bb = tile / a.tiles_per_batch;
+  const int64_t line0 = (int64_t)(tile - bb * a.tiles_per_batch) * C;
+  const int64_t line = line0 + c;
+  const bool valid = line < a.lines;
+
+  cf va[E], vb[E];
+  if (valid) {
+    if constexpr (MAP == ELEM_FAST) {
+      const cf *src = in + bb * a.in_b + line * a.in_l + j;
+#pragma unroll
+      for (int m = 0; m < E; ++m) va[m] = ld_data<NT>(src + T * m);
+#pragma unroll
+      for (int m = 0; m < E; ++m) vb[m] = ld_data<NT>(src + H + T * m);
+    } else {
+      const cf *tin = in + bb * a.in_b + line0;
+      const uint32_t es = (uint32_t)a.in_e;
+      const uint32_t o = (uint32_t)c + (uint32_t)j * es;
+#pragma unroll
+      for (int m = 0; m < E; ++m) va[m] = ldg<NT>(tin, o + (uint32_t)(T * m) * es);
+#pragma unroll
+      for (int m = 0; m < E; ++m) vb[m] = ldg<NT>(tin, o + (uint32_t)(H + T * m) * es);
+    }
+    if constexpr (SW & 1) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) va[m] = cswap(va[m]), vb[m] = cswap(vb[m]);
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) va[m] = vb[m] = make_float2(0.0f, 0.0f);
+  }
+
+  // w_L^j from the two-level table of w_L (j < T <= 2^S: a lo entry alone)
+  constexpr int S = tw2_shift(P2<L>::LG);
+  cf wj;
+  if constexpr (T <= (1 << S)) {
+    wj = a.tw2[j];
+  } else {
+    wj = cmul(a.tw2[(1 << S) + (j >> S)], a.tw2[j & ((1 << S) - 1)]);
+  }
+
+  // pass twiddles: the sub-line's per-pass table, in LDS where it fits next
+  // to the half tile for two workgroups per CU, else read from global memory
+  using PT = PlainTw<H, C, MAP, OMAP, 16, NTH>;
+  constexpr int NTW = half_tw_entries<L, C, MAP, OMAP>();
+  __shared__ cf twl[NTW > 0 ? NTW : 1];
+  if constexpr (NTW > 0) PT::fill(twl, a, tid);
+  using TWS = std::conditional_t<(NTW > 0), TwLdsTable, TwTable>;
+  TWS tws;
+  if constexpr (NTW > 0) {
+    tws = TwLdsTable{twl};
+  } else {
+    tws = TwTable{a.tw};
+  }
+
+  half_split(va, vb, wj, std::make_integer_sequence<int, E>{});
+
+  int c2 = c, j2 = j;
+  if constexpr (OMAP != MAP) lane_map<H, 16, C, OMAP>(tid, c2, j2);
+  const int64_t line2 = line0 + c2;
+  // outputs of sub-line s: element j + T m holds X[2 (j + T m) + s]
+  auto finish = [&](cf(&v)[E], const int s) {
+    if constexpr (TW4) {
+      const uint32_t n2 = valid ? (uint32_t)line : 0u;
+      const uint32_t msk = (1u << a.tw4_shift) - 1u;
+      const uint32_t eA = n2 * (uint32_t)(2 * j + s), eB = n2 * (uint32_t)(2 * T);
+      const cf A = cmul(a.tw4_hi[eA >> a.tw4_shift], a.tw4_lo[eA & msk]);
+      const cf B = cmul(a.tw4_hi[eB >> a.tw4_shift], a.tw4_lo[eB & msk]);
+      tw4_apply_ab<E>(v, A, B);
+    }
+    if constexpr (SW & 2) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cscale(v[m], a.scale);
+    }
+    if constexpr (OMAP != MAP) {
+      // re-tile through LDS; the barrier after the reads frees the buffer
+      // for the next sub-line
+      auto wpos = [&](int m) { return LO::idx_off(c, j, T * m); };
+      auto rpos = [&](int m) { return LO::idx_off(c2, j2, T * m); };
+      lds_exchange<E, true>(v, lds, wpos, rpos);
+    }
+    if (line2 < a.lines) {
+      if constexpr (SW & 2) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = cswap(v[m]);
+      }
+      if constexpr (OMAP == ELEM_FAST) {
+        cf *dst = out + bb * a.out_b + line2 * a.out_l + 2 * j2 + s;
+#pragma unroll
+        for (int m = 0; m < E; ++m) st_data<NT>(dst + 2 * T * m, v[m]);
+      } else {
+        cf *tout = out + bb * a.out_b + line0;
+        const uint32_t es = (uint32_t)a.out_e;
+        const uint32_t o = (uint32_t)c2 + (uint32_t)(2 * j2 + s) * es;
+#pragma unroll
+        for (int m = 0; m < E; ++m) stg<NT>(tout, o + (uint32_t)(2 * T * m) * es, v[m]);
+      }
+    }
+  };
+  // The last exchange of a sub-line's passes ends with a barrier after its
+  // reads, and so does the re-tiling, so the next sub-line may write LDS.
+  all_passes<H, 16, C, MAP>(va, lds, tws, c, j, std::make_integer_sequence<int, G::NP>{});
+  finish(va, 0);
+  all_passes<H, 16, C, MAP>(vb, lds, tws, c, j, std::make_integer_sequence<int, G::NP>{});
+  finish(vb, 1);
+}
+
+// ---------------------------------------------------------------------------
 // registry of compiled instances
 // ---------------------------------------------------------------------------
 struct LineEntry {
@@ -315,6 +471,7 @@ struct LineEntry {
   bool pf;
   bool pref;          // the planner's default for its shape (measured fastest)
   int ept;
+  int sub = 1;        // sub-lines per line (2: k_lines_half)
 };
 
 #define KL(L_, C_, M_, O_, TW_, SW_) (const void *)&KFN<L_, C_, M_, O_, TW_, SW_, KEPT, KNT>
@@ -455,6 +612,44 @@ static const LineEntry kLineTablePf32x[] = {
 #undef KEPT
 #undef KNT
 
+// Split-first instances (k_lines_half): half the LDS of the plain tile, two
+// workgroups per CU.  The 1024-point column tiles of 16 are the default of
+// their shape (2D 1024 x 1024 column pass 11% faster than the persistent
+// 32-element tiles); the transposed rows of 1024 measured as fast as their
+// default and are opt-in.  Measured and not kept: tiles of 2048 (column
+// tiles with and without the four-step twiddle, transposed rows: 1-4%
+// slower, and 33% where the four-step twiddle spills registers at the
+// 128-VGPR budget of two workgroups per CU), 4096-point tiles of 4 (spills,
+// 35-70% slower) and the 1024-point four-step column tiles (5% slower than
+// the persistent ones).
+#define KH(L_, C_, M_, O_, TW_, SW_) (const void *)&k_lines_half<L_, C_, M_, O_, TW_, SW_, 0>
+#define HENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                        \
+  LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * (L_ / 32),                          \
+            (int)sizeof(cf) * lds_pairs<L_ / 2, C_, M_, O_>() +                              \
+                (int)sizeof(cf) * half_tw_entries<L_, C_, M_, O_>(),                          \
+            false, KPREF, 16, 2}
+#define HCOL(L_, C_)                                                                       \
+  HENTRY(L_, C_, LINE_FAST, LINE_FAST, false, KH(L_, C_, LINE_FAST, LINE_FAST, false, 0), \
+         nullptr, KH(L_, C_, LINE_FAST, LINE_FAST, false, 2),                               \
+         KH(L_, C_, LINE_FAST, LINE_FAST, false, 3))
+#define HROWT(L_, C_)                                                                      \
+  HENTRY(L_, C_, ELEM_FAST, LINE_FAST, false, KH(L_, C_, ELEM_FAST, LINE_FAST, false, 0), \
+         nullptr, KH(L_, C_, ELEM_FAST, LINE_FAST, false, 2), nullptr)
+#define KPREF true
+static const LineEntry kLineTableHalfPref[] = {
+    HCOL(1024, 16),
+};
+#undef KPREF
+#define KPREF false
+static const LineEntry kLineTableHalf[] = {
+    HROWT(1024, 16),
+};
+#undef KPREF
+#undef HCOL
+#undef HROWT
+#undef HENTRY
+#undef KH
+
 static void fill(const LineEntry &e, KernelInfo *out) {
   for (int i = 0; i < 4; ++i) out->fn_sw[i] = e.fn[i];
   out->fn = e.fn[0];
@@ -466,6 +661,7 @@ static void fill(const LineEntry &e, KernelInfo *out) {
   out->persistent = e.pf;
   out->preferred = e.pref;
   out->ept = e.ept;
+  out->sub = e.sub;
 }
 
 template <class F>
@@ -480,6 +676,8 @@ static void for_each_entry(F f) {
   for (const auto &e : kLineTablePf32Nts) f(e);
   for (const auto &e : kLineTablePf32Nt) f(e);
   for (const auto &e : kLineTablePf32x) f(e);
+  for (const auto &e : kLineTableHalfPref) f(e);
+  for (const auto &e : kLineTableHalf) f(e);
 }
 
 uint64_t line_registry_digest() {
@@ -493,7 +691,7 @@ uint64_t line_registry_digest() {
   };
   for_each_entry([&](const LineEntry &e) {
     mix(e.L), mix(e.C), mix(e.map), mix(e.omap), mix(e.tw4), mix(e.threads), mix(e.lds);
-    mix(e.pf), mix(e.pref), mix(e.ept);
+    mix(e.pf), mix(e.pref), mix(e.ept), mix(e.sub);
     for (int i = 0; i < 4; ++i) mix(e.fn[i] != nullptr);
   });
   return h;

@@ -200,6 +200,8 @@ VARIANTS = [
     (1 << 18, 3, "p0=0 p1=0"), (1 << 22, 2, "s=12 p0=1 t0=512"),
     (1 << 18, 3, "c0=32 t0=512 p0=0 c1=32 t1=512 p1=0"),
     (1 << 18, 3, "p0=1 c0=32 t0=512 p1=1 c1=32 t1=512"), (1 << 18, 3, "p0=1 c0=16 t0=256 p1=1 c1=16 t1=256"),
+    # split-first transposed rows (two sub-lines through half the LDS)
+    (1 << 20, 3, "c1=16 t1=512 p1=0"), (1 << 21, 2, "s=11 c1=16 t1=512 p1=0"),
 ]
 
 
@@ -222,7 +224,7 @@ def test_forced_variants(n, batch, force, monkeypatch):
 
 @pytest.mark.parametrize("n,force", [(2048, "c1=8"), (2048, "c1=4"), (2048, "k=1"), (1024, "p1=1"), (1024, "p1=0"),
                                      (2048, "p1=1 t1=512"), (1024, "p1=1 t1=512"), (512, "c1=16 t1=256"), (512, "c1=16 t1=512"),
-                                     (2048, "p1=0")])
+                                     (2048, "p1=0"), (1024, "c1=16 t1=1024 p1=0"), (1024, "c1=16 t1=512 p1=0")])
 def test_forced_2d_variants(n, force, monkeypatch):
     dp = _dp()
     monkeypatch.setenv("DPFFT_FORCE_PLAN", force)
