@@ -139,6 +139,23 @@ __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__res
   }
 }
 
+// Item of workgroup b in a launch of one workgroup per item.  Neighbouring
+// items (the column or row tiles of one signal) read or write row pieces that
+// share 128-byte lines, and workgroup ids are dealt round-robin over the 8
+// XCDs, each with its own L2: in order, each XCD would fetch every shared
+// line for its own piece.  So each round of 8 K ids gives XCD x the K
+// consecutive items 8 K r + K x + k (k < K), which run side by side and share
+// the lines in one L2; the rounds keep the largest-first order (and so every
+// XCD's share of the work) intact.  Ids past the last whole round keep their
+// own item.
+__device__ __forceinline__ uint32_t ragged_slot(uint32_t b, uint32_t n) {
+  constexpr uint32_t X = 8, K = 32;
+  const uint32_t full = n / (X * K) * (X * K);
+  if (b >= full) return b;
+  const uint32_t x = b % X, p = b / X;
+  return (p / K) * (X * K) + x * K + p % K;
+}
+
 // The buffers are separate restrict-qualified parameters so the compiler knows
 // no store of the kernel reaches the item list, and reads the (uniform)
 // descriptors through the scalar cache.
@@ -153,7 +170,7 @@ __global__ void __launch_bounds__(NTH, NTH == kRaggedThreads ? 4 : 1)
   a.tables = tables;
   const RaggedItem *__restrict__ items = item_list + a.first_item;
   if (a.direct) {
-    ragged_item<INV, NTH>(in, out, a, items[blockIdx.x], lds);
+    ragged_item<INV, NTH>(in, out, a, items[ragged_slot(blockIdx.x, gridDim.x)], lds);
     return;
   }
   int q = (int)blockIdx.x;
