@@ -380,6 +380,7 @@ bool choose_line(int L, int map, int omap, bool tw4, int cmax, int step, int64_t
     if (ov.c[step] < 0 && k.lines > cmax && !k.preferred) continue;
     if (ov.p[step] >= 0 && (int)k.persistent != ov.p[step]) continue;
     if (ov.t[step] >= 0 && k.threads != ov.t[step]) continue;
+    if (ov.h[step] >= 0 && k.sub != ov.h[step]) continue;
     if (ov.p[step] < 0 && k.persistent && !k.preferred) continue;
     // a persistent default pays off only where every resident workgroup gets
     // more than one tile (its prefetch needs a next tile); small batches take

@@ -51,6 +51,7 @@ Override parse_override(const std::string &text) {
       if (kind == 'c') o.c[idx] = val;
       if (kind == 'p') o.p[idx] = val;
       if (kind == 't') o.t[idx] = val;
+      if (kind == 'h') o.h[idx] = val;
     }
   }
   o.text = text;
@@ -183,16 +184,16 @@ std::vector<std::string> candidates(const fft_desc_t *d) {
     for (int i = 0; i < n; ++i)
       if (k[i].threads <= 1024)
         v.push_back(std::to_string(k[i].lines) + " " + std::to_string((int)k[i].persistent) + " " +
-                    std::to_string(k[i].threads));
+                    std::to_string(k[i].threads) + " " + std::to_string(k[i].sub));
     return v;
   };
   auto enc = [](int step, const std::string &cpt) {
     std::istringstream in(cpt);
-    int c, p, t;
-    in >> c >> p >> t;
+    int c, p, t, h;
+    in >> c >> p >> t >> h;
     const std::string i = std::to_string(step);
     return "c" + i + "=" + std::to_string(c) + " p" + i + "=" + std::to_string(p) + " t" + i + "=" +
-           std::to_string(t);
+           std::to_string(t) + " h" + i + "=" + std::to_string(h);
   };
   // two-pass plans: chunk sizes keeping one chunk's intermediate within 64,
   // 128 or 256 MiB (the memory-side cache holds 256 MB)

@@ -40,6 +40,7 @@ int resident_for(int lds_bytes, int threads);
 //   c<i>=<C>   lines (rows or columns) per workgroup
 //   p<i>=0|1   persistent variant off / on
 //   t<i>=<T>   threads per workgroup (instances differing in elements per thread)
+//   h<i>=1|2   sub-lines per line: plain tiles / split-first tiles
 //   o=0|1      radix order of runtime-radix lengths: powers of two first / odd first
 //   k=<n>      two-pass plans: transforms per chunk (0 = the whole batch at once)
 //   s=<n>      power-of-two four-step: log2 of the column length N1; ragged
@@ -57,6 +58,7 @@ struct Override {
   int c[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int p[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int t[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int h[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   int order = -1;
   int chunk = -1;
   int split = -1;

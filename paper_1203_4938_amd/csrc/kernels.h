@@ -45,7 +45,7 @@ template <int L, int EPT = 16> struct P2 {
     return k;
   }
   static constexpr int LG = lg();
-  static constexpr int RB = EPT >= 32 ? 5 : 4;  // log2 of the main radix
+  static constexpr int RB = EPT >= 32 ? 5 : EPT >= 16 ? 4 : 3;  // log2 of the main radix
   static constexpr int E = L >= EPT ? EPT : L;
   static constexpr int T = L / E;
   static constexpr int NP = (LG + RB - 1) / RB;
@@ -67,7 +67,7 @@ template <int L, int EPT = 16> struct P2 {
 constexpr int tw2_shift(int lg) { return (lg + 1) / 2; }
 
 // Runtime twin of P2<L, EPT> for the host.
-inline int pow2_rb(int ept) { return ept >= 32 ? 5 : 4; }
+inline int pow2_rb(int ept) { return ept >= 32 ? 5 : ept >= 16 ? 4 : 3; }
 inline int pow2_radix(int L, int p, int ept = 16) {
   int lg = 0;
   while ((1 << lg) < L) ++lg;

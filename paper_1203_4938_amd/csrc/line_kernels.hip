@@ -309,39 +309,42 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
 // b[n] = (x[n] - x[n + L/2]) w_L^n, n < L/2, whose L/2-point transforms are
 // the even and the odd outputs: X[2k] = A[k], X[2k + 1] = B[k].  The two
 // sub-lines then go through the Stockham passes one after the other, sharing
-// an LDS buffer of half a tile.  A tile of 8 lines of 2048 points needs
-// 76 KB of LDS instead of 152 KB, so two workgroups share a CU and overlap
-// each other's loads, barriers and butterflies, while every row piece the
-// tile reads or writes stays C x 8 bytes wide; the first sub-line's stores
-// drain while the second one is transformed.  Thread j of a line holds
-// elements j + T m (m < 32, T = L/32): the pairs (m, m + 16) are the split's
-// operands, and w_L^{j + T m} = w_L^j w_32^m.
+// an LDS buffer of half a tile, so two workgroups share a CU and overlap each
+// other's loads, barriers and butterflies, while every row piece the tile
+// reads or writes stays C x 8 bytes wide; the first sub-line's stores drain
+// while the second one is transformed.  Thread j of a line holds elements
+// j + T m (m < 2 ES, T = L / (2 ES)) with ES = 16 (radix-16 passes) or 8
+// (radix-8 passes, twice the threads and half the registers): the pairs
+// (m, m + ES) are the split's operands, and w_L^{j + T m} = w_L^j w_{2 ES}^m.
 // ---------------------------------------------------------------------------
-template <int L, int C, int MAP, int OMAP>
+// Pass twiddles of a sub-line: its per-pass table in LDS where it fits next to
+// the half tile for two workgroups per CU (else read from global memory).
+template <int L, int C, int MAP, int OMAP, int ES>
 constexpr int half_tw_entries() {
-  using PT = PlainTw<L / 2, C, MAP, OMAP, 16, C * (L / 32)>;
-  return PT::MODE == 1 ? PT::NTW : 0;
+  constexpr int n = P2<L / 2, ES>::twoff(P2<L / 2, ES>::NP);
+  return (n > 0 && (lds_pairs<L / 2, C, MAP, OMAP>() + n) * 8 <= 80 * 1024) ? n : 0;
 }
-template <int M>
+template <int ES, int M>
 __device__ __forceinline__ void half_split_one(cf &x, cf &y, cf wj) {
   const cf s = make_float2(x.x + y.x, x.y + y.y);
   const cf d = make_float2(x.x - y.x, x.y - y.y);
   x = s;
-  y = cmul(mulw32<32, M>(d), wj);
+  y = cmul(mulw32<2 * ES, M>(d), wj);
 }
-template <int... M>
-__device__ __forceinline__ void half_split(cf (&va)[16], cf (&vb)[16], cf wj,
+template <int ES, int... M>
+__device__ __forceinline__ void half_split(cf (&va)[ES], cf (&vb)[ES], cf wj,
                                            std::integer_sequence<int, M...>) {
-  (half_split_one<M>(va[M], vb[M], wj), ...);
+  (half_split_one<ES, M>(va[M], vb[M], wj), ...);
 }
 
-template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int NT>
-__global__ void __launch_bounds__(C * (L / 32)) __attribute__((amdgpu_waves_per_eu(4)))
+template <int L, int C, int MAP, int OMAP, bool TW4, int SW, int NT, int ES>
+__global__ void __launch_bounds__(C * L / (2 * ES))
+    __attribute__((amdgpu_waves_per_eu(C * L / (2 * ES) / 128)))
     k_lines_half(const cf *__restrict__ in, cf *__restrict__ out, LineArgs a) {
   constexpr int H = L / 2;
-  using G = P2<H, 16>;
+  using G = P2<H, ES>;
   constexpr int E = G::E, T = G::T, NTH = C * T;
-  static_assert(E == 16 && T * 32 == L, "16 elements of each sub-line per thread");
+  static_assert(E == ES && T * 2 * ES == L, "ES elements of each sub-line per thread");
   static_assert(NTH <= 1024, "a workgroup holds at most 1024 threads");
   using LO = Lds<H, C, OMAP, kPadShift>;
   constexpr int NP = lds_pairs<H, C, MAP, OMAP>();
@@ -349,7 +352,7 @@ __global__ void __launch_bounds__(C * (L / 32)) __attribute__((amdgpu_waves_per_
 
   const int tid = threadIdx.x;
   int c, j;
-  lane_map<H, 16, C, MAP>(tid, c, j);
+  lane_map<H, ES, C, MAP>(tid, c, j);
   const uint32_t tile = !(a.flags & F_REMAP)  ? blockIdx.x
                         : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x)
                                                : xcd_remap(blockIdx.x, gridDim.x);
@@ -393,12 +396,11 @@ __global__ void __launch_bounds__(C * (L / 32)) __attribute__((amdgpu_waves_per_
     wj = cmul(a.tw2[(1 << S) + (j >> S)], a.tw2[j & ((1 << S) - 1)]);
   }
 
-  // pass twiddles: the sub-line's per-pass table, in LDS where it fits next
-  // to the half tile for two workgroups per CU, else read from global memory
-  using PT = PlainTw<H, C, MAP, OMAP, 16, NTH>;
-  constexpr int NTW = half_tw_entries<L, C, MAP, OMAP>();
+  constexpr int NTW = half_tw_entries<L, C, MAP, OMAP, ES>();
   __shared__ cf twl[NTW > 0 ? NTW : 1];
-  if constexpr (NTW > 0) PT::fill(twl, a, tid);
+  if constexpr (NTW > 0) {
+    for (int i = tid; i < NTW; i += NTH) twl[i] = a.tw[i];
+  }
   using TWS = std::conditional_t<(NTW > 0), TwLdsTable, TwTable>;
   TWS tws;
   if constexpr (NTW > 0) {
@@ -407,10 +409,10 @@ __global__ void __launch_bounds__(C * (L / 32)) __attribute__((amdgpu_waves_per_
     tws = TwTable{a.tw};
   }
 
-  half_split(va, vb, wj, std::make_integer_sequence<int, E>{});
+  half_split<ES>(va, vb, wj, std::make_integer_sequence<int, E>{});
 
   int c2 = c, j2 = j;
-  if constexpr (OMAP != MAP) lane_map<H, 16, C, OMAP>(tid, c2, j2);
+  if constexpr (OMAP != MAP) lane_map<H, ES, C, OMAP>(tid, c2, j2);
   const int64_t line2 = line0 + c2;
   // outputs of sub-line s: element j + T m holds X[2 (j + T m) + s]
   auto finish = [&](cf(&v)[E], const int s) {
@@ -453,9 +455,9 @@ __global__ void __launch_bounds__(C * (L / 32)) __attribute__((amdgpu_waves_per_
   };
   // The last exchange of a sub-line's passes ends with a barrier after its
   // reads, and so does the re-tiling, so the next sub-line may write LDS.
-  all_passes<H, 16, C, MAP>(va, lds, tws, c, j, std::make_integer_sequence<int, G::NP>{});
+  all_passes<H, ES, C, MAP>(va, lds, tws, c, j, std::make_integer_sequence<int, G::NP>{});
   finish(va, 0);
-  all_passes<H, 16, C, MAP>(vb, lds, tws, c, j, std::make_integer_sequence<int, G::NP>{});
+  all_passes<H, ES, C, MAP>(vb, lds, tws, c, j, std::make_integer_sequence<int, G::NP>{});
   finish(vb, 1);
 }
 
@@ -616,18 +618,20 @@ static const LineEntry kLineTablePf32x[] = {
 // workgroups per CU.  The 1024-point column tiles of 16 are the default of
 // their shape (2D 1024 x 1024 column pass 11% faster than the persistent
 // 32-element tiles); the transposed rows of 1024 measured as fast as their
-// default and are opt-in.  Measured and not kept: tiles of 2048 (column
-// tiles with and without the four-step twiddle, transposed rows: 1-4%
-// slower, and 33% where the four-step twiddle spills registers at the
-// 128-VGPR budget of two workgroups per CU), 4096-point tiles of 4 (spills,
-// 35-70% slower) and the 1024-point four-step column tiles (5% slower than
-// the persistent ones).
-#define KH(L_, C_, M_, O_, TW_, SW_) (const void *)&k_lines_half<L_, C_, M_, O_, TW_, SW_, 0>
+// default and are opt-in.  Measured and not kept: 16-element tiles of 2048
+// (column tiles with and without the four-step twiddle, transposed rows:
+// 1-4% slower, and 33% where the four-step twiddle spills registers at the
+// 128-VGPR budget of two workgroups per CU), the same tiles with 8 elements
+// of each sub-line per thread (1024 threads, radix-8 passes, 32 waves per CU:
+// they spill at 64 registers and run 17-57% slower), 4096-point tiles of 4
+// (spills, 35-70% slower) and the 1024-point four-step column tiles (5%
+// slower than the persistent ones).
+#define KH(L_, C_, M_, O_, TW_, SW_) (const void *)&k_lines_half<L_, C_, M_, O_, TW_, SW_, 0, KES>
 #define HENTRY(L_, C_, M_, O_, TW_, F0, F1, F2, F3)                                        \
-  LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * (L_ / 32),                          \
+  LineEntry{L_, C_, M_, O_, TW_, {F0, F1, F2, F3}, C_ * L_ / (2 * KES),                     \
             (int)sizeof(cf) * lds_pairs<L_ / 2, C_, M_, O_>() +                              \
-                (int)sizeof(cf) * half_tw_entries<L_, C_, M_, O_>(),                          \
-            false, KPREF, 16, 2}
+                (int)sizeof(cf) * half_tw_entries<L_, C_, M_, O_, KES>(),                     \
+            false, KPREF, KES, 2}
 #define HCOL(L_, C_)                                                                       \
   HENTRY(L_, C_, LINE_FAST, LINE_FAST, false, KH(L_, C_, LINE_FAST, LINE_FAST, false, 0), \
          nullptr, KH(L_, C_, LINE_FAST, LINE_FAST, false, 2),                               \
@@ -635,6 +639,7 @@ static const LineEntry kLineTablePf32x[] = {
 #define HROWT(L_, C_)                                                                      \
   HENTRY(L_, C_, ELEM_FAST, LINE_FAST, false, KH(L_, C_, ELEM_FAST, LINE_FAST, false, 0), \
          nullptr, KH(L_, C_, ELEM_FAST, LINE_FAST, false, 2), nullptr)
+#define KES 16
 #define KPREF true
 static const LineEntry kLineTableHalfPref[] = {
     HCOL(1024, 16),
@@ -644,6 +649,7 @@ static const LineEntry kLineTableHalfPref[] = {
 static const LineEntry kLineTableHalf[] = {
     HROWT(1024, 16),
 };
+#undef KES
 #undef KPREF
 #undef HCOL
 #undef HROWT

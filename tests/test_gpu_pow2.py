@@ -202,6 +202,7 @@ VARIANTS = [
     (1 << 18, 3, "p0=1 c0=32 t0=512 p1=1 c1=32 t1=512"), (1 << 18, 3, "p0=1 c0=16 t0=256 p1=1 c1=16 t1=256"),
     # split-first transposed rows (two sub-lines through half the LDS)
     (1 << 20, 3, "c1=16 t1=512 p1=0"), (1 << 21, 2, "s=11 c1=16 t1=512 p1=0"),
+    (1 << 20, 2, "h1=2"), (1 << 20, 2, "h1=1 p1=0 t1=1024"),
 ]
 
 

@@ -107,6 +107,33 @@ def test_override_env_changes_the_kernel():
     assert "C=2" in out and 'override="c0=2"' in out
 
 
+SPLIT_FIRST = """
+import paper_1203_4938_amd as dp
+d, k = dp.make_desc(shape=(1024, 1024), rank=2, batch=8)
+print(dp.fft_plan_dry(d)[1])
+d, k = dp.make_desc(1 << 20, 4)
+print(dp.fft_plan_dry(d)[1])
+"""
+
+
+def test_split_first_tiles_and_the_h_override():
+    """The 2D 1024-point column pass defaults to the split-first tiles (two
+    sub-lines through half the LDS: 512 threads, 73600 B); h1=1 forces the
+    plain tiles; h1=2 puts the 2^20 transposed rows on the split-first tiles."""
+    def line(out, name):
+        return next(l for l in out.splitlines() if l.strip().startswith(name))
+
+    out = _run(SPLIT_FIRST, {})
+    col = line(out, "columns:")
+    assert "L=1024 C=16 threads=512 grid=" in col and "lds=73600B" in col, out
+    assert "lds=73600B" not in line(out, "fourstep_rows_transposed:"), out
+    out = _run(SPLIT_FIRST, {"DPFFT_FORCE_PLAN": "h1=1"})
+    assert "lds=73600B" not in line(out, "columns:"), out
+    out = _run(SPLIT_FIRST, {"DPFFT_FORCE_PLAN": "h1=2"})
+    rows = line(out, "fourstep_rows_transposed:")
+    assert "threads=512 grid=" in rows and "lds=73600B" in rows, out
+
+
 def _tune_key() -> str:
     out = _run(CODE.format(flags=0), {})
     key = re.search(r"tune_key=(\S+)", out).group(1)
