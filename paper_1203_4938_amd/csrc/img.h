@@ -25,12 +25,14 @@ struct ImgArgs {
   float tau;
 };
 
-// Kernel entry points (each launched with a grid of (tiles or groups, batch)).
+// Kernel entry points, each launched with a grid of (tiles, groups or
+// codewords, batch); k_img_assign takes img_assign_lds_bytes of dynamic LDS.
 const void *img_kernel_front();
 const void *img_kernel_count();
 const void *img_kernel_scan();
 const void *img_kernel_seed();
 const void *img_kernel_assign(bool accumulate);
 const void *img_kernel_update();
+size_t img_assign_lds_bytes(int k, bool accumulate);
 
 }  // namespace dpfft

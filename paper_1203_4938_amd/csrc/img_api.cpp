@@ -60,9 +60,10 @@ ImgArgs args_of(const img_desc_t *d) {
   return a;
 }
 
-hipError_t launch(const void *fn, dim3 grid, int threads, ImgArgs &a, hipStream_t s) {
+hipError_t launch(const void *fn, dim3 grid, int threads, ImgArgs &a, hipStream_t s,
+                  size_t lds = 0) {
   void *kargs[] = {(void *)&a};
-  return hipLaunchKernel(fn, grid, dim3(threads), kargs, 0, s);
+  return hipLaunchKernel(fn, grid, dim3(threads), kargs, lds, s);
 }
 
 }  // namespace
@@ -110,12 +111,13 @@ fft_status_t img_compress(const img_desc_t *desc, const uint8_t *rgb, const img_
   if (e == hipSuccess) e = launch(img_kernel_count(), gb, kImgBlocksPerGroup, a, s);
   if (e == hipSuccess) e = launch(img_kernel_scan(), dim3(B), 256, a, s);
   if (e == hipSuccess) e = launch(img_kernel_seed(), gb, kImgBlocksPerGroup, a, s);
-  const dim3 gu((unsigned)((a.k * 16 + 255) / 256), B);
+  const dim3 gu((unsigned)a.k, B);
   for (int it = 0; it < desc->iters && e == hipSuccess; ++it) {
-    e = launch(img_kernel_assign(true), gb, kImgBlocksPerGroup, a, s);
+    e = launch(img_kernel_assign(true), gb, kImgBlocksPerGroup, a, s, img_assign_lds_bytes(a.k, true));
     if (e == hipSuccess) e = launch(img_kernel_update(), gu, 256, a, s);
   }
-  if (e == hipSuccess) e = launch(img_kernel_assign(false), gb, kImgBlocksPerGroup, a, s);
+  if (e == hipSuccess)
+    e = launch(img_kernel_assign(false), gb, kImgBlocksPerGroup, a, s, img_assign_lds_bytes(a.k, false));
   if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return FFT_OK;
 }
@@ -134,7 +136,8 @@ fft_status_t img_encode(const img_desc_t *desc, const float *dev, const float *a
   a.codebook = const_cast<float *>(codebook);
   a.code = code;
   const hipError_t e = launch(img_kernel_assign(false), dim3((unsigned)a.groups, (unsigned)desc->batch),
-                              kImgBlocksPerGroup, a, (hipStream_t)hip_stream);
+                              kImgBlocksPerGroup, a, (hipStream_t)hip_stream,
+                              img_assign_lds_bytes(a.k, false));
   if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return FFT_OK;
 }

@@ -182,25 +182,39 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_seed(ImgArgs a) {
 }
 
 // Nearest codeword of every pattern block (ties to the lower index).
-// ACC: add the block to its cluster's sums (LDS atomics, then one partial
-// per group); otherwise write the codes of every block.
+// The squared distance |v - c|^2 = |v|^2 + 2 (|c|^2 / 2 - v.c) is ranked by
+// its codeword part h_c - v.c with h_c = |c|^2 / 2: one fused multiply-add
+// per component instead of a subtraction and a multiply-add (the kernel is
+// bound by vector instructions), the same minimiser in exact arithmetic.
+// Four codewords are scored at a time and compared in index order, so the
+// first of equal scores wins as in a plain scan.
+// ACC: the group's cluster sums.  Each pattern block takes a rank in its
+// cluster (one LDS atomic), the per-cluster counts are scanned, the blocks'
+// deviation vectors are scattered into cluster order, and the (cluster,
+// component) sums are read off the contiguous runs and written as the
+// group's partial: one atomic per block instead of seventeen.  Otherwise the
+// codes of every block are written.  The codebook and the group's work
+// arrays sit in dynamic LDS sized for k.
 template <bool ACC>
 __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
-  __shared__ float cbk[kImgMaxK * 16];
-  __shared__ float acc[ACC ? kImgMaxK * 17 : 1];
-  const int64_t img = blockIdx.y;
+  extern __shared__ __align__(16) float img_lds[];
   const int k = a.k;
+  float *cbk = img_lds;                          // k x 16
+  float *hc = cbk + k * 16;                      // k: |c|^2 / 2
+  float *sorted = hc + ((k + 3) & ~3);           // ACC: 256 x 16, in cluster order
+  int *cnt = (int *)(sorted + (ACC ? 16 * kImgBlocksPerGroup : 0));  // ACC: k counts
+  int *off = cnt + k;                            // ACC: k + 1 run offsets
+  const int64_t img = blockIdx.y;
+  const int tid = threadIdx.x;
   const float *gcb = a.codebook + img * (int64_t)k * 16;
-  for (int i = threadIdx.x; i < k * 16; i += kImgBlocksPerGroup) cbk[i] = gcb[i];
+  for (int i = tid; i < k * 16; i += kImgBlocksPerGroup) cbk[i] = gcb[i];
   if constexpr (ACC)
-    for (int i = threadIdx.x; i < k * 17; i += kImgBlocksPerGroup) acc[i] = 0.f;
-  __syncthreads();
-  const int64_t b = (int64_t)blockIdx.x * kImgBlocksPerGroup + threadIdx.x;
+    for (int i = tid; i < k; i += kImgBlocksPerGroup) cnt[i] = 0;
+  const int64_t b = (int64_t)blockIdx.x * kImgBlocksPerGroup + tid;
   const int64_t gb = img * a.nb + b;
   const bool in = b < a.nb;
   const bool pat = in && a.act[gb] >= a.tau;
   float v[16];
-  int best = 0;
   if (pat) {
     const float4 *d = reinterpret_cast<const float4 *>(a.dev + 16 * gb);
 #pragma unroll
@@ -211,49 +225,142 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
       v[4 * q + 2] = f.z;
       v[4 * q + 3] = f.w;
     }
-    float bd = 3.4e38f;
-    for (int c = 0; c < k; ++c) {
-      float dist = 0.f;
+  }
+  __syncthreads();
+  for (int c = tid; c < k; c += kImgBlocksPerGroup) {
+    float h = 0.f;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const float e = v[t] - cbk[16 * c + t];
-        dist = __builtin_fmaf(e, e, dist);
+    for (int t = 0; t < 16; ++t) h = __builtin_fmaf(cbk[16 * c + t], cbk[16 * c + t], h);
+    hc[c] = 0.5f * h;
+  }
+  __syncthreads();
+  int best = 0;
+  if (pat) {
+    float bd = 3.4e38f;
+    const float4 *cb4 = reinterpret_cast<const float4 *>(cbk);
+    int c = 0;
+    for (; c + 4 <= k; c += 4) {
+      float dot[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float4 w = cb4[4 * (c + u) + q];
+          dot[u] = __builtin_fmaf(v[4 * q], w.x, dot[u]);
+          dot[u] = __builtin_fmaf(v[4 * q + 1], w.y, dot[u]);
+          dot[u] = __builtin_fmaf(v[4 * q + 2], w.z, dot[u]);
+          dot[u] = __builtin_fmaf(v[4 * q + 3], w.w, dot[u]);
+        }
       }
-      if (dist < bd) {
-        bd = dist;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float sc = hc[c + u] - dot[u];
+        if (sc < bd) {
+          bd = sc;
+          best = c + u;
+        }
+      }
+    }
+    for (; c < k; ++c) {
+      float dot = 0.f;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) dot = __builtin_fmaf(v[t], cbk[16 * c + t], dot);
+      const float sc = hc[c] - dot;
+      if (sc < bd) {
+        bd = sc;
         best = c;
       }
     }
   }
   if constexpr (ACC) {
-    if (pat) {
+    const int rank = pat ? atomicAdd(&cnt[best], 1) : 0;
+    __syncthreads();
+    if (tid < 64) {
+      // exclusive scan of the k <= 256 counts by the first wave, four per lane
+      int loc[4], run = 0;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) atomicAdd(&acc[17 * best + t], v[t]);
-      atomicAdd(&acc[17 * best + 16], 1.0f);
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * tid + q;
+        loc[q] = run;
+        run += i < k ? cnt[i] : 0;
+      }
+      int incl = run;
+      for (int d = 1; d < 64; d *= 2) {
+        const int o = __shfl_up(incl, d, 64);
+        if (tid >= d) incl += o;
+      }
+      const int base = incl - run;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * tid + q;
+        if (i < k) off[i] = base + loc[q];
+      }
+      if (tid == 63) off[k] = incl;
+    }
+    __syncthreads();
+    if (pat) {
+      float4 *dst = reinterpret_cast<float4 *>(sorted + 16 * (off[best] + rank));
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        dst[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
     }
     __syncthreads();
     float *part = a.part + (img * a.groups + blockIdx.x) * (int64_t)k * 17;
-    for (int i = threadIdx.x; i < k * 17; i += kImgBlocksPerGroup) part[i] = acc[i];
+    for (int i = tid; i < k * 17; i += kImgBlocksPerGroup) {
+      const int c = i / 17, t = i % 17;
+      const int r0 = off[c], r1 = off[c + 1];
+      float sum;
+      if (t == 16) {
+        sum = (float)(r1 - r0);
+      } else {
+        sum = 0.f;
+        for (int r = r0; r < r1; ++r) sum += sorted[16 * r + t];
+      }
+      part[i] = sum;
+    }
   } else {
     if (in) a.code[gb] = pat ? best + 1 : 0;
   }
 }
 
-// New codewords: the groups' partial sums added in group order; a codeword
-// without blocks keeps its value.  Thread t of image blockIdx.y handles
-// (codeword t / 16, component t % 16).
+// Dynamic LDS of k_img_assign for k codewords.
+size_t img_assign_lds_bytes(int k, bool accumulate) {
+  const size_t f = (size_t)k * 16 + (size_t)((k + 3) & ~3);
+  return sizeof(float) * (f + (accumulate ? 16 * kImgBlocksPerGroup + 2 * (size_t)k + 1 : 0));
+}
+
+// New codewords: one workgroup per (codeword blockIdx.x, image blockIdx.y).
+// Thread i adds the partials of groups i, i + 256, ... in order, then the 256
+// thread sums are added in a fixed tree, so the result does not depend on
+// scheduling; a codeword without blocks keeps its value.
 __global__ void __launch_bounds__(256) k_img_update(ImgArgs a) {
+  __shared__ float red[17][256];
   const int64_t img = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.k * 16) return;
-  const int c = i / 16, t = i % 16;
-  const float *part = a.part + img * a.groups * (int64_t)a.k * 17;
-  float s = 0.f, n = 0.f;
-  for (int g = 0; g < a.groups; ++g) {
-    s += part[(int64_t)g * a.k * 17 + 17 * c + t];
-    n += part[(int64_t)g * a.k * 17 + 17 * c + 16];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int64_t K17 = (int64_t)a.k * 17;
+  const float *part = a.part + img * a.groups * K17 + 17 * c;
+  float s[17];
+#pragma unroll
+  for (int t = 0; t < 17; ++t) s[t] = 0.f;
+  for (int g = tid; g < a.groups; g += 256) {
+    const float *p = part + g * K17;
+#pragma unroll
+    for (int t = 0; t < 17; ++t) s[t] += p[t];
   }
-  if (n > 0.f) a.codebook[img * (int64_t)a.k * 16 + i] = s / n;
+#pragma unroll
+  for (int t = 0; t < 17; ++t) red[t][tid] = s[t];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+#pragma unroll
+      for (int t = 0; t < 17; ++t) red[t][tid] += red[t][tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid < 16) {
+    const float n = red[16][0];
+    if (n > 0.f) a.codebook[(img * a.k + c) * 16 + tid] = red[tid][0] / n;
+  }
 }
 
 const void *img_kernel_front() { return (const void *)&k_img_front; }
