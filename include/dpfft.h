@@ -261,12 +261,13 @@ typedef struct {
 } img_desc_t;
 
 /* Outputs of img_compress: caller-owned device buffers, per image back to back.
- *   y        batch x height x width          float32, 4-byte aligned
- *   cb, cr   batch x height/2 x width/2      float32
+ *   y        batch x height x width          float32, 16-byte aligned
+ *   cb, cr   batch x height/2 x width/2      float32, 8-byte aligned
  *   mean,act batch x (height/4) x (width/4)  float32 (blocks in raster order)
  *   dev      batch x blocks x 16             float32, 16-byte aligned
  *   codebook batch x k x 16                  float32
- *   code     batch x blocks                  int32 */
+ *   code     batch x blocks                  int32
+ * (buffers without a stated alignment: 4-byte aligned) */
 typedef struct {
   float *y, *cb, *cr, *mean, *act, *dev, *codebook;
   int32_t *code;
@@ -276,7 +277,8 @@ typedef struct {
 size_t img_workspace_bytes(const img_desc_t *desc);
 
 /* Steps (a)-(e) for `batch` RGB images (device pointer, interleaved uint8,
- * batch x height x width x 3).  workspace: img_workspace_bytes(desc) bytes,
+ * batch x height x width x 3, 4-byte aligned: each thread reads its four
+ * pixels as three 32-bit words).  workspace: img_workspace_bytes(desc) bytes,
  * 256-byte aligned, caller-owned.  Asynchronous on hip_stream.  Errors:
  * FFT_E_INVALID for a bad descriptor, NULL or misaligned buffers (checked
  * before any launch); FFT_E_UNSUPPORTED for images above 2^30 pixels;

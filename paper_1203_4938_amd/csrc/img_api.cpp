@@ -84,10 +84,12 @@ fft_status_t img_compress(const img_desc_t *desc, const uint8_t *rgb, const img_
   if (!rgb || !out->y || !out->cb || !out->cr || !out->mean || !out->act || !out->dev ||
       !out->codebook || !out->code || !workspace)
     return fail(FFT_E_INVALID, "a buffer is NULL");
-  if (misaligned(out->y, 4) || misaligned(out->cb, 4) || misaligned(out->cr, 4) ||
-      misaligned(out->mean, 4) || misaligned(out->act, 4) || misaligned(out->dev, 16) ||
-      misaligned(out->codebook, 4) || misaligned(out->code, 4) || misaligned(workspace, 256))
-    return fail(FFT_E_INVALID, "misaligned buffer (dev 16 bytes, workspace 256, others 4)");
+  if (misaligned(rgb, 4) || misaligned(out->y, 16) || misaligned(out->cb, 8) ||
+      misaligned(out->cr, 8) || misaligned(out->mean, 4) || misaligned(out->act, 4) ||
+      misaligned(out->dev, 16) || misaligned(out->codebook, 4) || misaligned(out->code, 4) ||
+      misaligned(workspace, 256))
+    return fail(FFT_E_INVALID,
+                "misaligned buffer (y and dev 16 bytes, cb and cr 8, workspace 256, rgb and others 4)");
   const WsLayout L = layout(desc);
   ImgArgs a = args_of(desc);
   a.rgb = rgb;

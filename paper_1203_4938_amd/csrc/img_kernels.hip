@@ -13,7 +13,7 @@
 //
 // (a)-(c) are one pass over the pixels (k_img_front): a 64 x 16 pixel tile
 // computes Y for itself and a one-pixel halo into LDS, writes Y and the
-// quarter-size chroma, then each of its 64 blocks reduces its 16 pixels.
+// quarter-size chroma, then four threads per block reduce its 16 pixels.
 // The k-means and the encoding walk the blocks in groups of 256, one block
 // per thread, the codebook in LDS; the cluster sums of a group go through
 // LDS atomics into per-group partials that k_img_update adds up in a fixed
@@ -39,8 +39,25 @@ constexpr int HW = kImgTileW + 2, HH = kImgTileH + 2;  // tile with its halo
 
 }  // namespace
 
+// Y of pixel (gy, gx) clamped to the image (the replicated edge).
+__device__ __forceinline__ float luma_at(const uint8_t *rgb, int64_t h, int64_t w, int64_t gy,
+                                         int64_t gx) {
+  gy = gy < 0 ? 0 : (gy >= h ? h - 1 : gy);
+  gx = gx < 0 ? 0 : (gx >= w ? w - 1 : gx);
+  const uint8_t *p = rgb + (gy * w + gx) * 3;
+  return luma((float)p[0], (float)p[1], (float)p[2]);
+}
+
+// Thread (row ry, group g) of a tile owns the 4 pixels x0 + 4 g .. + 3 of row
+// y0 + ry: their 12 bytes are three aligned 32-bit words (the width is a
+// multiple of 4).  It writes their Y, keeps it in LDS with the tile's
+// one-pixel halo, and leaves the Cb, Cr sums of its two horizontal pixel
+// pairs in LDS for the 2 x 2 means.  Then four threads take each 4 x 4 block,
+// one block row each, and add their row sums with lane shuffles.
 __global__ void __launch_bounds__(kImgThreads) k_img_front(ImgArgs a) {
+  static_assert(kImgTileW == 64 && kImgTileH == 16 && kImgThreads == 256, "tile shape");
   __shared__ float ys[HH * HW];
+  __shared__ float2 cpart[kImgTileH][kImgTileW / 2];
   const int64_t img = blockIdx.y;
   const int64_t tiles_x = (a.w + kImgTileW - 1) / kImgTileW;
   const int64_t tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
@@ -49,66 +66,94 @@ __global__ void __launch_bounds__(kImgThreads) k_img_front(ImgArgs a) {
   float *Y = a.y + img * a.h * a.w;
   const int tid = threadIdx.x;
 
-  // (a) luminance of the tile and its halo (coordinates clamped to the image:
-  // the replicated edge of the central differences)
-  for (int i = tid; i < HH * HW; i += kImgThreads) {
-    const int ly = i / HW, lx = i % HW;
-    int64_t gy = y0 + ly - 1, gx = x0 + lx - 1;
-    const bool inside = gy >= y0 && gy < y0 + kImgTileH && gx >= x0 && gx < x0 + kImgTileW &&
-                        gy < a.h && gx < a.w;
-    gy = gy < 0 ? 0 : (gy >= a.h ? a.h - 1 : gy);
-    gx = gx < 0 ? 0 : (gx >= a.w ? a.w - 1 : gx);
-    const uint8_t *p = rgb + (gy * a.w + gx) * 3;
-    const float v = luma((float)p[0], (float)p[1], (float)p[2]);
-    ys[i] = v;
-    if (inside) Y[gy * a.w + gx] = v;
-  }
-  // (b) chroma: one 2x2 square per thread
+  // (a) luminance of the tile, (b) chroma sums of horizontal pairs
   {
-    const int sy = tid / (kImgTileW / 2), sx = tid % (kImgTileW / 2);
-    const int64_t py = y0 + 2 * sy, px = x0 + 2 * sx;
-    if (sy < kImgTileH / 2 && py < a.h && px < a.w) {
-      float sb = 0.f, sr = 0.f;
+    const int ry = tid / 16, g = tid % 16;
+    const int64_t py = y0 + ry, px = x0 + 4 * g;
+    float yv[4];
+    if (py < a.h && px < a.w) {
+      const uint32_t *p = reinterpret_cast<const uint32_t *>(rgb + (py * a.w + px) * 3);
+      const uint32_t d0 = p[0], d1 = p[1], d2 = p[2];
+      const float r[4] = {(float)(d0 & 255u), (float)(d0 >> 24), (float)((d1 >> 16) & 255u),
+                          (float)((d2 >> 8) & 255u)};
+      const float gg[4] = {(float)((d0 >> 8) & 255u), (float)(d1 & 255u), (float)(d1 >> 24),
+                           (float)((d2 >> 16) & 255u)};
+      const float bb[4] = {(float)((d0 >> 16) & 255u), (float)((d1 >> 8) & 255u), (float)(d2 & 255u),
+                           (float)(d2 >> 24)};
+      float cb[4], cr[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint8_t *p = rgb + ((py + (q >> 1)) * a.w + px + (q & 1)) * 3;
-        const float r = p[0], g = p[1], b = p[2];
-        sb += chroma_b(r, g, b);
-        sr += chroma_r(r, g, b);
+      for (int i = 0; i < 4; ++i) {
+        yv[i] = luma(r[i], gg[i], bb[i]);
+        cb[i] = chroma_b(r[i], gg[i], bb[i]);
+        cr[i] = chroma_r(r[i], gg[i], bb[i]);
       }
-      const int64_t w2 = a.w / 2, o = img * (a.h / 2) * w2 + (py / 2) * w2 + px / 2;
-      a.cb[o] = 0.25f * sb;
-      a.cr[o] = 0.25f * sr;
+      *reinterpret_cast<float4 *>(Y + py * a.w + px) = make_float4(yv[0], yv[1], yv[2], yv[3]);
+      cpart[ry][2 * g] = make_float2(cb[0] + cb[1], cr[0] + cr[1]);
+      cpart[ry][2 * g + 1] = make_float2(cb[2] + cb[3], cr[2] + cr[3]);
+    } else {
+      // past the image's last row or column: the replicated edge, for the
+      // central differences of the blocks along it
+#pragma unroll
+      for (int i = 0; i < 4; ++i) yv[i] = luma_at(rgb, a.h, a.w, py, px + i);
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ys[(ry + 1) * HW + 4 * g + 1 + i] = yv[i];
+  }
+  // the halo: rows -1 and 16 of the tile, columns -1 and 64 (corners unused)
+  if (tid < 2 * kImgTileW + 2 * kImgTileH) {
+    int ly, lx;
+    if (tid < 2 * kImgTileW) {
+      ly = tid < kImgTileW ? 0 : HH - 1;
+      lx = tid % kImgTileW + 1;
+    } else {
+      const int q = tid - 2 * kImgTileW;
+      ly = q % kImgTileH + 1;
+      lx = q < kImgTileH ? 0 : HW - 1;
+    }
+    ys[ly * HW + lx] = luma_at(rgb, a.h, a.w, y0 + ly - 1, x0 + lx - 1);
   }
   __syncthreads();
-  // (c) blocks: one per thread for the first 64 threads
-  if (tid < (kImgTileW / 4) * (kImgTileH / 4)) {
-    const int by = tid / (kImgTileW / 4), bx = tid % (kImgTileW / 4);
-    const int64_t gby = y0 / 4 + by, gbx = x0 / 4 + bx;
-    const int64_t bw = a.w / 4;
+  // (b) chroma: means of 2 x 2 squares, two per thread of the first 128
+  if (tid < kImgTileH / 2 * kImgTileW / 4) {
+    const int rp = tid / 16, g = tid % 16;
+    const int64_t py = y0 + 2 * rp, px = x0 + 4 * g;
+    if (py < a.h && px < a.w) {
+      const float2 u0 = cpart[2 * rp][2 * g], l0 = cpart[2 * rp + 1][2 * g];
+      const float2 u1 = cpart[2 * rp][2 * g + 1], l1 = cpart[2 * rp + 1][2 * g + 1];
+      const int64_t w2 = a.w / 2, o = img * (a.h / 2) * w2 + (py / 2) * w2 + px / 2;
+      *reinterpret_cast<float2 *>(a.cb + o) = make_float2(0.25f * (u0.x + l0.x), 0.25f * (u1.x + l1.x));
+      *reinterpret_cast<float2 *>(a.cr + o) = make_float2(0.25f * (u0.y + l0.y), 0.25f * (u1.y + l1.y));
+    }
+  }
+  // (c) blocks: four threads per block (lanes 4 q .. 4 q + 3 of one wave)
+  {
+    const int blk = tid / 4, r = tid % 4;
+    const int by = blk / (kImgTileW / 4), bx = blk % (kImgTileW / 4);
+    const int ly = 4 * by + r + 1, lx0 = 4 * bx + 1;
+    float v[4], s = 0.f, g = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int lx = lx0 + j;
+      const float c = ys[ly * HW + lx];
+      const float gx = 0.5f * (ys[ly * HW + lx + 1] - ys[ly * HW + lx - 1]);
+      const float gyv = 0.5f * (ys[(ly + 1) * HW + lx] - ys[(ly - 1) * HW + lx]);
+      g += __builtin_sqrtf(gx * gx + gyv * gyv);
+      s += c;
+      v[j] = c;
+    }
+    s += __shfl_xor(s, 1, 64);
+    g += __shfl_xor(g, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    g += __shfl_xor(g, 2, 64);
+    const int64_t gby = y0 / 4 + by, gbx = x0 / 4 + bx, bw = a.w / 4;
     if (gby < a.h / 4 && gbx < bw) {
-      float v[16], s = 0.f, g = 0.f;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int ly = 4 * by + i + 1, lx = 4 * bx + j + 1;
-          const float c = ys[ly * HW + lx];
-          const float gx = 0.5f * (ys[ly * HW + lx + 1] - ys[ly * HW + lx - 1]);
-          const float gyv = 0.5f * (ys[(ly + 1) * HW + lx] - ys[(ly - 1) * HW + lx]);
-          g += __builtin_sqrtf(gx * gx + gyv * gyv);
-          s += c;
-          v[4 * i + j] = c;
-        }
       const float m = s * (1.0f / 16.0f);
       const int64_t b = img * a.nb + gby * bw + gbx;
-      a.mean[b] = m;
-      a.act[b] = g * (1.0f / 16.0f);
-      float4 *d = reinterpret_cast<float4 *>(a.dev + 16 * b);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        d[q] = make_float4(v[4 * q] - m, v[4 * q + 1] - m, v[4 * q + 2] - m, v[4 * q + 3] - m);
+      if (r == 0) {
+        a.mean[b] = m;
+        a.act[b] = g * (1.0f / 16.0f);
+      }
+      reinterpret_cast<float4 *>(a.dev + 16 * b)[r] = make_float4(v[0] - m, v[1] - m, v[2] - m, v[3] - m);
     }
   }
 }

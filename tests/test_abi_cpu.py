@@ -121,3 +121,13 @@ def test_img_descriptors_rejected_before_device():
     d = dp.ImgDesc(**ok)
     assert dp._lib.img_compress(ctypes.byref(d), None, None, None, None) == dp.FFT_E_INVALID
     assert dp._lib.img_encode(ctypes.byref(d), None, None, None, None, None) == dp.FFT_E_INVALID
+    # misaligned buffers are refused on the host (the pointers are never used):
+    # rgb must be 4-byte aligned, y 16, cb and cr 8
+    base = 1 << 20
+    good = dict(y=base, cb=base, cr=base, mean=base, act=base, dev=base, codebook=base, code=base)
+    for rgb, field, off in ((base + 2, None, 0), (base, "y", 8), (base, "cb", 4), (base, "cr", 4)):
+        o = dp.ImgOut(**{**good, **({field: base + off} if field else {})})
+        st = dp._lib.img_compress(ctypes.byref(d), ctypes.c_void_p(rgb), ctypes.byref(o),
+                                  ctypes.c_void_p(base), None)
+        assert st == dp.FFT_E_INVALID, (rgb, field)
+        assert "misaligned" in dp.fft_last_error()
