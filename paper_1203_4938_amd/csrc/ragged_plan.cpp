@@ -153,8 +153,8 @@ struct RaggedStep : Step {
     return e;
   }
 
-  // The persistent launches as a graph of up to three nodes in sequence,
-  // built once per (buffers, direction, stream).
+  // The launches as a graph of up to three nodes, built once per (buffers,
+  // direction, stream).
   hipError_t launch_graph(const ExecCtx &ctx) const {
     GraphKey key{ctx.in, ctx.out, ctx.ws, ctx.inverse, ctx.stream};
     hipGraphExec_t exec = nullptr;
@@ -176,7 +176,10 @@ struct RaggedStep : Step {
       hipGraph_t g = nullptr;
       hipError_t e = hipGraphCreate(&g, 0);
       if (e != hipSuccess) return e;
-      hipGraphNode_t prev = nullptr;
+      // The 1024-thread single-pass items share no data with the others, so
+      // their node is a branch of its own that may run beside the column
+      // launch; the row launch waits for the column launch only.
+      hipGraphNode_t cols = nullptr;
       for (int k = 0; k < 3 && e == hipSuccess; ++k) {
         if (rr[k].nitems == 0) continue;
         hipKernelNodeParams p{};
@@ -186,8 +189,9 @@ struct RaggedStep : Step {
         p.sharedMemBytes = (unsigned)lds_of(k);
         p.kernelParams = kp[k];
         hipGraphNode_t node = nullptr;
-        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-        prev = node;
+        const bool dep = k == 2 && cols;
+        e = hipGraphAddKernelNode(&node, g, dep ? &cols : nullptr, dep ? 1 : 0, &p);
+        if (k == 1) cols = node;
       }
       if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
