@@ -227,12 +227,19 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_seed(ImgArgs a) {
 }
 
 // Nearest codeword of every pattern block (ties to the lower index).
-// The squared distance |v - c|^2 = |v|^2 + 2 (|c|^2 / 2 - v.c) is ranked by
-// its codeword part h_c - v.c with h_c = |c|^2 / 2: one fused multiply-add
-// per component instead of a subtraction and a multiply-add (the kernel is
-// bound by vector instructions), the same minimiser in exact arithmetic.
-// Four codewords are scored at a time and compared in index order, so the
-// first of equal scores wins as in a plain scan.
+// The squared distance |v - c|^2 = |v|^2 - 2 (v.c - |c|^2 / 2) is ranked by
+// D_c = v.c - h_c with h_c = |c|^2 / 2, the same maximiser as the smallest
+// distance in exact arithmetic.  The dot products of a wave's 64 blocks with
+// all codewords are FP32 matrix products on the matrix cores
+// (v_mfma_f32_16x16x4_f32, 16 codewords x 16 blocks x 4 components each, the
+// accumulator started at -h_c): A = codebook rows, B = deviation vectors.
+// Operand layout of the 16x16x4 FP32 product: lane l supplies A row (l & 15)
+// and B column (l & 15) at k = l >> 4; it holds D column (l & 15), rows
+// 4 (l >> 4) + r, r < 4.  Step s of the four takes component 4 (l >> 4) + s,
+// so a lane's operands are one aligned float4 of a codeword and of a block.
+// Each lane keeps the best of its rows in index order (strictly larger wins),
+// then the four lanes of a column compare (value, index) pairs: the larger
+// value, on equal values the lower index, as a plain scan would pick.
 // ACC: the group's cluster sums.  Each pattern block takes a rank in its
 // cluster (one LDS atomic), the per-cluster counts are scanned, the blocks'
 // deviation vectors are scattered into cluster order, and the (cluster,
@@ -240,8 +247,11 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_seed(ImgArgs a) {
 // group's partial: one atomic per block instead of seventeen.  Otherwise the
 // codes of every block are written.  The codebook and the group's work
 // arrays sit in dynamic LDS sized for k.
+typedef float img_f4 __attribute__((ext_vector_type(4)));
+
 template <bool ACC>
 __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
+  static_assert(kImgBlocksPerGroup % 64 == 0, "whole waves of blocks");
   extern __shared__ __align__(16) float img_lds[];
   const int k = a.k;
   float *cbk = img_lds;                          // k x 16
@@ -250,26 +260,23 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
   int *cnt = (int *)(sorted + (ACC ? 16 * kImgBlocksPerGroup : 0));  // ACC: k counts
   int *off = cnt + k;                            // ACC: k + 1 run offsets
   const int64_t img = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, col = lane & 15, g4 = lane >> 4;
   const float *gcb = a.codebook + img * (int64_t)k * 16;
   for (int i = tid; i < k * 16; i += kImgBlocksPerGroup) cbk[i] = gcb[i];
   if constexpr (ACC)
     for (int i = tid; i < k; i += kImgBlocksPerGroup) cnt[i] = 0;
-  const int64_t b = (int64_t)blockIdx.x * kImgBlocksPerGroup + tid;
+  const int64_t b0 = (int64_t)blockIdx.x * kImgBlocksPerGroup + (tid - lane);  // the wave's first block
+  const int64_t b = b0 + lane;
   const int64_t gb = img * a.nb + b;
   const bool in = b < a.nb;
   const bool pat = in && a.act[gb] >= a.tau;
-  float v[16];
-  if (pat) {
-    const float4 *d = reinterpret_cast<const float4 *>(a.dev + 16 * gb);
+  // B operands: block b0 + 16 nt + col, components 4 g4 .. 4 g4 + 3
+  float4 vb[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 f = d[q];
-      v[4 * q] = f.x;
-      v[4 * q + 1] = f.y;
-      v[4 * q + 2] = f.z;
-      v[4 * q + 3] = f.w;
-    }
+  for (int nt = 0; nt < 4; ++nt) {
+    const int64_t bb = b0 + 16 * nt + col;
+    vb[nt] = bb < a.nb ? reinterpret_cast<const float4 *>(a.dev + 16 * (img * a.nb + bb))[g4]
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __syncthreads();
   for (int c = tid; c < k; c += kImgBlocksPerGroup) {
@@ -279,43 +286,50 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
     hc[c] = 0.5f * h;
   }
   __syncthreads();
+  float bv[4];
+  int bi[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) bv[nt] = -3.4e38f, bi[nt] = 0;
+  for (int m0 = 0; m0 < k; m0 += 16) {
+    const int ca = m0 + col;  // this lane's A row
+    const float4 va = ca < k ? reinterpret_cast<const float4 *>(cbk + 16 * ca)[g4]
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+    img_f4 init;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cr = m0 + 4 * g4 + r;
+      init[r] = cr < k ? -hc[cr] : -3.4e38f;
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      img_f4 d = init;
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb[nt].x, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[nt].y, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.z, vb[nt].z, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.w, vb[nt].w, d, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (d[r] > bv[nt]) {
+          bv[nt] = d[r];
+          bi[nt] = m0 + 4 * g4 + r;
+        }
+      }
+    }
+  }
+  // the four lanes of a column (g4 = 0..3) hold interleaved rows: combine
   int best = 0;
-  if (pat) {
-    float bd = 3.4e38f;
-    const float4 *cb4 = reinterpret_cast<const float4 *>(cbk);
-    int c = 0;
-    for (; c + 4 <= k; c += 4) {
-      float dot[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+  for (int nt = 0; nt < 4; ++nt) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float4 w = cb4[4 * (c + u) + q];
-          dot[u] = __builtin_fmaf(v[4 * q], w.x, dot[u]);
-          dot[u] = __builtin_fmaf(v[4 * q + 1], w.y, dot[u]);
-          dot[u] = __builtin_fmaf(v[4 * q + 2], w.z, dot[u]);
-          dot[u] = __builtin_fmaf(v[4 * q + 3], w.w, dot[u]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float sc = hc[c + u] - dot[u];
-        if (sc < bd) {
-          bd = sc;
-          best = c + u;
-        }
+    for (int x = 16; x <= 32; x *= 2) {
+      const float ov = __shfl_xor(bv[nt], x, 64);
+      const int oi = __shfl_xor(bi[nt], x, 64);
+      if (ov > bv[nt] || (ov == bv[nt] && oi < bi[nt])) {
+        bv[nt] = ov;
+        bi[nt] = oi;
       }
     }
-    for (; c < k; ++c) {
-      float dot = 0.f;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) dot = __builtin_fmaf(v[t], cbk[16 * c + t], dot);
-      const float sc = hc[c] - dot;
-      if (sc < bd) {
-        bd = sc;
-        best = c;
-      }
-    }
+    if (nt == g4) best = bi[nt];  // block b0 + 16 nt + col is this lane's own
   }
   if constexpr (ACC) {
     const int rank = pat ? atomicAdd(&cnt[best], 1) : 0;
@@ -344,10 +358,11 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
     }
     __syncthreads();
     if (pat) {
+      // the block's own deviation vector (the B operands hold other blocks')
+      const float4 *src = reinterpret_cast<const float4 *>(a.dev + 16 * gb);
       float4 *dst = reinterpret_cast<float4 *>(sorted + 16 * (off[best] + rank));
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        dst[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+      for (int q = 0; q < 4; ++q) dst[q] = src[q];
     }
     __syncthreads();
     float *part = a.part + (img * a.groups + blockIdx.x) * (int64_t)k * 17;
