@@ -202,11 +202,13 @@ void MixedStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_
 }
 
 hipError_t MixedStep::prepare() const {
-  // dynamic LDS above the default 64 KB needs an explicit opt-in per function
+  // dynamic LDS above the default 64 KB needs an explicit opt-in per function;
+  // the attribute is the function's, so it is set to the whole LDS of a CU
+  // (a plan needing less must not lower it under another plan)
   for (int sw = 0; sw < 4; ++sw)
     if (fn_sw[sw]) {
       const hipError_t e =
-          hipFuncSetAttribute(fn_sw[sw], hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+          hipFuncSetAttribute(fn_sw[sw], hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
       if (e != hipSuccess) return e;
     }
   return hipSuccess;

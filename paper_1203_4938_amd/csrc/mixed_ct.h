@@ -46,8 +46,11 @@ struct CtArgs {
   float scale;
 };
 
+// The first pass also stores this thread's entry `tv` of the pass-twiddle
+// table (loaded by the caller before the tile's data loads) at twl[tid]
+// once its data loads are issued; its closing barrier publishes the table.
 template <int L, int PP, int MAP, int OMAP, bool TW4, int SW>
-__device__ __forceinline__ void ct_pass(const CtArgs &a, lcf *lds, const lcf *twl) {
+__device__ __forceinline__ void ct_pass(const CtArgs &a, lcf *lds, lcf *twl, cf tv) {
   using PL = CtPlan<L>;
   constexpr int R = PL::R(PP), NS = PL::NS(PP), M = L / R, T = PL::T;
   constexpr int QM = (M + T - 1) / T;
@@ -67,6 +70,9 @@ __device__ __forceinline__ void ct_pass(const CtArgs &a, lcf *lds, const lcf *tw
       else
         v[q][r] = ldc(lds, ct_idx<L, MAP>(a.C, a.c, b + r * M));
     }
+  }
+  if constexpr (FIRST) {
+    if ((int)threadIdx.x < PL::NTW) stc(twl, (int)threadIdx.x, tv);
   }
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
@@ -130,14 +136,14 @@ __device__ __forceinline__ void ct_pass(const CtArgs &a, lcf *lds, const lcf *tw
 }
 
 template <int L, int MAP, int OMAP, bool TW4, int SW, int... PP>
-__device__ __forceinline__ void ct_passes(const CtArgs &a, lcf *lds, const lcf *twl,
+__device__ __forceinline__ void ct_passes(const CtArgs &a, lcf *lds, lcf *twl, cf tv,
                                           std::integer_sequence<int, PP...>) {
-  (ct_pass<L, PP, MAP, OMAP, TW4, SW>(a, lds, twl), ...);
+  (ct_pass<L, PP, MAP, OMAP, TW4, SW>(a, lds, twl, tv), ...);
 }
 
 // One tile through every pass.  `tw` is the per-pass table in global memory,
-// copied to LDS at twl (after the tile data); the barrier that ends the first
-// pass (which has no twiddles) publishes it.
+// copied to LDS at twl (after the tile data) while the first pass (which has
+// no twiddles) loads the tile; the barrier that ends that pass publishes it.
 // The arguments travel as scalars (a structure passed to a function that is
 // not inlined would live in scratch memory); the uniform ones are moved to
 // scalar registers.
@@ -167,8 +173,12 @@ __device__ __noinline__ void ct_tile(const gcf *src, gcf *dst, gcf *dst2, const 
   a.line = line;
   a.scale = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(scale)));
   nthreads = __builtin_amdgcn_readfirstlane(nthreads);
-  for (int i = threadIdx.x; i < PL::NTW; i += nthreads) stc(twl, i, ldc(tw, i));
-  ct_passes<L, MAP, OMAP, TW4, SW>(a, lds, twl, std::make_integer_sequence<int, PL::P>{});
+  // pass twiddles: entry tid is loaded now and stored by the first pass after
+  // the data loads are issued; entries past the first nthreads are copied here
+  for (int i = threadIdx.x + nthreads; i < PL::NTW; i += nthreads) stc(twl, i, ldc(tw, i));
+  cf tv = make_float2(0.0f, 0.0f);
+  if ((int)threadIdx.x < PL::NTW && (int)threadIdx.x < nthreads) tv = ldc(tw, threadIdx.x);
+  ct_passes<L, MAP, OMAP, TW4, SW>(a, lds, twl, tv, std::make_integer_sequence<int, PL::P>{});
   if constexpr (OMAP != MAP) {
     if (a.valid2) {
 #pragma unroll 4

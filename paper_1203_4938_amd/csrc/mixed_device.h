@@ -83,9 +83,13 @@ __device__ __forceinline__ cf tw4_lookup_m(const MixedArgs &a, uint32_t e) {
 // radix gets its own register allocation; its context travels as plain
 // scalars and address-space-qualified pointers.  `tw2` is the two-level
 // table of w_L held in LDS.
+// The first pass also copies the first `ntw` entries of the global table tw2g
+// into tw2 (one per thread): their loads are issued before the tile's data
+// loads and their LDS stores after them, so the copy adds no round trip of its
+// own (the pass's closing barrier publishes the table to the later passes).
 template <int MAP, int OMAP, bool TW4, int SW, int R>
 __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__restrict__ dst,
-                                        lcf *lds, const lcf *tw2,
+                                        lcf *lds, lcf *tw2, const gcf *__restrict__ tw2g, int ntw,
                                         const gcf *__restrict__ tw4_lo,
                                         const gcf *__restrict__ tw4_hi, int L, int T, int C,
                                         int pitch, int NS, int tw2_shift, int tw4_shift, int c,
@@ -135,12 +139,17 @@ __device__ __noinline__ void mixed_pass(const gcf *__restrict__ src, gcf *__rest
     }
   }
   if (first) {
+    ntw = __builtin_amdgcn_readfirstlane(ntw);
+    const int tid = (int)threadIdx.x;
+    cf tv = make_float2(0.0f, 0.0f);
+    if (tid < ntw) tv = ldc(tw2g, tid);
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
       if (!act[q]) continue;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = ldc(src, (uint32_t)(j + T * q + r * M) * ie);
     }
+    if (tid < ntw) stc(tw2, tid, tv);
   } else {
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
@@ -248,17 +257,20 @@ __device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &
     if (t.valid && t.j == 0) t.dst[0] = t.src[0];
     return;
   }
-  // pass twiddles to LDS; the barrier that ends the first pass publishes them
-  // before the second pass reads any
+  // pass twiddles to LDS: the first pass copies one entry per thread (see
+  // mixed_pass), entries past the first nthreads are copied here; the barrier
+  // that ends the first pass publishes them before the second pass reads any
   lcf *twl = as_lds(lds) + sh.tw_lds;
   const int ntw = tw2_entries(sh.L, sh.tw2_shift);
-  for (int i = threadIdx.x; i < ntw; i += nthreads) stc(twl, i, sh.tw2[i]);
+  for (int i = threadIdx.x + nthreads; i < ntw; i += nthreads) stc(twl, i, sh.tw2[i]);
+  const int ntw0 = ntw < nthreads ? ntw : nthreads;
   int ns = 1;
   for (int p = 0; p < sh.P; ++p) {
     const bool first = p == 0, last = p == sh.P - 1;
     const int R = (int)((sh.codes >> (5 * p)) & 31u);
 #define PASS(RR)                                                                                 \
   mixed_pass<MAP, OMAP, TW4, SW, RR>(as_glb(t.src), as_glb(t.dst), as_lds(lds), twl,            \
+                                     as_glb(sh.tw2), ntw0,                                       \
                                      as_glb(sh.tw4_lo), as_glb(sh.tw4_hi), sh.L, sh.T, sh.C,      \
                                      sh.pitch, ns, sh.tw2_shift, sh.tw4_shift, t.c, t.j, t.valid, \
                                      first, last, t.in_e, t.out_e, t.line, sh.scale)

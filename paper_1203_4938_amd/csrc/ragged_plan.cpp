@@ -68,13 +68,17 @@ struct RaggedStep : Step {
   }
 
   hipError_t prepare() const override {
-    // dynamic LDS above the default 64 KB needs an explicit opt-in per function
+    // dynamic LDS above the default 64 KB needs an explicit opt-in per
+    // function; the attribute belongs to the function, not to this plan, so it
+    // is set to the class's budget (a plan needing less must not lower it
+    // under another plan that needs more)
     for (bool inv : {false, true}) {
       hipError_t e = hipFuncSetAttribute(ragged_kernel(inv, false),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kRaggedLdsBytes);
       if (e == hipSuccess && n_big > 0)
         e = hipFuncSetAttribute(ragged_kernel(inv, true),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_big);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kRaggedBigLdsBytes);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;

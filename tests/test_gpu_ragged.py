@@ -67,6 +67,22 @@ def test_ragged_graph_replays_with_eager_work_between():
         assert e <= TOL_FP32
 
 
+def test_plans_with_different_lds_needs_coexist():
+    """A plan whose 1024-thread items need less LDS, built after one that
+    needs more, leaves the first plan runnable (the kernels' LDS limit is set
+    to the class budget, not to the last plan's need)."""
+    import paper_1203_4938_amd as dp
+    big, small = [16384, 15625, 16000, 16384], [5000, 5120, 6000, 5103]
+    fa, oa = synth.uniform_ragged(synth.BASE_SEED + 803, big)
+    fb, ob = synth.uniform_ragged(synth.BASE_SEED + 804, small)
+    pa = dp.Plan(ragged_sizes=big)
+    pb = dp.Plan(ragged_sizes=small)
+    say(f"[lds coexist] {pa.describe()} | {pb.describe()}")
+    for p, f, sz, of in ((pb, fb, small, ob), (pa, fa, big, oa)):
+        y = p.exec(to_dev(f)).cpu().numpy()
+        assert _ragged_errors(y, f, sz, of, False).max() <= TOL_FP32
+
+
 def test_ragged_with_gaps_and_explicit_offsets():
     import paper_1203_4938_amd as dp
     sizes = [100, 7, 20480, 64]
