@@ -173,14 +173,19 @@ __global__ void __launch_bounds__(NTH, NTH == kRaggedThreads ? 4 : 1)
     ragged_item<INV, NTH>(in, out, a, items[ragged_slot(blockIdx.x, gridDim.x)], lds);
     return;
   }
+  // walk q = blockIdx.x, + gridDim.x, ...: with a grid that is a multiple of
+  // 8, workgroup q mod gridDim sits on XCD q mod 8, so the same round mapping
+  // as the direct mode keeps neighbouring items on one XCD
+  const uint32_t n = (uint32_t)a.nitems;
+  const bool remap = gridDim.x % 8u == 0u;
   int q = (int)blockIdx.x;
   if (q >= a.nitems) return;
-  RaggedItem d = items[q];
+  RaggedItem d = items[remap ? ragged_slot((uint32_t)q, n) : (uint32_t)q];
   for (;;) {
     const int qn = q + (int)gridDim.x;
     // the next descriptor is in flight while this item runs
     RaggedItem dn = d;
-    if (qn < a.nitems) dn = items[qn];
+    if (qn < a.nitems) dn = items[remap ? ragged_slot((uint32_t)qn, n) : (uint32_t)qn];
     ragged_item<INV, NTH>(in, out, a, d, lds);
     if (qn >= a.nitems) break;
     __syncthreads();  // the next item reuses the LDS
