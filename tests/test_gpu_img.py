@@ -74,7 +74,8 @@ def pattern_images(seed, B, h, w, k):
     return synth.blocks_to_grey_rgb(synth.pattern_set(seed, k), pick.reshape(B, h // 4, w // 4))
 
 
-@pytest.mark.parametrize("k,iters", [(8, 0), (8, 1), (16, 5), (64, 10), (256, 3)])
+@pytest.mark.parametrize("k,iters", [(8, 0), (8, 1), (16, 5), (64, 10), (256, 3), (5, 4), (17, 3),
+                                     (100, 6)])
 def test_pattern_images_exact(k, iters):
     """Images of exact copies of k random patterns, seeded one codeword per
     pattern: every block's nearest codeword is decided by a wide margin, so
