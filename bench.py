@@ -299,7 +299,7 @@ def build_img(dp, torch, synth, dev):
     B, h, w, k, iters, tau = 16, 2048, 2048, 64, 8, 8.0
     rgb = torch.from_numpy(synth.images_rgb(synth.BASE_SEED + 7, B, h, w)).to(dev)
     first = dp.img_compress(rgb, k, iters, tau)
-    d = dp.ImgDesc(height=h, width=w, batch=B, k=k, iters=iters, tau=tau)
+    d = dp.ImgDesc(height=h, width=w, batch=B, k=k, iters=iters, tau=tau, flags=dp.IMG_F_GRAPH)
     o = dp.ImgOut(*(first[n].data_ptr() for n in ("y", "cb", "cr", "mean", "act", "dev",
                                                    "codebook", "code")))
     ws = first["_workspace"]
@@ -315,7 +315,8 @@ def build_img(dp, torch, synth, dev):
     item = MultiItem(torch, "img2048_b16_block_compress", run, run,
                      float(nb * k * 48 * (iters + 1)), (18.5 + 4.25 * iters) * npx,
                      f"img_compress: {B} RGB images {h}x{w}, k={k}, {iters} Lloyd iterations, "
-                     f"tau={tau}; GFLOP/s counts the codeword distances of every block")
+                     f"tau={tau}, replayed as a HIP graph (IMG_F_GRAPH); GFLOP/s counts the "
+                     f"codeword distances of every block")
     item.keep = (rgb, first)
     return item
 

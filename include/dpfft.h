@@ -258,7 +258,15 @@ typedef struct {
   int32_t k;             /* codewords, 1..256 */
   int32_t iters;         /* Lloyd iterations, 0..10000 (0: the seeds) */
   float tau;             /* activity threshold of pattern blocks */
+  uint32_t flags;        /* IMG_F_* (0: launch the kernels one by one) */
 } img_desc_t;
+
+/* img_compress: replay the launch sequence as a HIP graph.  A graph is
+ * instantiated on the first call for a given (descriptor, buffers, stream,
+ * device) and kept for later calls with the same arguments (the 8 most
+ * recent are kept); it saves the gaps between the 4 + 2 iters + 1 dependent
+ * launches, so it pays off when the same call repeats. */
+#define IMG_F_GRAPH 1u
 
 /* Outputs of img_compress: caller-owned device buffers, per image back to back.
  *   y        batch x height x width          float32, 16-byte aligned

@@ -45,11 +45,15 @@ class FftDesc(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
+IMG_F_GRAPH = 1
+
+
 class ImgDesc(ctypes.Structure):
     """img_desc_t: images height x width (multiples of 4), batch, codewords k,
     Lloyd iterations, activity threshold tau."""
     _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("k", ctypes.c_int32), ("iters", ctypes.c_int32), ("tau", ctypes.c_float)]
+                ("k", ctypes.c_int32), ("iters", ctypes.c_int32), ("tau", ctypes.c_float),
+                ("flags", ctypes.c_uint32)]
 
 
 class ImgOut(ctypes.Structure):
@@ -149,18 +153,21 @@ def img_workspace_bytes(desc: ImgDesc) -> int:
     return _lib.img_workspace_bytes(ctypes.byref(desc))
 
 
-def img_compress(rgb: torch.Tensor, k: int, iters: int, tau: float, stream=None) -> dict:
+def img_compress(rgb: torch.Tensor, k: int, iters: int, tau: float, stream=None,
+                 graph: bool = False) -> dict:
     """Image block compression of a batch of RGB images (uint8 CUDA tensor of
     shape (batch, height, width, 3) or (height, width, 3)): returns the
     outputs of img_compress as tensors y, cb, cr, mean, act, dev, codebook,
-    code."""
+    code.  graph=True sets IMG_F_GRAPH (pays off only for repeated calls on
+    the same buffers; this function allocates new outputs per call)."""
     if rgb.dim() == 3:
         rgb = rgb.unsqueeze(0)
     if rgb.dtype != torch.uint8 or rgb.device.type != "cuda" or not rgb.is_contiguous() or \
             rgb.dim() != 4 or rgb.shape[-1] != 3:
         raise ValueError("rgb must be a contiguous uint8 CUDA tensor (batch, height, width, 3)")
     B, h, w = (int(v) for v in rgb.shape[:3])
-    d = ImgDesc(height=h, width=w, batch=B, k=int(k), iters=int(iters), tau=float(tau))
+    d = ImgDesc(height=h, width=w, batch=B, k=int(k), iters=int(iters), tau=float(tau),
+                flags=IMG_F_GRAPH if graph else 0)
     dev = rgb.device
     f32 = dict(dtype=torch.float32, device=dev)
     nb = (h // 4) * (w // 4)

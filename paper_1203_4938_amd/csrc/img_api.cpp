@@ -3,7 +3,10 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dpfft.h"
 #include "img.h"
@@ -44,6 +47,7 @@ fft_status_t check_desc(const img_desc_t *d) {
   if (d->k < 1 || d->k > kImgMaxK) return fail(FFT_E_INVALID, "k must be in [1, 256]");
   if (d->iters < 0 || d->iters > 10000) return fail(FFT_E_INVALID, "iters must be in [0, 10000]");
   if (!isfinite(d->tau)) return fail(FFT_E_INVALID, "tau must be finite");
+  if (d->flags & ~IMG_F_GRAPH) return fail(FFT_E_INVALID, "unknown img flags");
   return FFT_OK;
 }
 
@@ -64,6 +68,97 @@ hipError_t launch(const void *fn, dim3 grid, int threads, ImgArgs &a, hipStream_
                   size_t lds = 0) {
   void *kargs[] = {(void *)&a};
   return hipLaunchKernel(fn, grid, dim3(threads), kargs, lds, s);
+}
+
+struct Launch {
+  const void *fn;
+  dim3 grid;
+  int threads;
+  size_t lds;
+};
+
+// The launches of steps (a)-(e), in order: front end, pattern counts, their
+// scan, seeds, iters x (assignment with cluster sums, codebook update), codes.
+std::vector<Launch> sequence(const img_desc_t *d, const ImgArgs &a) {
+  const unsigned B = (unsigned)d->batch;
+  const int64_t tiles = ((a.w + kImgTileW - 1) / kImgTileW) * ((a.h + kImgTileH - 1) / kImgTileH);
+  const dim3 gb((unsigned)a.groups, B), gu((unsigned)a.k, B);
+  std::vector<Launch> v;
+  v.push_back({img_kernel_front(), dim3((unsigned)tiles, B), kImgThreads, 0});
+  v.push_back({img_kernel_count(), gb, kImgBlocksPerGroup, 0});
+  v.push_back({img_kernel_scan(), dim3(B), 256, 0});
+  v.push_back({img_kernel_seed(), gb, kImgBlocksPerGroup, 0});
+  for (int it = 0; it < d->iters; ++it) {
+    v.push_back({img_kernel_assign(true), gb, kImgBlocksPerGroup, img_assign_lds_bytes(a.k, true)});
+    v.push_back({img_kernel_update(), gu, 256, 0});
+  }
+  v.push_back({img_kernel_assign(false), gb, kImgBlocksPerGroup, img_assign_lds_bytes(a.k, false)});
+  return v;
+}
+
+// Instantiated graphs of the sequence, most recent first (IMG_F_GRAPH).
+struct GraphKey {
+  img_desc_t d;
+  const void *ptr[11];
+  hipStream_t stream;
+  int device;
+  bool operator==(const GraphKey &o) const {
+    return d.height == o.d.height && d.width == o.d.width && d.batch == o.d.batch &&
+           d.k == o.d.k && d.iters == o.d.iters && d.tau == o.d.tau &&
+           std::equal(ptr, ptr + 11, o.ptr) && stream == o.stream && device == o.device;
+  }
+};
+constexpr size_t kMaxImgGraphs = 8;
+std::mutex g_mu;
+std::vector<std::pair<GraphKey, hipGraphExec_t>> g_graphs;
+
+hipError_t run_graph(const GraphKey &key, const std::vector<Launch> &seq, ImgArgs &a,
+                     hipStream_t s) {
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (size_t i = 0; i < g_graphs.size(); ++i)
+      if (g_graphs[i].first == key) {
+        std::rotate(g_graphs.begin(), g_graphs.begin() + i, g_graphs.begin() + i + 1);
+        exec = g_graphs[0].second;
+        break;
+      }
+  }
+  if (!exec) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    hipGraphNode_t prev = nullptr;
+    for (const Launch &l : seq) {
+      void *kargs[] = {(void *)&a};  // copied into the node
+      hipKernelNodeParams p{};
+      p.func = const_cast<void *>(l.fn);
+      p.gridDim = l.grid;
+      p.blockDim = dim3(l.threads);
+      p.sharedMemBytes = (unsigned)l.lds;
+      p.kernelParams = kargs;
+      hipGraphNode_t node = nullptr;
+      e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+      if (e != hipSuccess) break;
+      prev = node;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_graphs.size() >= kMaxImgGraphs) {
+      // the evicted graph may still be running on its stream
+      const hipError_t se = hipStreamSynchronize(g_graphs.back().first.stream);
+      if (se != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return se;
+      }
+      (void)hipGraphExecDestroy(g_graphs.back().second);
+      g_graphs.pop_back();
+    }
+    g_graphs.insert(g_graphs.begin(), {key, exec});
+  }
+  return hipGraphLaunch(exec, s);
 }
 
 }  // namespace
@@ -106,20 +201,23 @@ fft_status_t img_compress(const img_desc_t *desc, const uint8_t *rgb, const img_
   a.npat = (int32_t *)(ws + L.npat);
   a.part = (float *)(ws + L.part);
   hipStream_t s = (hipStream_t)hip_stream;
-  const unsigned B = (unsigned)desc->batch;
-  const int64_t tiles = ((a.w + kImgTileW - 1) / kImgTileW) * ((a.h + kImgTileH - 1) / kImgTileH);
-  const dim3 gb((unsigned)a.groups, B);
-  hipError_t e = launch(img_kernel_front(), dim3((unsigned)tiles, B), kImgThreads, a, s);
-  if (e == hipSuccess) e = launch(img_kernel_count(), gb, kImgBlocksPerGroup, a, s);
-  if (e == hipSuccess) e = launch(img_kernel_scan(), dim3(B), 256, a, s);
-  if (e == hipSuccess) e = launch(img_kernel_seed(), gb, kImgBlocksPerGroup, a, s);
-  const dim3 gu((unsigned)a.k, B);
-  for (int it = 0; it < desc->iters && e == hipSuccess; ++it) {
-    e = launch(img_kernel_assign(true), gb, kImgBlocksPerGroup, a, s, img_assign_lds_bytes(a.k, true));
-    if (e == hipSuccess) e = launch(img_kernel_update(), gu, 256, a, s);
+  const std::vector<Launch> seq = sequence(desc, a);
+  hipError_t e = hipSuccess;
+  if (desc->flags & IMG_F_GRAPH) {
+    GraphKey key{};
+    key.d = *desc;
+    const void *ptrs[11] = {rgb, out->y, out->cb, out->cr, out->mean, out->act,
+                            out->dev, out->codebook, out->code, workspace, nullptr};
+    std::copy(ptrs, ptrs + 11, key.ptr);
+    key.stream = s;
+    e = hipGetDevice(&key.device);
+    if (e == hipSuccess) e = run_graph(key, seq, a, s);
+  } else {
+    for (const Launch &l : seq) {
+      e = launch(l.fn, l.grid, l.threads, a, s, l.lds);
+      if (e != hipSuccess) break;
+    }
   }
-  if (e == hipSuccess)
-    e = launch(img_kernel_assign(false), gb, kImgBlocksPerGroup, a, s, img_assign_lds_bytes(a.k, false));
   if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return FFT_OK;
 }

@@ -114,7 +114,7 @@ def test_img_descriptors_rejected_before_device():
     ok = dict(height=64, width=64, batch=2, k=16, iters=3, tau=1.0)
     assert dp.img_workspace_bytes(dp.ImgDesc(**ok)) > 0
     for bad in (dict(height=62), dict(width=0), dict(batch=-1), dict(k=0), dict(k=257),
-                dict(iters=-1), dict(tau=float("nan"))):
+                dict(iters=-1), dict(tau=float("nan")), dict(flags=2)):
         d = dp.ImgDesc(**{**ok, **bad})
         assert dp.img_workspace_bytes(d) == 0
         assert dp._lib.img_compress(ctypes.byref(d), None, None, None, None) == dp.FFT_E_INVALID

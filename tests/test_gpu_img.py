@@ -95,6 +95,39 @@ def test_pattern_images_exact(k, iters):
         f"{np.abs(g['codebook'][-1] - book).max():.1e}")
 
 
+def test_graph_replays_match_direct_launches():
+    """IMG_F_GRAPH: the launch sequence replayed from a HIP graph on the same
+    buffers, three times with eager work between the replays and the outputs
+    overwritten before each, gives exactly the outputs of the direct launches
+    (pattern images: every cluster sum adds copies of one vector, so no
+    rounding depends on the order of the additions)."""
+    import ctypes
+
+    import torch
+    dp = _dp()
+    k, iters, B, h, w = 16, 4, 2, 64, 128
+    rgb = torch.from_numpy(pattern_images(synth.BASE_SEED + 930, B, h, w, k)).cuda()
+    ref = dp.img_compress(rgb, k, iters, 0.0)
+    torch.cuda.synchronize()
+    ref_np = {n: t.cpu().numpy() for n, t in ref.items() if not n.startswith("_")}
+    out = {n: torch.empty_like(t) for n, t in ref.items() if not n.startswith("_")}
+    ws = torch.empty_like(ref["_workspace"])
+    names = ("y", "cb", "cr", "mean", "act", "dev", "codebook", "code")
+    o = dp.ImgOut(*(out[n].data_ptr() for n in names))
+    d = dp.ImgDesc(height=h, width=w, batch=B, k=k, iters=iters, tau=0.0, flags=dp.IMG_F_GRAPH)
+    for rep in range(3):
+        for t in out.values():
+            t.fill_(7)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        st = dp._lib.img_compress(ctypes.byref(d), ctypes.c_void_p(rgb.data_ptr()), ctypes.byref(o),
+                                  ctypes.c_void_p(ws.data_ptr()), None)
+        assert st == dp.FFT_OK, dp.fft_last_error()
+        torch.cuda.synchronize()
+        for n in names:
+            assert np.array_equal(out[n].cpu().numpy(), ref_np[n]), (rep, n)
+        say(f"[img graph] replay {rep}: outputs equal the direct launches (junk {float(junk):.1f})")
+
+
 def _valid_codes(gcode, dev, act, tau, book, act_eps=1e-3, rel_eps=1e-4):
     """Codes the oracle would accept: equal to its own, or a decision within
     FP32's reach of a tie (activity within act_eps of tau, or a codeword whose
