@@ -61,7 +61,12 @@ typedef enum {
 /* Arithmetic of the transform. FP32: float32 butterflies everywhere.  The
  * *_MFMA forms run the DFT-16 stages as FP16/BF16 matrix products on the
  * matrix cores with FP32 accumulation; *_SPLIT forms split inputs and
- * twiddles into hi + lo pieces to recover FP32-level accuracy. */
+ * twiddles into hi + lo pieces to recover FP32-level accuracy.  Lengths of
+ * the matrix-core forms (rank 1, not ragged, complex): N = 256 (one pass of
+ * 16 x 16), N = 65536 (both four-step passes of 256 points on the matrix
+ * cores), and N = 256 N2 with N2 a power of two from 64 to 4096 (the
+ * 256-point column pass on the matrix cores, the N2-point row pass in FP32);
+ * other lengths return FFT_E_UNSUPPORTED. */
 typedef enum {
   FFT_FP32 = 0,
   FFT_FP16_MFMA = 1,

@@ -725,7 +725,10 @@ std::unique_ptr<MfmaStep> make_mfma(dpfft_plan_s *P, const char *name, int prec,
   return s;
 }
 
-// Matrix-core plans: N = 256 (one pass) and N = 65536 (four-step 256 x 256).
+// Matrix-core plans: N = 256 (one pass), N = 65536 (four-step 256 x 256 with
+// both passes on the matrix cores), and N = 256 N2 for N2 = 64 .. 4096 (the
+// 256-point column pass on the matrix cores, the N2-point transposed-row pass
+// with the FP32 line kernels).
 fft_status_t plan_mfma_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch, D = P->dist;
   const int prec = P->precision;
@@ -744,8 +747,58 @@ fft_status_t plan_mfma_1d(dpfft_plan_s *P) {
     P->variant = "mfma single-pass";
     return FFT_OK;
   }
-  if (N != 65536)
-    return fail(FFT_E_UNSUPPORTED, "MFMA precision forms support N = 256 and N = 65536");
+  const int64_t N2 = N / 256;
+  if (N % 256 != 0 || N2 < 64 || N2 > 4096 || (N2 & (N2 - 1)) != 0)
+    return fail(FFT_E_UNSUPPORTED, "MFMA precision forms support N = 256 and N = 256 N2 with N2 "
+                                   "a power of two from 64 to 4096");
+  if (N2 != 256) {
+    const Override ov = read_override();
+    const int lg = ilog2(N);
+    auto a = make_mfma(P, "mfma_fourstep_columns", prec, LINE_FAST, LINE_FAST, true);
+    auto b = make_line(P, "fourstep_rows_transposed", (int)N2, ELEM_FAST, LINE_FAST, false, 16, 1,
+                       B * 256, ov);
+    if (!b) return fail(FFT_E_UNSUPPORTED, "no transposed-row kernel for N2=" + std::to_string(N2));
+    std::vector<std::complex<double>> lo, hi;
+    const int shift = (lg + 1) / 2;
+    fourstep_tables(N, shift, lo, hi);
+    a->tw4_lo_off = P->tables.add(lo);
+    a->tw4_hi_off = P->tables.add(hi);
+    a->a.tw4_shift = shift;
+    a->a.in_b = D;
+    a->a.in_l = 1;
+    a->a.in_e = N2;
+    a->a.out_b = N;
+    a->a.out_l = 1;
+    a->a.out_e = N2;
+    a->a.lines = N2;
+    a->a.tiles_per_batch = (N2 + C - 1) / C;
+    a->a.flags = F_REMAP | F_ROUNDS;
+    a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
+    a->first = true;
+    a->src = BUF_IN;
+    a->dst = BUF_WS;
+    const int CB = b->k.lines;
+    b->a.in_b = N;
+    b->a.in_l = N2;
+    b->a.in_e = 1;
+    b->a.out_b = D;
+    b->a.out_l = 1;
+    b->a.out_e = 256;
+    b->a.lines = 256;
+    b->a.tiles_per_batch = 256 / CB;
+    b->a.flags = F_REMAP | F_ROUNDS;
+    b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
+    b->a.ntiles = b->grid.x;
+    b->last = true;
+    b->inv_scale = (float)(1.0 / (double)N);
+    b->src = BUF_WS;
+    b->dst = BUF_OUT;
+    P->steps.push_back(std::move(a));
+    P->steps.push_back(std::move(b));
+    P->ws_bytes = (size_t)B * (size_t)N * sizeof(float2);
+    P->variant = "mfma four-step 256x" + std::to_string(N2) + " (matrix-core columns, FP32 rows)";
+    return FFT_OK;
+  }
   auto a = make_mfma(P, "mfma_fourstep_columns", prec, LINE_FAST, LINE_FAST, true);
   auto b = make_mfma(P, "mfma_fourstep_rows_transposed", prec, ELEM_FAST, LINE_FAST, false);
   std::vector<std::complex<double>> lo, hi;

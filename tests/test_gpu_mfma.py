@@ -53,8 +53,11 @@ def _check(prec, x, inverse_input=None):
 
 
 @pytest.mark.parametrize("prec", FORMS)
-@pytest.mark.parametrize("n,batch", [(256, 37), (65536, 3)])
+@pytest.mark.parametrize("n,batch", [(256, 37), (65536, 3), (1 << 14, 5), (1 << 15, 3), (1 << 18, 2),
+                                     (1 << 20, 1)])
 def test_mfma_forms(prec, n, batch):
+    """N = 256 and 65536 on the matrix cores throughout; N = 256 N2 for other
+    N2 (the 256-point column pass on the matrix cores, the rows in FP32)."""
     x = synth.uniform_complex(synth.BASE_SEED + 700, n, batch)
     _gate(prec, _check(prec, x), f"n={n} uniform")
 
@@ -76,7 +79,7 @@ RANGES = {
 
 @pytest.mark.parametrize("prec", FORMS)
 @pytest.mark.parametrize("case", sorted(RANGES))
-@pytest.mark.parametrize("n", [256, 65536])
+@pytest.mark.parametrize("n", [256, 65536, 1 << 18])
 def test_mfma_input_range(prec, case, n):
     base = synth.uniform_complex(synth.BASE_SEED + 702, n, 4)
     x = RANGES[case](base)

@@ -58,6 +58,15 @@ def test_workspace_sizes():
 def test_mfma_forms_plan():
     t = _dry(n=65536, batch=4096, precision="bf16_split3")
     assert "mfma four-step 256x256" in t and "bf16_split3" in t
+    # N = 256 N2: matrix-core columns, FP32 transposed rows of N2
+    t = _dry(n=1 << 18, batch=2, precision="fp16_split")
+    assert "mfma four-step 256x1024 (matrix-core columns, FP32 rows)" in t
+    assert "fourstep_rows_transposed: L=1024" in t, t
+    dp = _dp()
+    for n in (4096, 1 << 21, 3 * 256):
+        d, keep = dp.make_desc(n=n, batch=2, precision="fp16")
+        st, text = dp.fft_plan_dry(d)
+        assert st == dp.FFT_E_UNSUPPORTED, (n, text)
 
 
 def test_ragged_plan_counts():
