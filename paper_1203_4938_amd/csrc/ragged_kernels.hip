@@ -1,23 +1,25 @@
-// Persistent ragged-batch kernel.
+// Ragged-batch kernel.
 //
-// The work items of a ragged batch are listed largest first; a launch of
-// resident workgroups walks that list with a static stride (workgroup w runs
-// items w, w + grid, w + 2 grid, ...), so no workgroup ever waits on a shared
-// counter and each can fetch the descriptor of its next item while it works on
-// the current one.  Signals too long for one workgroup are split into
-// column-pass and row-pass tiles of a four-step transform.  The row tiles of a
-// signal need every column tile of it, and publishing data from one workgroup
-// to another inside a launch would take an agent-scope fence per tile (a
-// write-back of the XCD's whole L2 on this chip), so the batch runs as two such
-// launches back to back: the first over the single-pass items and column
-// tiles, the second over the row tiles.  The kernel boundary orders them.
-//
+// The work items of a ragged batch are self-contained: a group of whole
+// single-pass signals, or a column or row tile of a long signal's four-step
+// transform.  Each launch covers one list of items, largest first, with one
+// workgroup per item dispatched by the hardware (a new workgroup starts as
+// soon as one retires); the items are dealt to the XCDs in rounds so that a
+// signal's neighbouring tiles run side by side in one L2 (ragged_slot).  The
+// row tiles of a signal need every column tile of it, and publishing data
+// from one workgroup to another inside a launch would take an agent-scope
+// fence per tile (a write-back of the XCD's whole L2 on this chip), so the
+// column tiles (with the single-pass signals of 256-thread workgroups) and
+// the row tiles are two launches and the kernel boundary orders them.
 // Single-pass signals too long for a 256-thread workgroup (up to 16384
 // points: 16 elements per thread, 1024 threads, up to 160 KB of LDS) run in a
-// launch of their own with the 1024-thread instance, before the other two.
+// third launch with the 1024-thread instance, which needs nothing from the
+// other two.
 //
-// In direct mode the kernel runs item first_item + blockIdx.x and stops; the
-// per-length baseline launches it once per distinct length.
+// Optionally (persistent mode) a launch of resident workgroups walks its list
+// with a static stride (workgroup w runs items w, w + grid, w + 2 grid, ...),
+// fetching the descriptor of its next item while it works on the current one.
+// The per-length baseline launches the kernel once per distinct length.
 #include "mixed_ct.h"
 #include "mixed_device.h"
 #include "ragged.h"
