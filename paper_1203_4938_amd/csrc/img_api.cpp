@@ -109,22 +109,38 @@ struct GraphKey {
   }
 };
 constexpr size_t kMaxImgGraphs = 8;
+struct CachedGraph {
+  GraphKey key;
+  hipGraphExec_t exec;
+  hipEvent_t done;  // recorded after every launch; an evicted graph waits on it
+};
 std::mutex g_mu;
-std::vector<std::pair<GraphKey, hipGraphExec_t>> g_graphs;
+std::vector<CachedGraph> g_graphs;
+
+// launch a cached graph and record its completion (under g_mu, so that no
+// other thread evicts it in between)
+hipError_t launch_cached_locked(const CachedGraph &c, hipStream_t s) {
+  hipError_t e = hipGraphLaunch(c.exec, s);
+  if (e == hipSuccess) e = hipEventRecord(c.done, s);
+  return e;
+}
 
 hipError_t run_graph(const GraphKey &key, const std::vector<Launch> &seq, ImgArgs &a,
                      hipStream_t s) {
-  hipGraphExec_t exec = nullptr;
+  auto find = [&]() -> const CachedGraph * {
+    for (size_t i = 0; i < g_graphs.size(); ++i)
+      if (g_graphs[i].key == key) {
+        std::rotate(g_graphs.begin(), g_graphs.begin() + i, g_graphs.begin() + i + 1);
+        return &g_graphs[0];
+      }
+    return nullptr;
+  };
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    for (size_t i = 0; i < g_graphs.size(); ++i)
-      if (g_graphs[i].first == key) {
-        std::rotate(g_graphs.begin(), g_graphs.begin() + i, g_graphs.begin() + i + 1);
-        exec = g_graphs[0].second;
-        break;
-      }
+    if (const CachedGraph *c = find()) return launch_cached_locked(*c, s);
   }
-  if (!exec) {
+  hipGraphExec_t exec = nullptr;
+  {
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);
     if (e != hipSuccess) return e;
@@ -145,20 +161,32 @@ hipError_t run_graph(const GraphKey &key, const std::vector<Launch> &seq, ImgArg
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return e;
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (g_graphs.size() >= kMaxImgGraphs) {
-      // the evicted graph may still be running on its stream
-      const hipError_t se = hipStreamSynchronize(g_graphs.back().first.stream);
-      if (se != hipSuccess) {
-        (void)hipGraphExecDestroy(exec);
-        return se;
-      }
-      (void)hipGraphExecDestroy(g_graphs.back().second);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (const CachedGraph *other = find()) {  // built meanwhile by another thread
+    (void)hipGraphExecDestroy(exec);
+    return launch_cached_locked(*other, s);
+  }
+  hipEvent_t done = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+  if (e == hipSuccess && g_graphs.size() >= kMaxImgGraphs) {
+    // the evicted graph may still be running: wait for its last launch (the
+    // event stays valid if the caller has destroyed the stream since)
+    const CachedGraph &old = g_graphs.back();
+    e = hipEventSynchronize(old.done);
+    if (e == hipSuccess) {
+      (void)hipGraphExecDestroy(old.exec);
+      (void)hipEventDestroy(old.done);
       g_graphs.pop_back();
     }
-    g_graphs.insert(g_graphs.begin(), {key, exec});
   }
-  return hipGraphLaunch(exec, s);
+  if (e != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    if (done) (void)hipEventDestroy(done);
+    return e;
+  }
+  g_graphs.insert(g_graphs.begin(), CachedGraph{key, exec, done});
+  return launch_cached_locked(g_graphs.front(), s);
 }
 
 }  // namespace

@@ -34,8 +34,16 @@ struct GraphKey {
 
 // Instantiated graphs a plan keeps, most recently used first.  A caller that
 // rotates buffers gets a new graph per buffer set; beyond this many the
-// least recently used one is released (after its stream has drained).
+// least recently used one is released once its last launch has completed
+// (an event recorded after every launch: it stays valid if the caller has
+// destroyed the stream since).
 constexpr size_t kMaxGraphs = 8;
+
+struct CachedGraph {
+  GraphKey key;
+  hipGraphExec_t exec;
+  hipEvent_t done;
+};
 
 }  // namespace
 
@@ -61,10 +69,14 @@ struct RaggedStep : Step {
   std::vector<Range> ranges;  // per-size mode: one launch each
   std::string summary;
   mutable std::mutex mu;
-  mutable std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;  // most recent first
+  mutable std::vector<CachedGraph> graphs;  // most recent first
 
+  // (fft_destroy: no execution of the plan is pending)
   ~RaggedStep() override {
-    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipEventDestroy(g.done);
+    }
   }
 
   hipError_t prepare() const override {
@@ -85,13 +97,21 @@ struct RaggedStep : Step {
   }
 
   // the cached graph for `key`, moved to the front (nullptr if none)
-  hipGraphExec_t find_graph_locked(const GraphKey &key) const {
+  const CachedGraph *find_graph_locked(const GraphKey &key) const {
     for (size_t i = 0; i < graphs.size(); ++i)
-      if (graphs[i].first == key) {
+      if (graphs[i].key == key) {
         std::rotate(graphs.begin(), graphs.begin() + i, graphs.begin() + i + 1);
-        return graphs[0].second;
+        return &graphs[0];
       }
     return nullptr;
+  }
+
+  // launch a cached graph and record its completion event (under mu, so that
+  // no other thread evicts it in between)
+  static hipError_t launch_cached_locked(const CachedGraph &c, hipStream_t s) {
+    hipError_t e = hipGraphLaunch(c.exec, s);
+    if (e == hipSuccess) e = hipEventRecord(c.done, s);
+    return e;
   }
 
   void bind(const float2 *tables) override {
@@ -161,12 +181,12 @@ struct RaggedStep : Step {
   // direction, stream).
   hipError_t launch_graph(const ExecCtx &ctx) const {
     GraphKey key{ctx.in, ctx.out, ctx.ws, ctx.inverse, ctx.stream};
-    hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(mu);
-      exec = find_graph_locked(key);
+      if (const CachedGraph *c = find_graph_locked(key)) return launch_cached_locked(*c, ctx.stream);
     }
-    if (!exec) {
+    hipGraphExec_t exec = nullptr;
+    {
       RaggedArgs rr[3] = {args_for(ctx), args_for(ctx), args_for(ctx)};
       const float2 *s = (const float2 *)ctx.in;
       float2 *d = (float2 *)ctx.out;
@@ -200,26 +220,31 @@ struct RaggedStep : Step {
       if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return e;
-      std::lock_guard<std::mutex> lk(mu);
-      if (hipGraphExec_t other = find_graph_locked(key)) {
-        (void)hipGraphExecDestroy(exec);
-        exec = other;
-      } else {
-        if (graphs.size() >= kMaxGraphs) {
-          // the evicted graph may still be running on its stream
-          const auto &old = graphs.back();
-          const hipError_t se = hipStreamSynchronize(old.first.stream);
-          if (se != hipSuccess) {
-            (void)hipGraphExecDestroy(exec);
-            return se;
-          }
-          (void)hipGraphExecDestroy(old.second);
-          graphs.pop_back();
-        }
-        graphs.insert(graphs.begin(), {key, exec});
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (const CachedGraph *other = find_graph_locked(key)) {  // built meanwhile by another thread
+      (void)hipGraphExecDestroy(exec);
+      return launch_cached_locked(*other, ctx.stream);
+    }
+    hipEvent_t done = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e == hipSuccess && graphs.size() >= kMaxGraphs) {
+      // the evicted graph may still be running: wait for its last launch
+      const CachedGraph &old = graphs.back();
+      e = hipEventSynchronize(old.done);
+      if (e == hipSuccess) {
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipEventDestroy(old.done);
+        graphs.pop_back();
       }
     }
-    return hipGraphLaunch(exec, ctx.stream);
+    if (e != hipSuccess) {
+      (void)hipGraphExecDestroy(exec);
+      if (done) (void)hipEventDestroy(done);
+      return e;
+    }
+    graphs.insert(graphs.begin(), CachedGraph{key, exec, done});
+    return launch_cached_locked(graphs.front(), ctx.stream);
   }
 
   hipError_t launch(const ExecCtx &ctx) const override {

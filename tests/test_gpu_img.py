@@ -128,6 +128,38 @@ def test_graph_replays_match_direct_launches():
         say(f"[img graph] replay {rep}: outputs equal the direct launches (junk {float(junk):.1f})")
 
 
+def test_graph_cache_beyond_its_capacity():
+    """IMG_F_GRAPH on 10 output buffer sets (more than the 8 graphs kept),
+    then the first set again (rebuilt after its eviction): every call equals
+    the direct launches exactly (pattern images)."""
+    import ctypes
+
+    import torch
+    dp = _dp()
+    k, iters, B, h, w = 8, 2, 1, 32, 64
+    rgb = torch.from_numpy(pattern_images(synth.BASE_SEED + 931, B, h, w, k)).cuda()
+    ref = dp.img_compress(rgb, k, iters, 0.0)
+    torch.cuda.synchronize()
+    names = ("y", "cb", "cr", "mean", "act", "dev", "codebook", "code")
+    ref_np = {n: ref[n].cpu().numpy() for n in names}
+    sets = []
+    for _ in range(10):
+        out = {n: torch.empty_like(ref[n]) for n in names}
+        sets.append((out, dp.ImgOut(*(out[n].data_ptr() for n in names)),
+                     torch.empty_like(ref["_workspace"])))
+    d = dp.ImgDesc(height=h, width=w, batch=B, k=k, iters=iters, tau=0.0, flags=dp.IMG_F_GRAPH)
+    for i in list(range(10)) + [0]:
+        out, o, ws = sets[i]
+        for t in out.values():
+            t.fill_(5)
+        st = dp._lib.img_compress(ctypes.byref(d), ctypes.c_void_p(rgb.data_ptr()), ctypes.byref(o),
+                                  ctypes.c_void_p(ws.data_ptr()), None)
+        assert st == dp.FFT_OK, dp.fft_last_error()
+        torch.cuda.synchronize()
+        for n in names:
+            assert np.array_equal(out[n].cpu().numpy(), ref_np[n]), (i, n)
+
+
 def _valid_codes(gcode, dev, act, tau, book, act_eps=1e-3, rel_eps=1e-4):
     """Codes the oracle would accept: equal to its own, or a decision within
     FP32's reach of a tie (activity within act_eps of tau, or a codeword whose

@@ -67,6 +67,25 @@ def test_ragged_graph_replays_with_eager_work_between():
         assert e <= TOL_FP32
 
 
+def test_graph_cache_beyond_its_capacity():
+    """A graph plan run on 10 output buffers (more than the 8 graphs a plan
+    keeps), then on the first one again (its graph was evicted and is built
+    anew): every result matches the oracle."""
+    import torch
+
+    import paper_1203_4938_amd as dp
+    sizes = [64, 20480, 343, 1000, 49152, 7]
+    flat, offs = synth.uniform_ragged(synth.BASE_SEED + 805, sizes)
+    p = dp.Plan(ragged_sizes=sizes, graph=True)
+    x = to_dev(flat)
+    outs = [torch.empty_like(x) for _ in range(10)]
+    for i in list(range(10)) + [0, 1]:
+        outs[i].fill_(3)
+        y = p.exec(x, out=outs[i]).cpu().numpy()
+        assert _ragged_errors(y, flat, sizes, offs, False).max() <= TOL_FP32, i
+    say("[ragged graph cache] 10 buffer sets and two revisits match the oracle")
+
+
 def test_plans_with_different_lds_needs_coexist():
     """A plan whose 1024-thread items need less LDS, built after one that
     needs more, leaves the first plan runnable (the kernels' LDS limit is set
