@@ -9,6 +9,8 @@ constexpr int kImgTileW = 64;         // pixels per front-end tile, x
 constexpr int kImgTileH = 16;         // pixels per front-end tile, y
 constexpr int kImgThreads = 256;
 constexpr int kImgBlocksPerGroup = 256;  // 4x4 blocks per workgroup of the block-list kernels
+constexpr int kImgAssignBlocks = 1024;   // 4x4 blocks per workgroup of the assignment
+constexpr int kImgLdsSumK = 128;         // up to this k the assignment sums in LDS
 constexpr int kImgMaxK = 256;
 
 struct ImgArgs {
@@ -17,16 +19,18 @@ struct ImgArgs {
   int32_t *code;
   int32_t *wgcount;    // per image: per block group, pattern blocks (then their offsets)
   int32_t *npat;       // per image: pattern blocks
-  float *part;         // per image, per block group: k x 17 partial sums and counts
+  float *part;         // per image, per assignment group: k x 17 partial sums and counts
   int64_t h, w;        // pixels
   int64_t nb;          // blocks per image ((h/4) (w/4))
   int32_t groups;      // block groups per image (ceil(nb / 256))
+  int32_t agroups;     // assignment groups per image (ceil(nb / 1024))
   int32_t k;
   float tau;
 };
 
-// Kernel entry points, each launched with a grid of (tiles, groups or
-// codewords, batch); k_img_assign takes img_assign_lds_bytes of dynamic LDS.
+// Kernel entry points, each launched with a grid of (tiles, groups,
+// assignment groups or codewords, batch); k_img_assign takes
+// img_assign_lds_bytes of dynamic LDS.
 const void *img_kernel_front();
 const void *img_kernel_count();
 const void *img_kernel_scan();

@@ -22,18 +22,19 @@ struct WsLayout {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int64_t groups_of(const img_desc_t *d) {
+int64_t groups_of(const img_desc_t *d, int64_t per) {
   const int64_t nb = (int64_t)(d->height / 4) * (d->width / 4);
-  return (nb + kImgBlocksPerGroup - 1) / kImgBlocksPerGroup;
+  return (nb + per - 1) / per;
 }
 
 WsLayout layout(const img_desc_t *d) {
   WsLayout L;
-  const int64_t g = groups_of(d), B = d->batch;
+  const int64_t g = groups_of(d, kImgBlocksPerGroup), ga = groups_of(d, kImgAssignBlocks);
+  const int64_t B = d->batch;
   L.wgcount = 0;
   L.npat = align256(L.wgcount + sizeof(int32_t) * B * g);
   L.part = align256(L.npat + sizeof(int32_t) * B);
-  L.total = align256(L.part + sizeof(float) * B * g * d->k * 17);
+  L.total = align256(L.part + sizeof(float) * B * ga * d->k * 17);
   return L;
 }
 
@@ -58,7 +59,8 @@ ImgArgs args_of(const img_desc_t *d) {
   a.h = d->height;
   a.w = d->width;
   a.nb = (a.h / 4) * (a.w / 4);
-  a.groups = (int32_t)groups_of(d);
+  a.groups = (int32_t)groups_of(d, kImgBlocksPerGroup);
+  a.agroups = (int32_t)groups_of(d, kImgAssignBlocks);
   a.k = d->k;
   a.tau = d->tau;
   return a;
@@ -82,17 +84,17 @@ struct Launch {
 std::vector<Launch> sequence(const img_desc_t *d, const ImgArgs &a) {
   const unsigned B = (unsigned)d->batch;
   const int64_t tiles = ((a.w + kImgTileW - 1) / kImgTileW) * ((a.h + kImgTileH - 1) / kImgTileH);
-  const dim3 gb((unsigned)a.groups, B), gu((unsigned)a.k, B);
+  const dim3 gb((unsigned)a.groups, B), ga((unsigned)a.agroups, B), gu((unsigned)a.k, B);
   std::vector<Launch> v;
   v.push_back({img_kernel_front(), dim3((unsigned)tiles, B), kImgThreads, 0});
   v.push_back({img_kernel_count(), gb, kImgBlocksPerGroup, 0});
   v.push_back({img_kernel_scan(), dim3(B), 256, 0});
   v.push_back({img_kernel_seed(), gb, kImgBlocksPerGroup, 0});
   for (int it = 0; it < d->iters; ++it) {
-    v.push_back({img_kernel_assign(true), gb, kImgBlocksPerGroup, img_assign_lds_bytes(a.k, true)});
+    v.push_back({img_kernel_assign(true), ga, kImgThreads, img_assign_lds_bytes(a.k, true)});
     v.push_back({img_kernel_update(), gu, 256, 0});
   }
-  v.push_back({img_kernel_assign(false), gb, kImgBlocksPerGroup, img_assign_lds_bytes(a.k, false)});
+  v.push_back({img_kernel_assign(false), ga, kImgThreads, img_assign_lds_bytes(a.k, false)});
   return v;
 }
 
@@ -263,9 +265,8 @@ fft_status_t img_encode(const img_desc_t *desc, const float *dev, const float *a
   a.act = const_cast<float *>(act);
   a.codebook = const_cast<float *>(codebook);
   a.code = code;
-  const hipError_t e = launch(img_kernel_assign(false), dim3((unsigned)a.groups, (unsigned)desc->batch),
-                              kImgBlocksPerGroup, a, (hipStream_t)hip_stream,
-                              img_assign_lds_bytes(a.k, false));
+  const hipError_t e = launch(img_kernel_assign(false), dim3((unsigned)a.agroups, (unsigned)desc->batch),
+                              kImgThreads, a, (hipStream_t)hip_stream, img_assign_lds_bytes(a.k, false));
   if (e != hipSuccess) return fail(FFT_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return FFT_OK;
 }

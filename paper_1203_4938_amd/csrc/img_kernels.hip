@@ -240,153 +240,186 @@ __global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_seed(ImgArgs a) {
 // Each lane keeps the best of its rows in index order (strictly larger wins),
 // then the four lanes of a column compare (value, index) pairs: the larger
 // value, on equal values the lower index, as a plain scan would pick.
-// ACC: the group's cluster sums.  Each pattern block takes a rank in its
-// cluster (one LDS atomic), the per-cluster counts are scanned, the blocks'
-// deviation vectors are scattered into cluster order, and the (cluster,
-// component) sums are read off the contiguous runs and written as the
-// group's partial: one atomic per block instead of seventeen.  Otherwise the
-// codes of every block are written.  The codebook and the group's work
-// arrays sit in dynamic LDS sized for k.
+// A workgroup covers kImgAssignBlocks blocks in rounds of 256 (one per
+// thread), so the codebook and h_c are staged in LDS once per 1024 blocks.
+// ACC: the group's cluster sums.  In each round every pattern block takes a
+// rank among its wave's blocks of the same code from the wave's own LDS
+// counter (one atomic per block; no other wave touches it, so the ranks do
+// not depend on how the waves are scheduled), the per-wave counts are
+// scanned, the blocks' deviation vectors are scattered into (code, wave,
+// rank) order, and the (cluster, component) sums are read off the contiguous
+// runs and added, round after round, to the group's running sums (each entry
+// owned by one thread, which reads back only its own writes): in LDS for up
+// to kImgLdsSumK codewords, else in the group's partial in global memory,
+// where they leave the LDS for more workgroups per CU.  One partial per 1024
+// blocks.
+// Otherwise the codes of every block are written.  The codebook and the
+// group's work arrays sit in dynamic LDS sized for k.
 typedef float img_f4 __attribute__((ext_vector_type(4)));
 
 template <bool ACC>
-__global__ void __launch_bounds__(kImgBlocksPerGroup) k_img_assign(ImgArgs a) {
-  static_assert(kImgBlocksPerGroup % 64 == 0, "whole waves of blocks");
+__global__ void __launch_bounds__(kImgThreads) k_img_assign(ImgArgs a) {
+  static_assert(kImgThreads % 64 == 0 && kImgAssignBlocks % kImgThreads == 0,
+                "whole waves of blocks, whole rounds");
   extern __shared__ __align__(16) float img_lds[];
   const int k = a.k;
   float *cbk = img_lds;                          // k x 16
   float *hc = cbk + k * 16;                      // k: |c|^2 / 2
   float *sorted = hc + ((k + 3) & ~3);           // ACC: 256 x 16, in cluster order
-  int *cnt = (int *)(sorted + (ACC ? 16 * kImgBlocksPerGroup : 0));  // ACC: k counts
-  int *off = cnt + k;                            // ACC: k + 1 run offsets
+  int *wcnt = (int *)(sorted + (ACC ? 16 * kImgThreads : 0));  // ACC: 4 x k per-wave counts
+  int *off = wcnt + 4 * k;                       // ACC: k + 1 run offsets
+  const bool lsum = k <= kImgLdsSumK;            // ACC: running sums in LDS
+  float *gsum = (float *)(off + ((k + 4) & ~3)); // ACC, lsum: k x 17 running sums
   const int64_t img = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, col = lane & 15, g4 = lane >> 4;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, g4 = lane >> 4;
   const float *gcb = a.codebook + img * (int64_t)k * 16;
-  for (int i = tid; i < k * 16; i += kImgBlocksPerGroup) cbk[i] = gcb[i];
-  if constexpr (ACC)
-    for (int i = tid; i < k; i += kImgBlocksPerGroup) cnt[i] = 0;
-  const int64_t b0 = (int64_t)blockIdx.x * kImgBlocksPerGroup + (tid - lane);  // the wave's first block
-  const int64_t b = b0 + lane;
-  const int64_t gb = img * a.nb + b;
-  const bool in = b < a.nb;
-  const bool pat = in && a.act[gb] >= a.tau;
-  // B operands: block b0 + 16 nt + col, components 4 g4 .. 4 g4 + 3
-  float4 vb[4];
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const int64_t bb = b0 + 16 * nt + col;
-    vb[nt] = bb < a.nb ? reinterpret_cast<const float4 *>(a.dev + 16 * (img * a.nb + bb))[g4]
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int i = tid; i < k * 16; i += kImgThreads) cbk[i] = gcb[i];
+  if constexpr (ACC) {
+    for (int i = tid; i < 4 * k; i += kImgThreads) wcnt[i] = 0;
   }
   __syncthreads();
-  for (int c = tid; c < k; c += kImgBlocksPerGroup) {
+  for (int c = tid; c < k; c += kImgThreads) {
     float h = 0.f;
 #pragma unroll
     for (int t = 0; t < 16; ++t) h = __builtin_fmaf(cbk[16 * c + t], cbk[16 * c + t], h);
     hc[c] = 0.5f * h;
   }
   __syncthreads();
-  float bv[4];
-  int bi[4];
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) bv[nt] = -3.4e38f, bi[nt] = 0;
-  for (int m0 = 0; m0 < k; m0 += 16) {
-    const int ca = m0 + col;  // this lane's A row
-    const float4 va = ca < k ? reinterpret_cast<const float4 *>(cbk + 16 * ca)[g4]
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
-    img_f4 init;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int cr = m0 + 4 * g4 + r;
-      init[r] = cr < k ? -hc[cr] : -3.4e38f;
-    }
+  float *part = a.part + (img * a.agroups + blockIdx.x) * (int64_t)k * 17;
+  const int64_t base = (int64_t)blockIdx.x * kImgAssignBlocks;
+  for (int rd = 0; rd < kImgAssignBlocks / kImgThreads; ++rd) {
+    const int64_t r0 = base + (int64_t)rd * kImgThreads;  // the round's first block
+    if (r0 >= a.nb) break;                                // uniform over the workgroup
+    const int64_t b0 = r0 + (tid - lane);                 // the wave's first block
+    const int64_t b = b0 + lane;
+    const int64_t gb = img * a.nb + b;
+    const bool in = b < a.nb;
+    const bool pat = in && a.act[gb] >= a.tau;
+    // B operands: block b0 + 16 nt + col, components 4 g4 .. 4 g4 + 3
+    float4 vb[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      img_f4 d = init;
-      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb[nt].x, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[nt].y, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.z, vb[nt].z, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.w, vb[nt].w, d, 0, 0, 0);
+      const int64_t bb = b0 + 16 * nt + col;
+      vb[nt] = bb < a.nb ? reinterpret_cast<const float4 *>(a.dev + 16 * (img * a.nb + bb))[g4]
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float bv[4];
+    int bi[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bv[nt] = -3.4e38f, bi[nt] = 0;
+    for (int m0 = 0; m0 < k; m0 += 16) {
+      const int ca = m0 + col;  // this lane's A row
+      const float4 va = ca < k ? reinterpret_cast<const float4 *>(cbk + 16 * ca)[g4]
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+      img_f4 init;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (d[r] > bv[nt]) {
-          bv[nt] = d[r];
-          bi[nt] = m0 + 4 * g4 + r;
+        const int cr = m0 + 4 * g4 + r;
+        init[r] = cr < k ? -hc[cr] : -3.4e38f;
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        img_f4 d = init;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb[nt].x, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[nt].y, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.z, vb[nt].z, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(va.w, vb[nt].w, d, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (d[r] > bv[nt]) {
+            bv[nt] = d[r];
+            bi[nt] = m0 + 4 * g4 + r;
+          }
         }
       }
     }
-  }
-  // the four lanes of a column (g4 = 0..3) hold interleaved rows: combine
-  int best = 0;
+    // the four lanes of a column (g4 = 0..3) hold interleaved rows: combine
+    int best = 0;
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
+    for (int nt = 0; nt < 4; ++nt) {
 #pragma unroll
-    for (int x = 16; x <= 32; x *= 2) {
-      const float ov = __shfl_xor(bv[nt], x, 64);
-      const int oi = __shfl_xor(bi[nt], x, 64);
-      if (ov > bv[nt] || (ov == bv[nt] && oi < bi[nt])) {
-        bv[nt] = ov;
-        bi[nt] = oi;
+      for (int x = 16; x <= 32; x *= 2) {
+        const float ov = __shfl_xor(bv[nt], x, 64);
+        const int oi = __shfl_xor(bi[nt], x, 64);
+        if (ov > bv[nt] || (ov == bv[nt] && oi < bi[nt])) {
+          bv[nt] = ov;
+          bi[nt] = oi;
+        }
       }
+      if (nt == g4) best = bi[nt];  // block b0 + 16 nt + col is this lane's own
     }
-    if (nt == g4) best = bi[nt];  // block b0 + 16 nt + col is this lane's own
+    if constexpr (ACC) {
+      int *wc = wcnt;
+      const int rank = pat ? atomicAdd(&wc[wave * k + best], 1) : 0;
+      __syncthreads();
+      if (tid < 64) {
+        // exclusive scan of the k <= 256 counts by the first wave, four per lane
+        int loc[4], run = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 4 * tid + q;
+          loc[q] = run;
+          run += i < k ? wc[i] + wc[k + i] + wc[2 * k + i] + wc[3 * k + i] : 0;
+        }
+        int incl = run;
+        for (int d = 1; d < 64; d *= 2) {
+          const int o = __shfl_up(incl, d, 64);
+          if (tid >= d) incl += o;
+        }
+        const int base_off = incl - run;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 4 * tid + q;
+          if (i < k) off[i] = base_off + loc[q];
+        }
+        if (tid == 63) off[k] = incl;
+      }
+      __syncthreads();
+      if (pat) {
+        // the block's own deviation vector (the B operands hold other blocks')
+        int pos = off[best] + rank;
+        for (int w = 0; w < wave; ++w) pos += wc[w * k + best];
+        const float4 *src = reinterpret_cast<const float4 *>(a.dev + 16 * gb);
+        float4 *dst = reinterpret_cast<float4 *>(sorted + 16 * pos);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = src[q];
+      }
+      __syncthreads();
+      for (int i = tid; i < k * 17; i += kImgThreads) {
+        const int c = i / 17, t = i % 17;
+        const int q0 = off[c], q1 = off[c + 1];
+        float sum;
+        if (t == 16) {
+          sum = (float)(q1 - q0);
+        } else {
+          sum = 0.f;
+          for (int q = q0; q < q1; ++q) sum += sorted[16 * q + t];
+        }
+        float *acc = lsum ? gsum : part;
+        acc[i] = rd == 0 ? sum : acc[i] + sum;
+      }
+      // other waves read this wave's counters only before the barrier above;
+      // the wave clears them before its next round's atomics
+      for (int i = lane; i < k; i += 64) wc[wave * k + i] = 0;
+      // the next round's scan and scatter overwrite off and sorted only after
+      // its first barrier, which every thread reaches after these reads
+    } else {
+      if (in) a.code[gb] = pat ? best + 1 : 0;
+    }
   }
   if constexpr (ACC) {
-    const int rank = pat ? atomicAdd(&cnt[best], 1) : 0;
-    __syncthreads();
-    if (tid < 64) {
-      // exclusive scan of the k <= 256 counts by the first wave, four per lane
-      int loc[4], run = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = 4 * tid + q;
-        loc[q] = run;
-        run += i < k ? cnt[i] : 0;
-      }
-      int incl = run;
-      for (int d = 1; d < 64; d *= 2) {
-        const int o = __shfl_up(incl, d, 64);
-        if (tid >= d) incl += o;
-      }
-      const int base = incl - run;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = 4 * tid + q;
-        if (i < k) off[i] = base + loc[q];
-      }
-      if (tid == 63) off[k] = incl;
-    }
-    __syncthreads();
-    if (pat) {
-      // the block's own deviation vector (the B operands hold other blocks')
-      const float4 *src = reinterpret_cast<const float4 *>(a.dev + 16 * gb);
-      float4 *dst = reinterpret_cast<float4 *>(sorted + 16 * (off[best] + rank));
-#pragma unroll
-      for (int q = 0; q < 4; ++q) dst[q] = src[q];
-    }
-    __syncthreads();
-    float *part = a.part + (img * a.groups + blockIdx.x) * (int64_t)k * 17;
-    for (int i = tid; i < k * 17; i += kImgBlocksPerGroup) {
-      const int c = i / 17, t = i % 17;
-      const int r0 = off[c], r1 = off[c + 1];
-      float sum;
-      if (t == 16) {
-        sum = (float)(r1 - r0);
-      } else {
-        sum = 0.f;
-        for (int r = r0; r < r1; ++r) sum += sorted[16 * r + t];
-      }
-      part[i] = sum;
-    }
-  } else {
-    if (in) a.code[gb] = pat ? best + 1 : 0;
+    if (lsum)  // each entry was last written by the thread that copies it
+      for (int i = tid; i < k * 17; i += kImgThreads) part[i] = gsum[i];
   }
 }
 
 // Dynamic LDS of k_img_assign for k codewords.
 size_t img_assign_lds_bytes(int k, bool accumulate) {
   const size_t f = (size_t)k * 16 + (size_t)((k + 3) & ~3);
-  return sizeof(float) * (f + (accumulate ? 16 * kImgBlocksPerGroup + 2 * (size_t)k + 1 : 0));
+  return sizeof(float) *
+         (f + (accumulate ? 16 * kImgThreads + 4 * (size_t)k + ((k + 4) & ~3) +
+                                (k <= kImgLdsSumK ? 17 * (size_t)k : 0)
+                          : 0));
 }
 
 // New codewords: one workgroup per (codeword blockIdx.x, image blockIdx.y).
@@ -398,11 +431,11 @@ __global__ void __launch_bounds__(256) k_img_update(ImgArgs a) {
   const int64_t img = blockIdx.y;
   const int c = blockIdx.x, tid = threadIdx.x;
   const int64_t K17 = (int64_t)a.k * 17;
-  const float *part = a.part + img * a.groups * K17 + 17 * c;
+  const float *part = a.part + img * a.agroups * K17 + 17 * c;
   float s[17];
 #pragma unroll
   for (int t = 0; t < 17; ++t) s[t] = 0.f;
-  for (int g = tid; g < a.groups; g += 256) {
+  for (int g = tid; g < a.agroups; g += 256) {
     const float *p = part + g * K17;
 #pragma unroll
     for (int t = 0; t < 17; ++t) s[t] += p[t];

@@ -95,6 +95,39 @@ def test_pattern_images_exact(k, iters):
         f"{np.abs(g['codebook'][-1] - book).max():.1e}")
 
 
+@pytest.mark.parametrize("k", [64, 150])
+def test_pattern_images_exact_ragged_groups(k):
+    """264 x 200 images: 3300 blocks, so the last workgroup of the assignment
+    (1024 blocks, rounds of 256) ends inside its first round; k = 64 keeps
+    the running cluster sums in LDS, k = 150 in the global partials."""
+    h, w, B, iters = 264, 200, 2, 3
+    rgb = pattern_images(synth.BASE_SEED + 941 + k, B, h, w, k)
+    g = _run(rgb, k=k, iters=iters, tau=0.0)
+    for b in range(B):
+        _, (y, cb, cr, mean, act, dev) = _check_front(g, b, rgb[b])
+        book, P = oracle.img_kmeans(dev, act, 0.0, k, iters)
+        code, margin = oracle.img_encode(dev, act, 0.0, book)
+        assert margin.min() > 1.0, float(margin.min())
+        assert np.array_equal(g["code"][b], code), int((g["code"][b] != code).sum())
+        assert np.abs(g["codebook"][b] - book).max() <= ATOL
+    say(f"[img patterns] 264x200, k={k}: codes equal, codebook max err "
+        f"{np.abs(g['codebook'][-1] - book).max():.1e}")
+
+
+@pytest.mark.parametrize("k", [64, 200])
+def test_photo_pipeline_is_deterministic(k):
+    """Photographs (near ties, sums whose rounding depends on their order):
+    two runs give the same bits in every output, with the cluster sums in LDS
+    (k = 64) and in the global partials (k = 200)."""
+    h, w, B, iters, tau = 512, 512, 2, 6, 8.0
+    rgb = synth.images_rgb(synth.BASE_SEED + 951, B, h, w)
+    g1 = _run(rgb, k=k, iters=iters, tau=tau)
+    g2 = _run(rgb, k=k, iters=iters, tau=tau)
+    for n in g1:
+        assert np.array_equal(g1[n], g2[n]), n
+    say(f"[img determinism] k={k}: two runs bitwise equal")
+
+
 def test_graph_replays_match_direct_launches():
     """IMG_F_GRAPH: the launch sequence replayed from a HIP graph on the same
     buffers, three times with eager work between the replays and the outputs
