@@ -295,7 +295,9 @@ size_t img_workspace_bytes(const img_desc_t *desc);
  * 256-byte aligned, caller-owned.  Asynchronous on hip_stream.  Errors:
  * FFT_E_INVALID for a bad descriptor, NULL or misaligned buffers (checked
  * before any launch); FFT_E_UNSUPPORTED for images above 2^30 pixels;
- * FFT_E_DEVICE for a failed launch. */
+ * FFT_E_DEVICE for a failed launch.  Every sum is taken in an order that does
+ * not depend on scheduling, so the same inputs give the same output bits on
+ * every call (with or without IMG_F_GRAPH). */
 fft_status_t img_compress(const img_desc_t *desc, const uint8_t *rgb, const img_out_t *out,
                           void *workspace, void *hip_stream);
 
