@@ -149,9 +149,10 @@ __device__ __forceinline__ void ragged_item(const cf *__restrict__ in, cf *__res
 // consecutive items 8 K r + K x + k (k < K), which run side by side and share
 // the lines in one L2; the rounds keep the largest-first order (and so every
 // XCD's share of the work) intact.  Ids past the last whole round keep their
-// own item.
+// own item.  K = 128 measured 1.3% faster on the 10,000-signal batch than
+// K = 32 (K = 16: 1% slower, 64: 0.6% faster, 256: 0.2% faster).
 __device__ __forceinline__ uint32_t ragged_slot(uint32_t b, uint32_t n) {
-  constexpr uint32_t X = 8, K = 32;
+  constexpr uint32_t X = 8, K = 128;
   const uint32_t full = n / (X * K) * (X * K);
   if (b >= full) return b;
   const uint32_t x = b % X, p = b / X;
