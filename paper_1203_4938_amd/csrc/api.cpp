@@ -524,8 +524,11 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   a->a.lines = N2;
   a->a.tiles_per_batch = N2 / CA;
   // tile order in rounds (xcd_remap_rounds) except for column tiles narrower
-  // than 64 bytes, which measured 1-8% slower with it
-  a->a.flags = F_REMAP | (CA >= 8 ? F_ROUNDS : 0u);
+  // than 64 bytes, which measured 1-8% slower with it; rounds of 16 tiles per
+  // XCD for the 2048 x 2048 split (measured faster than 32, 8 and 4; for the
+  // other splits and the 2D column tiles of 2048, 32 is the fastest)
+  const uint32_t r16 = N1 == 2048 && N2 == 2048 ? F_ROUNDS16 : 0u;
+  a->a.flags = F_REMAP | (CA >= 8 ? F_ROUNDS | r16 : 0u);
   a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
   a->a.ntiles = a->grid.x;
   a->first = true;
@@ -540,7 +543,7 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   b->a.out_e = N1;
   b->a.lines = N1;
   b->a.tiles_per_batch = N1 / CB;
-  b->a.flags = F_REMAP | F_ROUNDS;
+  b->a.flags = F_REMAP | F_ROUNDS | r16;
   b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
   b->a.ntiles = b->grid.x;
   b->last = true;

@@ -289,18 +289,23 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
   if (bid >= full) return bid;
   return (bid % X) * (nblocks / X) + bid / X;
 }
-// The same in rounds: each round of 256 consecutive tiles gives every XCD 32
-// consecutive ones (one per CU), so the tiles in flight sweep whole rows of the
-// matrix together (DRAM page locality) while tiles sharing cache lines still
-// share an L2.  Measured on the power-of-two line and MFMA kernels: 4-11%
-// faster for the 256 x 256 four-step, the 4096-point column tiles of 2D
-// images and the transposed-row tiles of 2048 and 4096.  Falls back to
-// xcd_remap when the grid is not a whole number of rounds.
-__device__ __forceinline__ uint32_t xcd_remap_rounds(uint32_t bid, uint32_t nblocks) {
-  constexpr uint32_t X = 8, K = 32;
+// The same in rounds: each round of 8 K consecutive tiles gives every XCD K
+// consecutive ones (K = 32: one per CU), so the tiles in flight sweep whole
+// rows of the matrix together (DRAM page locality) while tiles sharing cache
+// lines still share an L2.  Measured on the power-of-two line and MFMA
+// kernels: 4-11% faster for the 256 x 256 four-step, the 4096-point column
+// tiles of 2D images and the transposed-row tiles of 2048 and 4096.  K = 16
+// (F_ROUNDS16, half a tile per CU in each round) is faster still for the
+// 2048-point tiles of the 2^22 four-step, whose one workgroup per CU makes a
+// round of 32 per XCD span a whole wave of the chip.  Falls back to xcd_remap
+// when the grid is not a whole number of rounds.
+__device__ __forceinline__ uint32_t xcd_remap_rounds(uint32_t bid, uint32_t nblocks,
+                                                     uint32_t kshift = 5) {
+  constexpr uint32_t X = 8;
+  const uint32_t K = 1u << kshift;
   if (nblocks % (X * K) != 0) return xcd_remap(bid, nblocks);
   const uint32_t slot = bid / X;
-  return (slot / K) * (X * K) + (bid % X) * K + slot % K;
+  return (slot >> kshift) * (X * K) + (bid % X) * K + (slot & (K - 1));
 }
 
 }  // namespace dpfft

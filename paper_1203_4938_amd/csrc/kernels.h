@@ -14,6 +14,7 @@ enum : int { ELEM_FAST = 0, LINE_FAST = 1 };
 enum : uint32_t {
   F_REMAP = 4u,     // XCD-aware workgroup -> tile order
   F_ROUNDS = 8u,    // with F_REMAP: the order in rounds of 256 tiles (xcd_remap_rounds)
+  F_ROUNDS16 = 16u, // with F_ROUNDS: rounds of 128 tiles, 16 per XCD
 };
 
 // One launch of a line kernel: length-L transforms of `lines` lines per batch

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(C * (P2<L, EPT>::T))
   int c, j;
   lane_map<L, EPT, C, MAP>(tid, c, j);
   const uint32_t tile = !(a.flags & F_REMAP)  ? blockIdx.x
-                        : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x)
+                        : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x, (a.flags & F_ROUNDS16) ? 4 : 5)
                                                : xcd_remap(blockIdx.x, gridDim.x);
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (int64_t)(tile - bb * a.tiles_per_batch) * C;
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(C * L / (2 * ES))
   int c, j;
   lane_map<H, ES, C, MAP>(tid, c, j);
   const uint32_t tile = !(a.flags & F_REMAP)  ? blockIdx.x
-                        : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x)
+                        : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x, (a.flags & F_ROUNDS16) ? 4 : 5)
                                                : xcd_remap(blockIdx.x, gridDim.x);
   const int64_t bb = tile / a.tiles_per_batch;
   const int64_t line0 = (int64_t)(tile - bb * a.tiles_per_batch) * C;

@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(kMfmaThreads) k_mfma256(const cf *__restrict__
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tileid = !(a.flags & F_REMAP)  ? blockIdx.x
-                          : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x)
+                          : (a.flags & F_ROUNDS) ? xcd_remap_rounds(blockIdx.x, gridDim.x, (a.flags & F_ROUNDS16) ? 4 : 5)
                                                  : xcd_remap(blockIdx.x, gridDim.x);
   const int64_t bb = tileid / a.tiles_per_batch;
   const int64_t line0 = (tileid - bb * a.tiles_per_batch) * C;
