@@ -266,6 +266,26 @@ def test_photo_pipeline_seeds_and_lloyd():
             f"{sse(g0['codebook'][b].astype(np.float64)):.4g} -> {sse(gbook):.4g}")
 
 
+@pytest.mark.parametrize("k,h,w", [(1, 64, 64), (2, 4, 8), (3, 4, 4)])
+def test_small_k_and_tiny_images(k, h, w):
+    """Edge cases of the assignment: one codeword (every pattern block in
+    cluster 0), images of one or two 4x4 blocks (one partial round of the
+    first workgroup, most lanes past the last block); tau = 0, so every block
+    with any gradient is a pattern block."""
+    B, iters = 3, 2
+    rgb = synth.images_rgb(synth.BASE_SEED + 961 + k, B, h, w)
+    g = _run(rgb, k=k, iters=iters, tau=0.0)
+    for b in range(B):
+        _, (y, cb, cr, mean, act, dev) = _check_front(g, b, rgb[b])
+        book, P = oracle.img_kmeans(dev, act, 0.0, k, iters)
+        assert np.abs(g["codebook"][b] - book).max() <= ATOL, b
+        ok, n = _valid_codes(g["code"][b], g["dev"][b].astype(np.float64),
+                             g["act"][b].reshape(-1).astype(np.float64), 0.0,
+                             g["codebook"][b].astype(np.float64))
+        assert ok, (b, n)
+    say(f"[img small] k={k} {h}x{w}: codebooks within {ATOL}, codes valid")
+
+
 def test_batch_zero_and_uniform_image():
     """An empty batch is a no-op; a flat image has no pattern block (all codes
     0, zero codebook)."""
