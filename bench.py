@@ -291,6 +291,20 @@ def build_real(dp, torch, synth, dev):
                      p.describe().splitlines()[0])
 
 
+def build_real_1d(dp, torch, synth, dev):
+    """The c2 signals of 2^22 points as real input (their real parts): 32 x 2^22
+    float32 -> 32 x (2^21 + 1) bins, through the 2^21-point four-step core and
+    the pairing launch."""
+    n, b = 1 << 22, 32
+    x = synth.uniform_complex_torch(synth.BASE_SEED + 2, n, b, dev).real.contiguous()
+    p = dp.Plan(n, b, real=True)
+    spec = torch.empty((b, n // 2 + 1), dtype=torch.complex64, device=dev)
+    alg = b * (4.0 * n + 8.0 * (n // 2 + 1))
+    return MultiItem(torch, "real2^22_b32", lambda: p.exec(x, out=spec),
+                     lambda: p.exec(spec, out=x, inverse=True), 0.5 * flops(n, b), alg,
+                     p.describe().splitlines()[0])
+
+
 def build_img(dp, torch, synth, dev):
     """Image block compression (section III-B): 16 colour photographs of
     2048 x 2048, k = 64 codewords, 8 Lloyd iterations, tau = 8.  Algorithmic
@@ -324,7 +338,8 @@ def build_img(dp, torch, synth, dev):
 def build_extras(dp, torch, synth, dev):
     """Comparison entries timed after the c2 step: the c4 precision forms, the
     c5 ragged batch (graph, no graph, one plan per length, one launch per
-    length), the c3 images as complex and as real input, the fused
+    length), the c3 images as complex and as real input, the c2 signals of 2^22
+    points as real input, the fused
     convolution against its unfused chain, and the image block compression."""
     out = []
     c4, _ = build_c4(dp, torch, synth, dev)
@@ -335,6 +350,7 @@ def build_extras(dp, torch, synth, dev):
         out.append(it)
     out.append(build_c5_fair(dp, torch, synth, dev))
     out.append(build_real(dp, torch, synth, dev))
+    out.append(build_real_1d(dp, torch, synth, dev))
     out.extend(build_conv(dp, torch, synth, dev))
     out.append(build_img(dp, torch, synth, dev))
     return out

@@ -309,6 +309,39 @@ std::string RealStep::describe() const {
   return o.str();
 }
 
+void RealPairStep::bind(const float2 *tables) {
+  a.lo = tables + lo_off;
+  a.hi = tables + hi_off;
+}
+
+hipError_t RealPairStep::launch(const ExecCtx &ctx) const {
+  const float2 *s = buf_c(ctx, src, 0);
+  float2 *d = buf_m(ctx, dst, 0);
+  RealPairArgs args = a;
+  void *kargs[] = {(void *)&s, (void *)&d, (void *)&args};
+  const dim3 grid((unsigned)((a.L / 2 + 1 + 255) / 256), (unsigned)std::min<int64_t>(a.batch, 65535));
+  return hipLaunchKernel(real_pair_kernel(inv), grid, dim3(256), kargs, 0, ctx.stream);
+}
+
+void RealPairStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const {
+  // forward: Z[0..L-1] in, bins 0..L out; inverse: bins 0..L in, L values out
+  max_in = (a.batch - 1) * a.in_b + (inv ? a.L : a.L - 1);
+  max_out = (a.batch - 1) * a.out_b + (inv ? a.L - 1 : a.L);
+  src_id = src;
+  dst_id = dst;
+}
+
+bool RealPairStep::valid() const {
+  return a.L >= 2 && (a.L & (a.L - 1)) == 0 && a.L / 2 + 1 <= int64_t(1) << 32 &&
+         real_pair_kernel(inv) != nullptr;
+}
+
+std::string RealPairStep::describe() const {
+  std::ostringstream o;
+  o << name << ": pairs k, L - k of L=" << a.L << " (N=" << 2 * a.L << ") batch=" << a.batch;
+  return o.str();
+}
+
 }  // namespace dpfft
 
 dpfft_plan_s::~dpfft_plan_s() {
@@ -471,6 +504,72 @@ void push_chunked(dpfft_plan_s *P, std::unique_ptr<LineStep> a, std::unique_ptr<
 // transforms per chunk: the override, else the whole batch at once
 int64_t chunk_of(const Override &ov) { return ov.chunk > 0 ? ov.chunk : 0; }
 
+// The two launches of an N-point power-of-two four-step over B signals,
+// in_b and out_b elements apart in the caller's input and output: pass A
+// reads the input (BUF_IN) into the workspace, pass B the workspace into the
+// output (BUF_OUT); pass A takes the inverse's input swap, pass B its output
+// swap and 1/N.
+bool fourstep_steps(dpfft_plan_s *P, int64_t N, int64_t B, int64_t in_b, int64_t out_b,
+                    const Override &ov, std::unique_ptr<LineStep> &a, std::unique_ptr<LineStep> &b) {
+  // four-step: N = N1 * N2, x[n1*N2 + n2]; pass A: N1-point column FFTs
+  // (stride N2) and twiddle w_N^{n2 k1} into the workspace Y[k1][n2]; pass B:
+  // N2-point FFTs along the rows of Y, stored transposed: X[k1 + N1 k2].
+  // Default split: N1 = N2 (or N2 = 2 N1).  For 2^22, 2048 x 2048 measured
+  // 1.5% faster than 4096 x 1024 (and steadier) and 2% faster than
+  // 1024 x 4096; the tuner tries all three (override s=).
+  const int lg = ilog2(N);
+  int lg1 = lg / 2;
+  if (ov.split > 0 && ov.split < lg) lg1 = ov.split;
+  const int N1 = 1 << lg1, N2 = 1 << (lg - lg1);
+  a = make_line(P, "fourstep_columns", N1, LINE_FAST, LINE_FAST, true, 16, 0, B * N2, ov);
+  b = make_line(P, "fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false, 16, 1, B * N1, ov);
+  if (!a || !b) return false;
+  const int CA = a->k.lines, CB = b->k.lines;
+  std::vector<std::complex<double>> lo, hi;
+  const int shift = (lg + 1) / 2;
+  fourstep_tables(N, shift, lo, hi);
+  a->has_tw4 = true;
+  a->tw4_lo_off = P->tables.add(lo);
+  a->tw4_hi_off = P->tables.add(hi);
+  a->a.tw4_shift = shift;
+  a->a.in_b = in_b;
+  a->a.in_l = 1;
+  a->a.in_e = N2;
+  a->a.out_b = N;
+  a->a.out_l = 1;
+  a->a.out_e = N2;
+  a->a.lines = N2;
+  a->a.tiles_per_batch = N2 / CA;
+  // tile order in rounds (xcd_remap_rounds) except for column tiles narrower
+  // than 64 bytes, which measured 1-8% slower with it; rounds of 16 tiles per
+  // XCD for the 2048 x 2048 split (measured faster than 32, 8 and 4; for the
+  // other splits and the 2D column tiles of 2048, 32 is the fastest)
+  const uint32_t r16 = N1 == 2048 && N2 == 2048 ? F_ROUNDS16 : 0u;
+  a->a.flags = F_REMAP | (CA >= 8 ? F_ROUNDS | r16 : 0u);
+  a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
+  a->a.ntiles = a->grid.x;
+  a->first = true;
+  a->src = BUF_IN;
+  a->dst = BUF_WS;
+
+  b->a.in_b = N;
+  b->a.in_l = N2;
+  b->a.in_e = 1;
+  b->a.out_b = out_b;
+  b->a.out_l = 1;
+  b->a.out_e = N1;
+  b->a.lines = N1;
+  b->a.tiles_per_batch = N1 / CB;
+  b->a.flags = F_REMAP | F_ROUNDS | r16;
+  b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
+  b->a.ntiles = b->grid.x;
+  b->last = true;
+  b->inv_scale = (float)(1.0 / (double)N);
+  b->src = BUF_WS;
+  b->dst = BUF_OUT;
+  return true;
+}
+
 fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch, D = P->dist;
   const Override ov = read_override();
@@ -494,62 +593,10 @@ fft_status_t plan_pow2_1d(dpfft_plan_s *P) {
     P->variant = "single-pass";
     return FFT_OK;
   }
-  // four-step: N = N1 * N2, x[n1*N2 + n2]; pass A: N1-point column FFTs
-  // (stride N2) and twiddle w_N^{n2 k1} into the workspace Y[k1][n2]; pass B:
-  // N2-point FFTs along the rows of Y, stored transposed: X[k1 + N1 k2].
-  // Default split: N1 = N2 (or N2 = 2 N1).  For 2^22, 2048 x 2048 measured
-  // 1.5% faster than 4096 x 1024 (and steadier) and 2% faster than
-  // 1024 x 4096; the tuner tries all three (override s=).
-  const int lg = ilog2(N);
-  int lg1 = lg / 2;
-  if (ov.split > 0 && ov.split < lg) lg1 = ov.split;
-  const int N1 = 1 << lg1, N2 = 1 << (lg - lg1);
-  auto a = make_line(P, "fourstep_columns", N1, LINE_FAST, LINE_FAST, true, 16, 0, B * N2, ov);
-  auto b = make_line(P, "fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false, 16, 1, B * N1, ov);
-  if (!a || !b) return fail(FFT_E_UNSUPPORTED, "no four-step kernels for N=" + std::to_string(N));
-  const int CA = a->k.lines, CB = b->k.lines;
-  std::vector<std::complex<double>> lo, hi;
-  const int shift = (lg + 1) / 2;
-  fourstep_tables(N, shift, lo, hi);
-  a->has_tw4 = true;
-  a->tw4_lo_off = P->tables.add(lo);
-  a->tw4_hi_off = P->tables.add(hi);
-  a->a.tw4_shift = shift;
-  a->a.in_b = D;
-  a->a.in_l = 1;
-  a->a.in_e = N2;
-  a->a.out_b = N;
-  a->a.out_l = 1;
-  a->a.out_e = N2;
-  a->a.lines = N2;
-  a->a.tiles_per_batch = N2 / CA;
-  // tile order in rounds (xcd_remap_rounds) except for column tiles narrower
-  // than 64 bytes, which measured 1-8% slower with it; rounds of 16 tiles per
-  // XCD for the 2048 x 2048 split (measured faster than 32, 8 and 4; for the
-  // other splits and the 2D column tiles of 2048, 32 is the fastest)
-  const uint32_t r16 = N1 == 2048 && N2 == 2048 ? F_ROUNDS16 : 0u;
-  a->a.flags = F_REMAP | (CA >= 8 ? F_ROUNDS | r16 : 0u);
-  a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
-  a->a.ntiles = a->grid.x;
-  a->first = true;
-  a->src = BUF_IN;
-  a->dst = BUF_WS;
-
-  b->a.in_b = N;
-  b->a.in_l = N2;
-  b->a.in_e = 1;
-  b->a.out_b = D;
-  b->a.out_l = 1;
-  b->a.out_e = N1;
-  b->a.lines = N1;
-  b->a.tiles_per_batch = N1 / CB;
-  b->a.flags = F_REMAP | F_ROUNDS | r16;
-  b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
-  b->a.ntiles = b->grid.x;
-  b->last = true;
-  b->inv_scale = (float)(1.0 / (double)N);
-  b->src = BUF_WS;
-  b->dst = BUF_OUT;
+  std::unique_ptr<LineStep> a, b;
+  if (!fourstep_steps(P, N, B, D, D, ov, a, b))
+    return fail(FFT_E_UNSUPPORTED, "no four-step kernels for N=" + std::to_string(N));
+  const int N1 = a->L, N2 = b->L;
   const int64_t k = chunk_of(ov);
   push_chunked(P, std::move(a), std::move(b), B, k, D);
   P->ws_bytes = (size_t)(k > 0 && k < B ? k : B) * (size_t)N * sizeof(float2);
@@ -885,9 +932,56 @@ std::unique_ptr<RealStep> make_real(dpfft_plan_s *P, const char *name, int64_t N
   return s;
 }
 
-// Real-input batch of 1D signals: one launch per direction.
+// Real-input batch of 1D signals: one launch per direction while the
+// N/2-point complex core fits one workgroup; above, the core is the
+// four-step pair of launches and the pairing of k with N/2 - k a launch of its
+// own (forward: four-step, then pairing in place in the output; inverse:
+// pairing from the input into the output, then the four-step from the output
+// through the workspace back into it, scaled by 1/N).
 fft_status_t plan_real_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch;
+  if (N / 2 > kSinglePassMax) {
+    const int64_t L = N / 2;
+    const Override ov = read_override();
+    std::unique_ptr<LineStep> a, b, ai, bi;
+    if (!fourstep_steps(P, L, B, L, L + 1, ov, a, b) || !fourstep_steps(P, L, B, L, L, ov, ai, bi))
+      return fail(FFT_E_UNSUPPORTED, "no four-step kernels for the real-input core L=" + std::to_string(L));
+    std::vector<std::complex<double>> lo, hi;
+    const int shift = (ilog2(N) + 1) / 2;
+    fourstep_tables(N, shift, lo, hi);
+    const size_t lo_off = P->tables.add(lo), hi_off = P->tables.add(hi);
+    auto pair = [&](bool inv) {
+      auto r = std::make_unique<RealPairStep>();
+      r->inv = inv;
+      r->name = inv ? "real_pairs_inverse" : "real_pairs";
+      r->a.L = L;
+      r->a.batch = B;
+      r->a.in_b = L + 1;  // forward: Z in the output (bins apart); inverse: the bins
+      r->a.out_b = inv ? L : L + 1;
+      r->a.shift = shift;
+      r->lo_off = lo_off;
+      r->hi_off = hi_off;
+      r->src = inv ? BUF_IN : BUF_OUT;
+      r->dst = BUF_OUT;
+      return r;
+    };
+    a->name = "real_core_columns";
+    b->name = "real_core_rows_transposed";
+    ai->name = "real_core_columns_inverse";
+    bi->name = "real_core_rows_transposed_inverse";
+    ai->src = BUF_OUT;  // the paired values the first inverse launch wrote
+    bi->inv_scale = (float)(1.0 / (double)N);
+    const int N1 = a->L, N2 = b->L;
+    P->steps.push_back(std::move(a));
+    P->steps.push_back(std::move(b));
+    P->steps.push_back(pair(false));
+    P->isteps.push_back(pair(true));
+    P->isteps.push_back(std::move(ai));
+    P->isteps.push_back(std::move(bi));
+    P->ws_bytes = (size_t)B * (size_t)L * sizeof(float2);
+    P->variant = "real four-step " + std::to_string(N1) + "x" + std::to_string(N2) + " + pairing";
+    return FFT_OK;
+  }
   auto f = make_real(P, "real_forward", N, false, B, 0, 0);
   auto i = make_real(P, "real_inverse", N, true, B, 0, 0);
   if (!f || !i) return fail(FFT_E_UNSUPPORTED, "no real-input kernel for N=" + std::to_string(N));
@@ -964,8 +1058,9 @@ fft_status_t validate_desc(const fft_desc_t *d) {
     if (d->dist != 0) return fail(FFT_E_INVALID, "real-input plans are dense (dist must be 0)");
     const int64_t nr = d->rank == 1 ? d->n[0] : d->n[1];
     if (nr <= 0 || (d->rank == 2 && d->n[0] <= 0)) return fail(FFT_E_INVALID, "sizes must be >= 1");
-    if (!is_pow2(nr) || nr < 2 || nr > 2 * kSinglePassMax)
-      return fail(FFT_E_UNSUPPORTED, "real-input lengths are powers of two in [2, 32768]");
+    if (!is_pow2(nr) || nr < 2 || nr > (d->rank == 1 ? kMaxN : 2 * kSinglePassMax))
+      return fail(FFT_E_UNSUPPORTED, d->rank == 1 ? "real-input lengths are powers of two in [2, 2^24]"
+                                                  : "real-input rows are powers of two in [2, 32768]");
     if (d->rank == 2 && (!is_pow2(d->n[0]) || d->n[0] > kSinglePassMax))
       return fail(FFT_E_UNSUPPORTED, "real-input images need ny a power of two <= 16384");
   }

@@ -147,6 +147,22 @@ struct RealStep : Step {
   bool valid() const override;
 };
 
+// Pairing pass of a real transform whose complex core is a four-step pair
+// of launches (forward: after them, in place in the output; inverse: before
+// them, from the input into the output).
+struct RealPairStep : Step {
+  bool inv = false;
+  RealPairArgs a{};
+  size_t lo_off = 0, hi_off = 0;
+  int src = BUF_OUT, dst = BUF_OUT;
+  std::string name;
+  void bind(const float2 *tables) override;
+  hipError_t launch(const ExecCtx &ctx) const override;
+  std::string describe() const override;
+  void extent(int64_t &max_in, int64_t &max_out, int &src_id, int &dst_id) const override;
+  bool valid() const override;
+};
+
 // Fused convolution launch: a single-pass line (forward, product with the
 // filter spectrum, inverse) or the row launch of the four-step form.
 struct ConvStep : Step {

@@ -115,6 +115,53 @@ __global__ void __launch_bounds__(C * (P2<L>::T))
   }
 }
 
+// Real transforms longer than one workgroup's LDS (N > 32768): the L-point
+// complex transform of z runs as the four-step pair of launches, and this
+// pass pairs the elements k and L - k that the in-kernel form pairs through
+// LDS.  With Fe[L-k] = conj Fe[k], Fo[L-k] = conj Fo[k] and w_N^{L-k} =
+// -conj w_N^k, one twiddle serves both outputs of a pair:
+//   X[k] = Fe[k] + w_N^k Fo[k],   X[L-k] = conj(Fe[k] - w_N^k Fo[k])
+// (k = 0: X[L], from Z[0] alone; k = L/2 pairs with itself).  The inverse
+// forms Fe' + i Fo' at k and L - k the same way (its conjugate halves) for the
+// complex inverse, which holds the samples once scaled by 1/N.  The forward
+// pass runs in place in the output (a thread reads both elements of its pair
+// before it writes them), so in and out are not restrict-qualified.
+template <bool INV>
+__global__ void __launch_bounds__(256) k_real_pair(const cf *in, cf *out, RealPairArgs a) {
+  const int64_t np = a.L / 2 + 1;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= np) return;
+  const uint32_t msk = (1u << a.shift) - 1u;
+  const cf w = cmul(a.hi[(uint32_t)k >> a.shift], a.lo[(uint32_t)k & msk]);  // w_N^k
+  const int64_t kr = a.L - k;  // k = 0: bin L on the spectrum side, Z[0] on the other
+  for (int64_t b = blockIdx.y; b < a.batch; b += gridDim.y) {
+    const cf *src = in + b * a.in_b;
+    cf *dst = out + b * a.out_b;
+    if constexpr (!INV) {
+      const cf zk = src[k], zr = src[kr & (a.L - 1)];
+      const cf fe = make_float2(0.5f * (zk.x + zr.x), 0.5f * (zk.y - zr.y));
+      const cf fo = make_float2(0.5f * (zk.y + zr.y), -0.5f * (zk.x - zr.x));
+      const cf t = cmul(w, fo);
+      dst[k] = cadd(fe, t);
+      if (kr != k) dst[kr] = make_float2(fe.x - t.x, t.y - fe.y);
+    } else {
+      cf xk = src[k], xr = src[kr];
+      if (k == 0) {  // bins 0 and L of a Hermitian spectrum are real
+        xk.y = 0.f;
+        xr.y = 0.f;
+      }
+      const cf fe = make_float2(xk.x + xr.x, xk.y - xr.y);                   // X[k] + conj X[L-k]
+      const cf fo = cmul(make_float2(xk.x - xr.x, xk.y + xr.y), make_float2(w.x, -w.y));
+      dst[k] = make_float2(fe.x - fo.y, fe.y + fo.x);                        // Fe' + i Fo'
+      if (k != 0 && kr != k) dst[kr] = make_float2(fe.x + fo.y, fo.x - fe.y);  // conj Fe' + i conj Fo'
+    }
+  }
+}
+
+const void *real_pair_kernel(bool inverse) {
+  return inverse ? (const void *)&k_real_pair<true> : (const void *)&k_real_pair<false>;
+}
+
 struct RealEntry {
   int L, C;
   const void *fwd, *inv;

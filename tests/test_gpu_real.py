@@ -49,7 +49,8 @@ def _real_batch(seed: int, n: int, batch: int) -> np.ndarray:
     return np.ascontiguousarray(synth.uniform_complex(seed, n, batch).real)
 
 
-SIZES_1D = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
+SIZES_1D = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768,
+            1 << 16, 1 << 18, 1 << 20, 1 << 22]
 
 
 @pytest.mark.parametrize("n", SIZES_1D)
@@ -57,7 +58,9 @@ def test_real_1d_forward_inverse(n):
     import torch
 
     import paper_1203_4938_amd as dp
-    batch = 521 if n <= 1024 else 37  # several workgroups and a ragged last tile
+    # several workgroups and a ragged last tile; above 32768 (the four-step
+    # core and the pairing launch) a few signals
+    batch = 521 if n <= 1024 else 37 if n <= 32768 else 3
     x = _real_batch(synth.BASE_SEED + 31, n, batch)
     p = dp.Plan(n, batch, real=True)
     say(f"[real 1d] n={n} batch={batch}:", p.describe().replace("\n", " | "))
@@ -89,19 +92,19 @@ def test_real_1d_closed_forms():
     import torch
 
     import paper_1203_4938_amd as dp
-    n = 4096
-    j = np.arange(n)
-    f = 37
-    rows = np.stack([np.cos(2 * np.pi * f * j / n), np.full(n, 0.75), (-1.0) ** j]).astype(np.float32)
-    p = dp.Plan(n, 3, real=True)
-    y = p.exec(torch.from_numpy(rows).cuda()).cpu().numpy()
-    expect = np.zeros((3, n // 2 + 1), dtype=np.complex128)
-    expect[0, f] = n / 2
-    expect[1, 0] = 0.75 * n
-    expect[2, n // 2] = n
-    err = np.abs(y - expect).max(axis=1) / np.abs(expect).max(axis=1)
-    say(f"[real closed forms] max abs error / peak: {err}")
-    assert np.all(err <= 1e-5)
+    for n in (4096, 1 << 20):  # one launch; the four-step core and the pairing launch
+        j = np.arange(n)
+        f = 37
+        rows = np.stack([np.cos(2 * np.pi * f * j / n), np.full(n, 0.75), (-1.0) ** j]).astype(np.float32)
+        p = dp.Plan(n, 3, real=True)
+        y = p.exec(torch.from_numpy(rows).cuda()).cpu().numpy()
+        expect = np.zeros((3, n // 2 + 1), dtype=np.complex128)
+        expect[0, f] = n / 2
+        expect[1, 0] = 0.75 * n
+        expect[2, n // 2] = n
+        err = np.abs(y - expect).max(axis=1) / np.abs(expect).max(axis=1)
+        say(f"[real closed forms] n={n} max abs error / peak: {err}")
+        assert np.all(err <= 1e-5)
 
 
 def test_real_2d_small_images():
@@ -183,7 +186,7 @@ def test_real_plan_edges():
     del x
     for kw, code in ((dict(n=64, batch=2, real=True, inplace=True), dp.FFT_E_UNSUPPORTED),
                      (dict(n=96, batch=2, real=True), dp.FFT_E_UNSUPPORTED),
-                     (dict(n=65536, batch=2, real=True), dp.FFT_E_UNSUPPORTED),
+                     (dict(n=1 << 25, batch=2, real=True), dp.FFT_E_UNSUPPORTED),
                      (dict(n=64, batch=2, real=True, dist=80), dp.FFT_E_INVALID),
                      (dict(n=64, batch=2, real=True, precision="fp16"), dp.FFT_E_UNSUPPORTED)):
         with pytest.raises(dp.FftError) as e:

@@ -226,6 +226,23 @@ def test_real_1d_plans(n):
     assert f"real_inverse: N={n}" in t
 
 
+@pytest.mark.parametrize("n", [1 << 16, 1 << 20, 1 << 24])
+def test_real_1d_four_step_plans(n):
+    """Real lengths above 32768: the N/2-point core as the four-step pair of
+    launches and the pairing of k with N/2 - k as a third, after the pair
+    (forward) or before it (inverse); workspace batch * N/2 complex64."""
+    dp = _dp()
+    b = 3
+    t = _dry(n=n, batch=b, flags=dp.FFT_F_REAL)
+    assert "variant=real four-step" in t and "launches=3" in t, t
+    assert f"workspace={b * (n // 2) * 8}B" in t, t
+    fwd, inv = t.split("\n  inverse:")
+    assert fwd.index("real_core_columns:") < fwd.index("real_core_rows_transposed:") < fwd.index("real_pairs:")
+    assert inv.index("real_pairs_inverse:") < inv.index("real_core_columns_inverse:") \
+        < inv.index("real_core_rows_transposed_inverse:")
+    assert f"L={n // 2} (N={n}) batch={b}" in t
+
+
 def test_real_2d_plan_layout():
     """Forward: real rows then in-place columns over nx/2 + 1 columns; inverse:
     columns into a workspace of batch * ny * (nx/2 + 1) complex64, then the
@@ -245,7 +262,7 @@ def test_real_2d_plan_layout():
     (dict(n=64, batch=2, flags=16 | 1), "FFT_E_UNSUPPORTED"),      # in place
     (dict(n=96, batch=2, flags=16), "FFT_E_UNSUPPORTED"),          # not a power of two
     (dict(n=1, batch=2, flags=16), "FFT_E_UNSUPPORTED"),           # N = 1 has no pairs
-    (dict(n=65536, batch=2, flags=16), "FFT_E_UNSUPPORTED"),       # above one pass
+    (dict(n=1 << 25, batch=2, flags=16), "FFT_E_UNSUPPORTED"),     # above 2^24
     (dict(n=64, batch=2, dist=64, flags=16), "FFT_E_INVALID"),     # dense only
     (dict(n=64, batch=2, flags=16, precision="bf16"), "FFT_E_UNSUPPORTED"),
     (dict(rank=2, shape=(3, 64), batch=1, flags=16), "FFT_E_UNSUPPORTED"),
