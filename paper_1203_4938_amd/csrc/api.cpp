@@ -935,16 +935,20 @@ std::unique_ptr<RealStep> make_real(dpfft_plan_s *P, const char *name, int64_t N
 // Real-input batch of 1D signals: one launch per direction while the
 // N/2-point complex core fits one workgroup; above, the core is the
 // four-step pair of launches and the pairing of k with N/2 - k a launch of its
-// own (forward: four-step, then pairing in place in the output; inverse:
-// pairing from the input into the output, then the four-step from the output
-// through the workspace back into it, scaled by 1/N).
+// own.  Forward: the core from the input through the output (used as scratch
+// at N/2 elements per signal, so every tile stays on 128-byte boundaries)
+// into the workspace, then the pairing from the workspace into the output's
+// N/2 + 1 bins per signal, whose rows start at any 8-byte offset but which
+// the pairing writes as contiguous runs.  Inverse: the pairing from the input
+// into the output, then the core from the output through the workspace back
+// into it, scaled by 1/N.
 fft_status_t plan_real_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch;
   if (N / 2 > kSinglePassMax) {
     const int64_t L = N / 2;
     const Override ov = read_override();
     std::unique_ptr<LineStep> a, b, ai, bi;
-    if (!fourstep_steps(P, L, B, L, L + 1, ov, a, b) || !fourstep_steps(P, L, B, L, L, ov, ai, bi))
+    if (!fourstep_steps(P, L, B, L, L, ov, a, b) || !fourstep_steps(P, L, B, L, L, ov, ai, bi))
       return fail(FFT_E_UNSUPPORTED, "no four-step kernels for the real-input core L=" + std::to_string(L));
     std::vector<std::complex<double>> lo, hi;
     const int shift = (ilog2(N) + 1) / 2;
@@ -956,12 +960,12 @@ fft_status_t plan_real_1d(dpfft_plan_s *P) {
       r->name = inv ? "real_pairs_inverse" : "real_pairs";
       r->a.L = L;
       r->a.batch = B;
-      r->a.in_b = L + 1;  // forward: Z in the output (bins apart); inverse: the bins
+      r->a.in_b = inv ? L + 1 : L;  // inverse: the bins; forward: Z in the workspace
       r->a.out_b = inv ? L : L + 1;
       r->a.shift = shift;
       r->lo_off = lo_off;
       r->hi_off = hi_off;
-      r->src = inv ? BUF_IN : BUF_OUT;
+      r->src = inv ? BUF_IN : BUF_WS;
       r->dst = BUF_OUT;
       return r;
     };
@@ -969,6 +973,9 @@ fft_status_t plan_real_1d(dpfft_plan_s *P) {
     b->name = "real_core_rows_transposed";
     ai->name = "real_core_columns_inverse";
     bi->name = "real_core_rows_transposed_inverse";
+    a->dst = BUF_OUT;   // Y, N/2 elements per signal, in the output as scratch
+    b->src = BUF_OUT;
+    b->dst = BUF_WS;    // Z, read by the pairing
     ai->src = BUF_OUT;  // the paired values the first inverse launch wrote
     bi->inv_scale = (float)(1.0 / (double)N);
     const int N1 = a->L, N2 = b->L;

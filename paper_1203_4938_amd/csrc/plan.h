@@ -148,8 +148,8 @@ struct RealStep : Step {
 };
 
 // Pairing pass of a real transform whose complex core is a four-step pair
-// of launches (forward: after them, in place in the output; inverse: before
-// them, from the input into the output).
+// of launches (forward: after them, from the workspace into the output;
+// inverse: before them, from the input into the output).
 struct RealPairStep : Step {
   bool inv = false;
   RealPairArgs a{};

@@ -123,9 +123,9 @@ __global__ void __launch_bounds__(C * (P2<L>::T))
 //   X[k] = Fe[k] + w_N^k Fo[k],   X[L-k] = conj(Fe[k] - w_N^k Fo[k])
 // (k = 0: X[L], from Z[0] alone; k = L/2 pairs with itself).  The inverse
 // forms Fe' + i Fo' at k and L - k the same way (its conjugate halves) for the
-// complex inverse, which holds the samples once scaled by 1/N.  The forward
-// pass runs in place in the output (a thread reads both elements of its pair
-// before it writes them), so in and out are not restrict-qualified.
+// complex inverse, which holds the samples once scaled by 1/N.  A thread
+// reads both elements of its pair before it writes them, so the pass would
+// also be correct in place; in and out are not restrict-qualified.
 template <bool INV>
 __global__ void __launch_bounds__(256) k_real_pair(const cf *in, cf *out, RealPairArgs a) {
   const int64_t np = a.L / 2 + 1;
