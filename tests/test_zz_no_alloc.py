@@ -87,6 +87,30 @@ def test_noalloc_real_images_inverse():
     assert e <= 1e-5
 
 
+def test_noalloc_real_1d_four_step_core():
+    """Real signals of 2^17 samples: the four-step core runs in the library's
+    array (the forward also uses the output as scratch), both directions equal
+    to fft_exec, the forward within the oracle's bound."""
+    import torch
+    dp = _dp()
+    n, b = 1 << 17, 3
+    x = np.ascontiguousarray(synth.uniform_complex(synth.BASE_SEED + 402, n, b).real)
+    p = dp.Plan(n, b, real=True)
+    assert p.workspace_bytes == b * (n // 2) * 8
+    xd = torch.from_numpy(x).cuda()
+    ya, yb = _both(p, xd, False, out_shape=(b, n // 2 + 1), out_dtype=torch.complex64)
+    assert np.array_equal(ya, yb)
+    ref = oracle.fft_batch(x.astype(np.complex64))[:, : n // 2 + 1]
+    e = float(np.max(oracle.rel_l2_f32(yb, ref)))
+    say(f"[noalloc] real 1d n={n}: forward equal to fft_exec, max rel L2 {e:.2e}")
+    assert e <= TOL_FP32
+    za, zb = _both(p, torch.from_numpy(ya).cuda(), True, out_shape=(b, n), out_dtype=torch.float32)
+    assert np.array_equal(za, zb)
+    er = float(np.max(np.abs(zb - x)))
+    say(f"   inverse equal to fft_exec, max abs round-trip error {er:.2e}")
+    assert er <= 1e-5
+
+
 def test_noalloc_rejects_large_workspace():
     import torch
     dp = _dp()
