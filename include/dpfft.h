@@ -115,14 +115,16 @@ typedef struct {
  *                  transforms have been inverted, which are real for a
  *                  Hermitian 2D spectrum).
  * Signals (images) are packed back to back on both sides: dist must be 0.
- * Supported: FFT_FP32, rank 1 with N a power of two in [2, 2^24] (one
- * launch per direction up to 32768; above, three: the N/2-point complex
- * transform of the samples read as N/2 complex pairs as a four-step pair of
- * launches and a launch that pairs bin k with N/2 - k, with a workspace of
- * batch * N/2 complex64), rank 2 with nx a power of two in [2, 32768] and ny
- * a power of two in [1, 16384] (two launches per direction; the inverse needs
- * a workspace of batch * ny * (nx/2 + 1) complex64).  in != out.  Both
- * buffers are device pointers owned by the caller, 8-byte aligned.
+ * Supported: FFT_FP32, rank 1 with N an even number in [2, 2^24] whose
+ * prime factors are at most 7 (powers of two up to 32768: one launch per
+ * direction; otherwise the N/2-point complex transform of the samples read
+ * as N/2 complex pairs runs on launches of its own, one single pass or a
+ * four-step pair, and one more launch pairs bin k with N/2 - k, with a
+ * workspace of batch * N/2 complex64), rank 2 with nx a power of two in
+ * [2, 32768] and ny a power of two in [1, 16384] (two launches per
+ * direction; the inverse needs a workspace of batch * ny * (nx/2 + 1)
+ * complex64).  in != out.  Both buffers are device pointers owned by the
+ * caller, 8-byte aligned.
  */
 
 /*

@@ -332,8 +332,7 @@ void RealPairStep::extent(int64_t &max_in, int64_t &max_out, int &src_id, int &d
 }
 
 bool RealPairStep::valid() const {
-  return a.L >= 2 && (a.L & (a.L - 1)) == 0 && a.L / 2 + 1 <= int64_t(1) << 32 &&
-         real_pair_kernel(inv) != nullptr;
+  return a.L >= 1 && a.L / 2 + 1 <= int64_t(1) << 32 && real_pair_kernel(inv) != nullptr;
 }
 
 std::string RealPairStep::describe() const {
@@ -682,6 +681,57 @@ int mixed_lines(int64_t L, int map, int omap, int thr, int cmin) {
   return C;
 }
 
+// The two launches of an N-point 7-smooth four-step over B signals, in_b
+// and out_b elements apart in the caller's input and output (pass A: input
+// -> workspace with the twiddle; pass B: workspace -> output, transposed).
+bool mixed_fourstep_steps(dpfft_plan_s *P, int64_t N, int64_t B, int64_t in_b, int64_t out_b,
+                          std::unique_ptr<MixedStep> &a, std::unique_ptr<MixedStep> &b) {
+  const int64_t N1 = split_factor(N), N2 = N / N1;
+  if (N2 > kSinglePassMax) return false;
+  const int CA = mixed_lines(N1, LINE_FAST, LINE_FAST, 1024, 1);
+  const int CB = mixed_lines(N2, ELEM_FAST, LINE_FAST, 1024, 1);
+  a = CA ? make_mixed(P, "mixed_fourstep_columns", N1, LINE_FAST, LINE_FAST, true, std::min(CA, 16))
+         : nullptr;
+  b = CB ? make_mixed(P, "mixed_fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false,
+                      std::min(CB, 16))
+         : nullptr;
+  if (!a || !b) return false;
+  std::vector<std::complex<double>> lo, hi;
+  const int shift = (ilog2(N) + 1) / 2;
+  fourstep_tables(N, shift, lo, hi);
+  a->tw4_lo_off = P->tables.add(lo);
+  a->tw4_hi_off = P->tables.add(hi);
+  a->a.tw4_shift = shift;
+  a->a.in_b = in_b;
+  a->a.in_l = 1;
+  a->a.in_e = N2;
+  a->a.out_b = N;
+  a->a.out_l = 1;
+  a->a.out_e = N2;
+  a->a.lines = N2;
+  a->a.tiles_per_batch = (N2 + a->a.mp.C - 1) / a->a.mp.C;
+  a->a.flags = F_REMAP;
+  a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
+  a->first = true;
+  a->src = BUF_IN;
+  a->dst = BUF_WS;
+  b->a.in_b = N;
+  b->a.in_l = N2;
+  b->a.in_e = 1;
+  b->a.out_b = out_b;
+  b->a.out_l = 1;
+  b->a.out_e = N1;
+  b->a.lines = N1;
+  b->a.tiles_per_batch = (N1 + b->a.mp.C - 1) / b->a.mp.C;
+  b->a.flags = F_REMAP;
+  b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
+  b->last = true;
+  b->inv_scale = (float)(1.0 / (double)N);
+  b->src = BUF_WS;
+  b->dst = BUF_OUT;
+  return true;
+}
+
 fft_status_t plan_mixed_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch, D = P->dist;
   const Override ov = read_override();
@@ -706,51 +756,10 @@ fft_status_t plan_mixed_1d(dpfft_plan_s *P) {
     P->variant = "mixed single-pass";
     return FFT_OK;
   }
-  const int64_t N1 = split_factor(N), N2 = N / N1;
-  if (N2 > kSinglePassMax)
-    return fail(FFT_E_UNSUPPORTED, "no two-factor split of N=" + std::to_string(N));
-  const int CA = mixed_lines(N1, LINE_FAST, LINE_FAST, 1024, 1);
-  const int CB = mixed_lines(N2, ELEM_FAST, LINE_FAST, 1024, 1);
-  auto a = CA ? make_mixed(P, "mixed_fourstep_columns", N1, LINE_FAST, LINE_FAST, true,
-                           std::min(CA, 16))
-              : nullptr;
-  auto b = CB ? make_mixed(P, "mixed_fourstep_rows_transposed", N2, ELEM_FAST, LINE_FAST, false,
-                           std::min(CB, 16))
-              : nullptr;
-  if (!a || !b) return fail(FFT_E_UNSUPPORTED, "no mixed four-step plan for N=" + std::to_string(N));
-  std::vector<std::complex<double>> lo, hi;
-  const int shift = (ilog2(N) + 1) / 2;
-  fourstep_tables(N, shift, lo, hi);
-  a->tw4_lo_off = P->tables.add(lo);
-  a->tw4_hi_off = P->tables.add(hi);
-  a->a.tw4_shift = shift;
-  a->a.in_b = D;
-  a->a.in_l = 1;
-  a->a.in_e = N2;
-  a->a.out_b = N;
-  a->a.out_l = 1;
-  a->a.out_e = N2;
-  a->a.lines = N2;
-  a->a.tiles_per_batch = (N2 + a->a.mp.C - 1) / a->a.mp.C;
-  a->a.flags = F_REMAP;
-  a->grid = dim3((unsigned)(B * a->a.tiles_per_batch));
-  a->first = true;
-  a->src = BUF_IN;
-  a->dst = BUF_WS;
-  b->a.in_b = N;
-  b->a.in_l = N2;
-  b->a.in_e = 1;
-  b->a.out_b = D;
-  b->a.out_l = 1;
-  b->a.out_e = N1;
-  b->a.lines = N1;
-  b->a.tiles_per_batch = (N1 + b->a.mp.C - 1) / b->a.mp.C;
-  b->a.flags = F_REMAP;
-  b->grid = dim3((unsigned)(B * b->a.tiles_per_batch));
-  b->last = true;
-  b->inv_scale = (float)(1.0 / (double)N);
-  b->src = BUF_WS;
-  b->dst = BUF_OUT;
+  std::unique_ptr<MixedStep> a, b;
+  if (!mixed_fourstep_steps(P, N, B, D, D, a, b))
+    return fail(FFT_E_UNSUPPORTED, "no mixed four-step plan for N=" + std::to_string(N));
+  const int64_t N1 = a->a.mp.L, N2 = b->a.mp.L;
   P->steps.push_back(std::move(a));
   P->steps.push_back(std::move(b));
   P->ws_bytes = (size_t)B * (size_t)N * sizeof(float2);
@@ -944,49 +953,103 @@ std::unique_ptr<RealStep> make_real(dpfft_plan_s *P, const char *name, int64_t N
 // into it, scaled by 1/N.
 fft_status_t plan_real_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch;
-  if (N / 2 > kSinglePassMax) {
+  if (!is_pow2(N) || N / 2 > kSinglePassMax) {
     const int64_t L = N / 2;
     const Override ov = read_override();
-    std::unique_ptr<LineStep> a, b, ai, bi;
-    if (!fourstep_steps(P, L, B, L, L, ov, a, b) || !fourstep_steps(P, L, B, L, L, ov, ai, bi))
-      return fail(FFT_E_UNSUPPORTED, "no four-step kernels for the real-input core L=" + std::to_string(L));
     std::vector<std::complex<double>> lo, hi;
     const int shift = (ilog2(N) + 1) / 2;
     fourstep_tables(N, shift, lo, hi);
     const size_t lo_off = P->tables.add(lo), hi_off = P->tables.add(hi);
-    auto pair = [&](bool inv) {
+    auto pair = [&](bool inv, int src, int dst) {
       auto r = std::make_unique<RealPairStep>();
       r->inv = inv;
       r->name = inv ? "real_pairs_inverse" : "real_pairs";
       r->a.L = L;
       r->a.batch = B;
-      r->a.in_b = inv ? L + 1 : L;  // inverse: the bins; forward: Z in the workspace
+      r->a.in_b = inv ? L + 1 : L;  // inverse: the bins; forward: Z at L per signal
       r->a.out_b = inv ? L : L + 1;
       r->a.shift = shift;
       r->lo_off = lo_off;
       r->hi_off = hi_off;
-      r->src = inv ? BUF_IN : BUF_WS;
-      r->dst = BUF_OUT;
+      r->src = src;
+      r->dst = dst;
       return r;
     };
-    a->name = "real_core_columns";
-    b->name = "real_core_rows_transposed";
-    ai->name = "real_core_columns_inverse";
-    bi->name = "real_core_rows_transposed_inverse";
-    a->dst = BUF_OUT;   // Y, N/2 elements per signal, in the output as scratch
-    b->src = BUF_OUT;
-    b->dst = BUF_WS;    // Z, read by the pairing
-    ai->src = BUF_OUT;  // the paired values the first inverse launch wrote
-    bi->inv_scale = (float)(1.0 / (double)N);
-    const int N1 = a->L, N2 = b->L;
-    P->steps.push_back(std::move(a));
-    P->steps.push_back(std::move(b));
-    P->steps.push_back(pair(false));
-    P->isteps.push_back(pair(true));
-    P->isteps.push_back(std::move(ai));
-    P->isteps.push_back(std::move(bi));
+    std::string core;
+    if (L <= kSinglePassMax && !is_pow2(L)) {
+      // single-pass runtime-radix core: input -> workspace (forward), and
+      // workspace -> output after the pairing (inverse), never in place
+      int C = mixed_lines(L, ELEM_FAST, ELEM_FAST, 256, 1);
+      if (ov.c[0] > 0 && ov.c[0] <= mixed_lines(L, ELEM_FAST, ELEM_FAST, 1024, 1)) C = ov.c[0];
+      std::unique_ptr<MixedStep> c[2];
+      for (int i = 0; i < 2; ++i) {
+        c[i] = C ? make_mixed(P, i ? "real_core_rows_inverse" : "real_core_rows", L, ELEM_FAST,
+                              ELEM_FAST, false, C)
+                 : nullptr;
+        if (!c[i]) return fail(FFT_E_UNSUPPORTED, "no runtime-radix core for real N=" + std::to_string(N));
+        c[i]->a.in_b = c[i]->a.out_b = 0;
+        c[i]->a.in_l = c[i]->a.out_l = L;
+        c[i]->a.in_e = c[i]->a.out_e = 1;
+        c[i]->a.lines = B;
+        c[i]->a.tiles_per_batch = (B + C - 1) / C;
+        c[i]->grid = dim3((unsigned)c[i]->a.tiles_per_batch);
+        c[i]->first = c[i]->last = true;
+        c[i]->inv_scale = (float)(1.0 / (double)N);
+      }
+      c[0]->src = BUF_IN;
+      c[0]->dst = BUF_WS;
+      c[1]->src = BUF_WS;
+      c[1]->dst = BUF_OUT;
+      P->steps.push_back(std::move(c[0]));
+      P->steps.push_back(pair(false, BUF_WS, BUF_OUT));
+      P->isteps.push_back(pair(true, BUF_IN, BUF_WS));
+      P->isteps.push_back(std::move(c[1]));
+      core = "runtime-radix single-pass";
+    } else {
+      // four-step core (powers of two: the line kernels; else runtime radix)
+      std::unique_ptr<Step> a, b, ai, bi;
+      std::string split;
+      if (is_pow2(L)) {
+        std::unique_ptr<LineStep> x[4];
+        if (!fourstep_steps(P, L, B, L, L, ov, x[0], x[1]) || !fourstep_steps(P, L, B, L, L, ov, x[2], x[3]))
+          return fail(FFT_E_UNSUPPORTED, "no four-step kernels for the real-input core L=" + std::to_string(L));
+        const char *nm[4] = {"real_core_columns", "real_core_rows_transposed",
+                             "real_core_columns_inverse", "real_core_rows_transposed_inverse"};
+        for (int i = 0; i < 4; ++i) x[i]->name = nm[i];
+        split = std::to_string(x[0]->L) + "x" + std::to_string(x[1]->L);
+        // forward: Y in the output as scratch (L per signal, whole 128-byte
+        // lines), Z into the workspace; inverse: output -> workspace -> output
+        x[0]->dst = BUF_OUT;
+        x[1]->src = BUF_OUT;
+        x[1]->dst = BUF_WS;
+        x[2]->src = BUF_OUT;
+        x[3]->inv_scale = (float)(1.0 / (double)N);
+        a = std::move(x[0]), b = std::move(x[1]), ai = std::move(x[2]), bi = std::move(x[3]);
+      } else {
+        std::unique_ptr<MixedStep> x[4];
+        if (!mixed_fourstep_steps(P, L, B, L, L, x[0], x[1]) || !mixed_fourstep_steps(P, L, B, L, L, x[2], x[3]))
+          return fail(FFT_E_UNSUPPORTED, "no four-step core for real N=" + std::to_string(N));
+        const char *nm[4] = {"real_core_columns", "real_core_rows_transposed",
+                             "real_core_columns_inverse", "real_core_rows_transposed_inverse"};
+        for (int i = 0; i < 4; ++i) x[i]->name = nm[i];
+        split = std::to_string(x[0]->a.mp.L) + "x" + std::to_string(x[1]->a.mp.L);
+        x[0]->dst = BUF_OUT;
+        x[1]->src = BUF_OUT;
+        x[1]->dst = BUF_WS;
+        x[2]->src = BUF_OUT;
+        x[3]->inv_scale = (float)(1.0 / (double)N);
+        a = std::move(x[0]), b = std::move(x[1]), ai = std::move(x[2]), bi = std::move(x[3]);
+      }
+      P->steps.push_back(std::move(a));
+      P->steps.push_back(std::move(b));
+      P->steps.push_back(pair(false, BUF_WS, BUF_OUT));
+      P->isteps.push_back(pair(true, BUF_IN, BUF_OUT));
+      P->isteps.push_back(std::move(ai));
+      P->isteps.push_back(std::move(bi));
+      core = "four-step " + split;
+    }
     P->ws_bytes = (size_t)B * (size_t)L * sizeof(float2);
-    P->variant = "real four-step " + std::to_string(N1) + "x" + std::to_string(N2) + " + pairing";
+    P->variant = "real " + core + " + pairing";
     return FFT_OK;
   }
   auto f = make_real(P, "real_forward", N, false, B, 0, 0);
@@ -1065,9 +1128,12 @@ fft_status_t validate_desc(const fft_desc_t *d) {
     if (d->dist != 0) return fail(FFT_E_INVALID, "real-input plans are dense (dist must be 0)");
     const int64_t nr = d->rank == 1 ? d->n[0] : d->n[1];
     if (nr <= 0 || (d->rank == 2 && d->n[0] <= 0)) return fail(FFT_E_INVALID, "sizes must be >= 1");
-    if (!is_pow2(nr) || nr < 2 || nr > (d->rank == 1 ? kMaxN : 2 * kSinglePassMax))
-      return fail(FFT_E_UNSUPPORTED, d->rank == 1 ? "real-input lengths are powers of two in [2, 2^24]"
-                                                  : "real-input rows are powers of two in [2, 32768]");
+    if (d->rank == 1) {
+      if (nr < 2 || nr % 2 || nr > kMaxN || largest_prime_factor(nr) > 7)
+        return fail(FFT_E_UNSUPPORTED, "real-input lengths are even 7-smooth numbers in [2, 2^24]");
+    } else if (!is_pow2(nr) || nr < 2 || nr > 2 * kSinglePassMax) {
+      return fail(FFT_E_UNSUPPORTED, "real-input rows are powers of two in [2, 32768]");
+    }
     if (d->rank == 2 && (!is_pow2(d->n[0]) || d->n[0] > kSinglePassMax))
       return fail(FFT_E_UNSUPPORTED, "real-input images need ny a power of two <= 16384");
   }

@@ -26,7 +26,7 @@ bool real_kernel(int L, RealKernel *out);
 // inverse transform, halved, holds the real samples in pairs.
 struct RealPairArgs {
   int64_t in_b, out_b;      // complex elements between the signals of in and out
-  int64_t L;                // N / 2, a power of two
+  int64_t L;                // N / 2
   int64_t batch;
   const float2 *lo, *hi;    // two-level table of w_N: w_N^e = hi[e >> shift] lo[e & mask]
   int32_t shift;

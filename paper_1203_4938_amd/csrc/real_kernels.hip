@@ -115,13 +115,14 @@ __global__ void __launch_bounds__(C * (P2<L>::T))
   }
 }
 
-// Real transforms longer than one workgroup's LDS (N > 32768): the L-point
-// complex transform of z runs as the four-step pair of launches, and this
-// pass pairs the elements k and L - k that the in-kernel form pairs through
-// LDS.  With Fe[L-k] = conj Fe[k], Fo[L-k] = conj Fo[k] and w_N^{L-k} =
+// Real transforms longer than one workgroup's LDS (N > 32768), or of even
+// lengths that are not powers of two: the L-point complex transform of z runs
+// as launches of its own (the four-step pair, or the runtime-radix single
+// pass), and this pass pairs the elements k and L - k that the in-kernel form
+// pairs through LDS.  With Fe[L-k] = conj Fe[k], Fo[L-k] = conj Fo[k] and w_N^{L-k} =
 // -conj w_N^k, one twiddle serves both outputs of a pair:
 //   X[k] = Fe[k] + w_N^k Fo[k],   X[L-k] = conj(Fe[k] - w_N^k Fo[k])
-// (k = 0: X[L], from Z[0] alone; k = L/2 pairs with itself).  The inverse
+// (k = 0: X[L], from Z[0] alone; for even L, k = L/2 pairs with itself).  The inverse
 // forms Fe' + i Fo' at k and L - k the same way (its conjugate halves) for the
 // complex inverse, which holds the samples once scaled by 1/N.  A thread
 // reads both elements of its pair before it writes them, so the pass would
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(256) k_real_pair(const cf *in, cf *out, RealPa
     const cf *src = in + b * a.in_b;
     cf *dst = out + b * a.out_b;
     if constexpr (!INV) {
-      const cf zk = src[k], zr = src[kr & (a.L - 1)];
+      const cf zk = src[k], zr = src[kr == a.L ? 0 : kr];
       const cf fe = make_float2(0.5f * (zk.x + zr.x), 0.5f * (zk.y - zr.y));
       const cf fo = make_float2(0.5f * (zk.y + zr.y), -0.5f * (zk.x - zr.x));
       const cf t = cmul(w, fo);

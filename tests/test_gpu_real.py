@@ -50,7 +50,10 @@ def _real_batch(seed: int, n: int, batch: int) -> np.ndarray:
 
 
 SIZES_1D = [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768,
-            1 << 16, 1 << 18, 1 << 20, 1 << 22]
+            1 << 16, 1 << 18, 1 << 20, 1 << 22,
+            # even 7-smooth lengths: the runtime-radix core (single pass up to
+            # N/2 = 16384, then the four-step pair) and the pairing launch
+            6, 10, 14, 30, 96, 1000, 6000, 30000, 100000, 118098, 2 * 5 ** 7]
 
 
 @pytest.mark.parametrize("n", SIZES_1D)
@@ -185,7 +188,7 @@ def test_real_plan_edges():
     assert st == dp.FFT_OK
     del x
     for kw, code in ((dict(n=64, batch=2, real=True, inplace=True), dp.FFT_E_UNSUPPORTED),
-                     (dict(n=96, batch=2, real=True), dp.FFT_E_UNSUPPORTED),
+                     (dict(n=22, batch=2, real=True), dp.FFT_E_UNSUPPORTED),
                      (dict(n=1 << 25, batch=2, real=True), dp.FFT_E_UNSUPPORTED),
                      (dict(n=64, batch=2, real=True, dist=80), dp.FFT_E_INVALID),
                      (dict(n=64, batch=2, real=True, precision="fp16"), dp.FFT_E_UNSUPPORTED)):

@@ -243,6 +243,24 @@ def test_real_1d_four_step_plans(n):
     assert f"L={n // 2} (N={n}) batch={b}" in t
 
 
+@pytest.mark.parametrize("n,core,launches", [(6, "runtime-radix single-pass", 2),
+                                              (1000, "runtime-radix single-pass", 2),
+                                              (30000, "runtime-radix single-pass", 2),
+                                              (100000, "four-step 200x250", 3),
+                                              (118098, "four-step 243x243", 3)])
+def test_real_1d_mixed_plans(n, core, launches):
+    """Even 7-smooth lengths that are not powers of two: the N/2-point core on
+    the runtime-radix kernels (single pass, or the four-step pair), then the
+    pairing launch; the inverse pairs first."""
+    dp = _dp()
+    t = _dry(n=n, batch=3, flags=dp.FFT_F_REAL)
+    assert f"variant=real {core} + pairing" in t and f"launches={launches}" in t, t
+    assert f"workspace={3 * (n // 2) * 8}B" in t, t
+    fwd, inv = t.split("\n  inverse:")
+    assert fwd.index("real_core") < fwd.index("real_pairs:")
+    assert inv.index("real_pairs_inverse:") < inv.index("real_core")
+
+
 def test_real_2d_plan_layout():
     """Forward: real rows then in-place columns over nx/2 + 1 columns; inverse:
     columns into a workspace of batch * ny * (nx/2 + 1) complex64, then the
@@ -260,7 +278,8 @@ def test_real_2d_plan_layout():
 
 @pytest.mark.parametrize("kw,status", [
     (dict(n=64, batch=2, flags=16 | 1), "FFT_E_UNSUPPORTED"),      # in place
-    (dict(n=96, batch=2, flags=16), "FFT_E_UNSUPPORTED"),          # not a power of two
+    (dict(n=22, batch=2, flags=16), "FFT_E_UNSUPPORTED"),          # prime factor 11
+    (dict(n=15, batch=2, flags=16), "FFT_E_UNSUPPORTED"),          # odd
     (dict(n=1, batch=2, flags=16), "FFT_E_UNSUPPORTED"),           # N = 1 has no pairs
     (dict(n=1 << 25, batch=2, flags=16), "FFT_E_UNSUPPORTED"),     # above 2^24
     (dict(n=64, batch=2, dist=64, flags=16), "FFT_E_INVALID"),     # dense only
