@@ -138,7 +138,10 @@ typedef struct {
  *   desc       host pointer, read only during the call
  *   hip_stream stream used for the table uploads (NULL = default)
  * Supported: 1 <= N <= 2^24 with all prime factors <= 7 (FFT_E_UNSUPPORTED
- * otherwise); batch >= 0; rank 2 with each side a power of two <= 16384.
+ * otherwise); batch >= 0; rank 2 with each side <= 16384 and all prime
+ * factors <= 7 (powers of two on the line kernels, other sides on the
+ * runtime-radix kernels; complex only: real-input images need power-of-two
+ * sides).
  */
 fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream);
 

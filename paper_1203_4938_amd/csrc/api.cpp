@@ -732,6 +732,46 @@ bool mixed_fourstep_steps(dpfft_plan_s *P, int64_t N, int64_t B, int64_t in_b, i
   return true;
 }
 
+// Images whose sides are 7-smooth but not both powers of two: the row pass
+// (input -> output) and the column pass (column tiles in place on the
+// output) on the runtime-radix kernels, one pass through LDS each.  In place
+// is safe: with two or more passes every load of a tile precedes the barrier
+// that ends its first pass, and a one-pass line (a single radix) is one
+// butterfly of one thread.
+fft_status_t plan_mixed_2d(dpfft_plan_s *P) {
+  const int64_t NY = P->ny, NX = P->nx, B = P->batch, D = P->dist;
+  const int CR = mixed_lines(NX, ELEM_FAST, ELEM_FAST, 256, 1);
+  const int CC = mixed_lines(NY, LINE_FAST, LINE_FAST, 1024, 1);
+  auto r = CR ? make_mixed(P, "mixed_rows", NX, ELEM_FAST, ELEM_FAST, false, CR) : nullptr;
+  auto c = CC ? make_mixed(P, "mixed_columns", NY, LINE_FAST, LINE_FAST, false, std::min(CC, 16))
+              : nullptr;
+  if (!r || !c) return fail(FFT_E_UNSUPPORTED, "no runtime-radix 2D kernels for this shape");
+  r->a.in_b = r->a.out_b = D;
+  r->a.in_l = r->a.out_l = NX;
+  r->a.in_e = r->a.out_e = 1;
+  r->a.lines = NY;
+  r->a.tiles_per_batch = (NY + r->a.mp.C - 1) / r->a.mp.C;
+  r->grid = dim3((unsigned)(B * r->a.tiles_per_batch));
+  r->first = true;
+  r->src = BUF_IN;
+  r->dst = BUF_OUT;
+  c->a.in_b = c->a.out_b = D;
+  c->a.in_l = c->a.out_l = 1;
+  c->a.in_e = c->a.out_e = NX;
+  c->a.lines = NX;
+  c->a.tiles_per_batch = (NX + c->a.mp.C - 1) / c->a.mp.C;
+  c->a.flags = F_REMAP;
+  c->grid = dim3((unsigned)(B * c->a.tiles_per_batch));
+  c->last = true;
+  c->inv_scale = (float)(1.0 / ((double)NX * (double)NY));
+  c->src = BUF_OUT;
+  c->dst = BUF_OUT;
+  P->steps.push_back(std::move(r));
+  P->steps.push_back(std::move(c));
+  P->variant = "mixed 2d rows+columns";
+  return FFT_OK;
+}
+
 fft_status_t plan_mixed_1d(dpfft_plan_s *P) {
   const int64_t N = P->n, B = P->batch, D = P->dist;
   const Override ov = read_override();
@@ -1162,9 +1202,9 @@ fft_status_t validate_desc(const fft_desc_t *d) {
     if (d->ragged_sizes) return fail(FFT_E_INVALID, "ragged batches are rank 1 only");
     if (d->n[0] <= 0 || d->n[1] <= 0) return fail(FFT_E_INVALID, "image sides must be >= 1");
     if (d->flags & FFT_F_REAL) return FFT_OK;
-    if (!is_pow2(d->n[0]) || !is_pow2(d->n[1]) || d->n[0] > kSinglePassMax ||
-        d->n[1] > kSinglePassMax)
-      return fail(FFT_E_UNSUPPORTED, "rank 2 needs power-of-two sides <= 16384");
+    if (largest_prime_factor(d->n[0]) > 7 || largest_prime_factor(d->n[1]) > 7 ||
+        d->n[0] > kSinglePassMax || d->n[1] > kSinglePassMax)
+      return fail(FFT_E_UNSUPPORTED, "rank 2 needs sides <= 16384 with prime factors <= 7");
     if (d->dist != 0 && d->dist < d->n[0] * d->n[1])
       return fail(FFT_E_INVALID, "dist must be 0 or >= ny*nx");
   }
@@ -1232,7 +1272,7 @@ static fft_status_t build_plan_once(const fft_desc_t *desc, std::unique_ptr<dpff
     else
       st = is_pow2(P->n) ? plan_pow2_1d(P.get()) : plan_mixed_1d(P.get());
   } else {
-    st = plan_pow2_2d(P.get());
+    st = is_pow2(P->ny) && is_pow2(P->nx) ? plan_pow2_2d(P.get()) : plan_mixed_2d(P.get());
   }
   if (st != FFT_OK) return st;
   if (desc->flags & FFT_F_CONV) {

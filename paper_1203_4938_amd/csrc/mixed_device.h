@@ -253,8 +253,13 @@ __host__ __device__ inline int tw2_entries(int L, int shift) {
 template <int MAP, int OMAP, bool TW4, int SW>
 __device__ __forceinline__ void mixed_tile(const LineShape &sh, const TileLine &t, cf *lds,
                                            int nthreads) {
-  if (sh.P == 0) {  // length 1: the transform is the identity (both swaps cancel)
-    if (t.valid && t.j == 0) t.dst[0] = t.src[0];
+  if (sh.P == 0) {  // length 1: the transform is the identity, up to the swaps and the scale
+    if (t.valid && t.j == 0) {
+      cf y = t.src[0];
+      if (SW & 1) y = cswap(y);
+      if (SW & 2) y = cswap(cscale(y, sh.scale));
+      t.dst[0] = y;
+    }
     return;
   }
   // pass twiddles to LDS: the first pass copies one entry per thread (see

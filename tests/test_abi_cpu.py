@@ -70,7 +70,7 @@ def _no_gpu():
     (dict(n=13 * 64, batch=4), 2),
     (dict(n=(1 << 24) + 1, batch=1), 2),
     (dict(n=1 << 25, batch=1), 2),
-    (dict(rank=2, shape=(100, 128), batch=1), 2),
+    (dict(rank=2, shape=(22, 128), batch=1), 2),
     (dict(rank=2, shape=(0, 128), batch=1), 1),
     (dict(ragged_sizes=[64, 0, 16]), 1),
     (dict(ragged_sizes=[64, 22, 16]), 2),

@@ -64,3 +64,24 @@ def test_mixed_closed_forms_on_device():
     ref2 = np.zeros(n)
     ref2[17] = n
     assert np.linalg.norm(y[2] - ref2) / n < 1e-5
+
+
+@pytest.mark.parametrize("ny,nx,batch", [(100, 128, 3), (96, 81, 2), (1000, 7, 2), (243, 250, 2),
+                                         (6, 3000, 2), (16384, 3, 1), (3, 16384, 1), (1, 30, 4),
+                                         (30, 1, 4), (125, 2048, 1)])
+def test_mixed_2d_images(ny, nx, batch):
+    """Images whose sides are 7-smooth but not both powers of two: the row and
+    column passes on the runtime-radix kernels, both directions against the
+    oracle's separable 2D transforms (sides of 1 included: the identity pass
+    still takes the inverse's swap)."""
+    import paper_1203_4938_amd as dp
+    x = synth.uniform_complex(synth.BASE_SEED + 310, ny * nx, batch).reshape(batch, ny, nx)
+    p = dp.Plan(shape=(ny, nx), batch=batch, rank=2)
+    say(f"[mixed 2d] {batch} x {ny}x{nx}:", p.describe().replace("\n", " | "))
+    xd = to_dev(x)
+    for inv in (False, True):
+        y = run_plan(p, xd, inverse=inv).cpu().numpy()
+        e = max_rel(y, oracle.fft2d(x, inverse=inv))
+        say(f"   inverse={inv} max rel L2 = {e:.3e}")
+        assert e <= TOL_FP32, (ny, nx, inv, e)
+

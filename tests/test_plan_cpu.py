@@ -261,6 +261,15 @@ def test_real_1d_mixed_plans(n, core, launches):
     assert inv.index("real_pairs_inverse:") < inv.index("real_core")
 
 
+@pytest.mark.parametrize("shape", [(100, 128), (96, 81), (1, 30), (16384, 3)])
+def test_mixed_2d_plans(shape):
+    """Images with 7-smooth sides that are not both powers of two: the
+    runtime-radix row pass, then the column tiles in place; no workspace."""
+    t = _dry(rank=2, shape=shape, batch=2)
+    assert "variant=mixed 2d rows+columns" in t and "launches=2" in t and "workspace=0B" in t, t
+    assert t.index("mixed_rows:") < t.index("mixed_columns:")
+
+
 def test_real_2d_plan_layout():
     """Forward: real rows then in-place columns over nx/2 + 1 columns; inverse:
     columns into a workspace of batch * ny * (nx/2 + 1) complex64, then the
