@@ -120,11 +120,13 @@ typedef struct {
  * direction; otherwise the N/2-point complex transform of the samples read
  * as N/2 complex pairs runs on launches of its own, one single pass or a
  * four-step pair, and one more launch pairs bin k with N/2 - k, with a
- * workspace of batch * N/2 complex64), rank 2 with nx a power of two in
- * [2, 32768] and ny a power of two in [1, 16384] (two launches per
- * direction; the inverse needs a workspace of batch * ny * (nx/2 + 1)
- * complex64).  in != out.  Both buffers are device pointers owned by the
- * caller, 8-byte aligned.
+ * workspace of batch * N/2 complex64), rank 2 with nx an even number in
+ * [2, 32768] and ny in [1, 16384], both with prime factors <= 7 (powers of
+ * two: two launches per direction, the inverse with a workspace of batch *
+ * ny * (nx/2 + 1) complex64; other sides: three, the rows of nx/2 pairs on
+ * the runtime-radix kernels, the pairing, the columns, with that workspace
+ * in both directions).  in != out.  Both buffers are device pointers owned
+ * by the caller, 8-byte aligned.
  */
 
 /*
@@ -140,8 +142,7 @@ typedef struct {
  * Supported: 1 <= N <= 2^24 with all prime factors <= 7 (FFT_E_UNSUPPORTED
  * otherwise); batch >= 0; rank 2 with each side <= 16384 and all prime
  * factors <= 7 (powers of two on the line kernels, other sides on the
- * runtime-radix kernels; complex only: real-input images need power-of-two
- * sides).
+ * runtime-radix kernels).
  */
 fft_status_t fft_plan(fft_plan_t *out, const fft_desc_t *desc, void *hip_stream);
 

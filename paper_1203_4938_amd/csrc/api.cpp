@@ -1105,8 +1105,87 @@ fft_status_t plan_real_1d(dpfft_plan_s *P) {
 // then the column transforms in place on `out`; inverse = column transforms
 // of `in` into the workspace (scale 1/ny), then the complex-to-real rows from
 // the workspace into `out` (scale 1/nx).
+// Real-input images whose sides are not both powers of two: the rows of
+// nx/2 complex pairs through the runtime-radix single pass, the pairing of
+// bin k with nx/2 - k per row, then the runtime-radix column tiles over the
+// nx/2 + 1 columns.  Forward: rows input -> workspace, pairing workspace ->
+// output, columns in place on the output.  Inverse: columns input ->
+// workspace (scale 1/ny), pairing workspace -> output (rows of nx/2), rows in
+// place on the output (scale 1/nx).
+fft_status_t plan_real_2d_mixed(dpfft_plan_s *P) {
+  const int64_t NY = P->ny, NX = P->nx, B = P->batch;
+  const int64_t L = NX / 2, W = L + 1, R = B * NY;
+  const int CR = mixed_lines(L, ELEM_FAST, ELEM_FAST, 256, 1);
+  const int CC = mixed_lines(NY, LINE_FAST, LINE_FAST, 1024, 1);
+  std::unique_ptr<MixedStep> row[2], col[2];
+  for (int i = 0; i < 2; ++i) {
+    row[i] = CR ? make_mixed(P, i ? "real_core_rows_inverse" : "real_core_rows", L, ELEM_FAST,
+                             ELEM_FAST, false, CR)
+                : nullptr;
+    col[i] = CC ? make_mixed(P, i ? "columns_inverse" : "columns", NY, LINE_FAST, LINE_FAST, false,
+                             std::min(CC, 16))
+                : nullptr;
+    if (!row[i] || !col[i])
+      return fail(FFT_E_UNSUPPORTED, "no runtime-radix kernels for this real-input image");
+    MixedStep &r = *row[i];
+    r.a.in_b = r.a.out_b = 0;
+    r.a.in_l = r.a.out_l = L;
+    r.a.in_e = r.a.out_e = 1;
+    r.a.lines = R;
+    r.a.tiles_per_batch = (R + r.a.mp.C - 1) / r.a.mp.C;
+    r.grid = dim3((unsigned)r.a.tiles_per_batch);
+    r.first = r.last = true;
+    r.inv_scale = (float)(1.0 / (double)NX);
+    MixedStep &c = *col[i];
+    c.a.in_b = c.a.out_b = NY * W;
+    c.a.in_l = c.a.out_l = 1;
+    c.a.in_e = c.a.out_e = W;
+    c.a.lines = W;
+    c.a.tiles_per_batch = (W + c.a.mp.C - 1) / c.a.mp.C;
+    c.a.flags = F_REMAP;
+    c.grid = dim3((unsigned)(B * c.a.tiles_per_batch));
+    c.first = c.last = true;
+    c.inv_scale = (float)(1.0 / (double)NY);
+  }
+  std::vector<std::complex<double>> lo, hi;
+  const int shift = (ilog2(NX) + 1) / 2;
+  fourstep_tables(NX, shift, lo, hi);
+  const size_t lo_off = P->tables.add(lo), hi_off = P->tables.add(hi);
+  auto pair = [&](bool inv) {
+    auto r = std::make_unique<RealPairStep>();
+    r->inv = inv;
+    r->name = inv ? "real_pairs_inverse" : "real_pairs";
+    r->a.L = L;
+    r->a.batch = R;
+    r->a.in_b = inv ? W : L;
+    r->a.out_b = inv ? L : W;
+    r->a.shift = shift;
+    r->lo_off = lo_off;
+    r->hi_off = hi_off;
+    r->src = BUF_WS;
+    r->dst = BUF_OUT;
+    return r;
+  };
+  row[0]->src = BUF_IN;
+  row[0]->dst = BUF_WS;
+  col[0]->src = col[0]->dst = BUF_OUT;
+  col[1]->src = BUF_IN;
+  col[1]->dst = BUF_WS;
+  row[1]->src = row[1]->dst = BUF_OUT;
+  P->steps.push_back(std::move(row[0]));
+  P->steps.push_back(pair(false));
+  P->steps.push_back(std::move(col[0]));
+  P->isteps.push_back(std::move(col[1]));
+  P->isteps.push_back(pair(true));
+  P->isteps.push_back(std::move(row[1]));
+  P->ws_bytes = (size_t)B * (size_t)NY * (size_t)W * sizeof(float2);
+  P->variant = "real 2d runtime-radix rows + pairing + columns";
+  return FFT_OK;
+}
+
 fft_status_t plan_real_2d(dpfft_plan_s *P) {
   const int64_t NY = P->ny, NX = P->nx, B = P->batch;
+  if (!is_pow2(NY) || !is_pow2(NX)) return plan_real_2d_mixed(P);
   const int64_t W = NX / 2 + 1;  // bins per row
   const Override ov = read_override();
   auto rf = make_real(P, "real_rows", NX, false, NY, NY * NX / 2, NY * W);
@@ -1171,11 +1250,11 @@ fft_status_t validate_desc(const fft_desc_t *d) {
     if (d->rank == 1) {
       if (nr < 2 || nr % 2 || nr > kMaxN || largest_prime_factor(nr) > 7)
         return fail(FFT_E_UNSUPPORTED, "real-input lengths are even 7-smooth numbers in [2, 2^24]");
-    } else if (!is_pow2(nr) || nr < 2 || nr > 2 * kSinglePassMax) {
-      return fail(FFT_E_UNSUPPORTED, "real-input rows are powers of two in [2, 32768]");
+    } else if (nr < 2 || nr % 2 || nr > 2 * kSinglePassMax || largest_prime_factor(nr) > 7) {
+      return fail(FFT_E_UNSUPPORTED, "real-input rows are even 7-smooth numbers in [2, 32768]");
     }
-    if (d->rank == 2 && (!is_pow2(d->n[0]) || d->n[0] > kSinglePassMax))
-      return fail(FFT_E_UNSUPPORTED, "real-input images need ny a power of two <= 16384");
+    if (d->rank == 2 && (largest_prime_factor(d->n[0]) > 7 || d->n[0] > kSinglePassMax))
+      return fail(FFT_E_UNSUPPORTED, "real-input images need ny <= 16384 with prime factors <= 7");
   }
   if (d->ragged_offsets && !d->ragged_sizes)
     return fail(FFT_E_INVALID, "ragged_offsets given without ragged_sizes");

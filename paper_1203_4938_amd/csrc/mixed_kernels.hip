@@ -121,6 +121,7 @@ const void *mixed_kernel(int map, int omap, bool tw4, int sw) {
   // column tiles: 2D column pass (fwd, inv = swap out), four-step first pass (fwd, swap in)
   MK(LINE_FAST, LINE_FAST, false, 0)
   MK(LINE_FAST, LINE_FAST, false, 2)
+  MK(LINE_FAST, LINE_FAST, false, 3)
   MK(LINE_FAST, LINE_FAST, true, 0)
   MK(LINE_FAST, LINE_FAST, true, 1)
   // four-step second pass: rows stored transposed (fwd, swap out)

@@ -133,6 +133,35 @@ def test_real_2d_small_images():
         assert ef.max() <= TOL_FP32 and ei.max() <= TOL_FP32
 
 
+@pytest.mark.parametrize("ny,nx,b", [(100, 128, 3), (96, 90, 2), (3, 6, 4), (1, 10, 3), (30, 2, 3),
+                                     (243, 1000, 2), (2048, 2000, 1), (64, 30000, 1)])
+def test_real_2d_mixed_images(ny, nx, b):
+    """Real images whose sides are not both powers of two (runtime-radix rows,
+    the pairing launch, runtime-radix columns), both directions against the
+    oracle's 2D transforms, and the round trip."""
+    import torch
+
+    import paper_1203_4938_amd as dp
+    x = _real_batch(synth.BASE_SEED + 34, ny * nx, b).reshape(b, ny, nx)
+    p = dp.Plan(shape=(ny, nx), batch=b, rank=2, real=True)
+    say(f"[real 2d mixed] {b} x {ny}x{nx}:", p.describe().replace("\n", " | "))
+    xd = torch.from_numpy(x).cuda()
+    spec = p.exec(xd)
+    torch.cuda.synchronize()
+    assert spec.shape == (b, ny, nx // 2 + 1)
+    ref = oracle.fft2d(_as_c64(x))[:, :, : nx // 2 + 1]
+    ef = oracle.rel_l2_f32(spec.cpu().numpy(), ref)
+    half = ref.astype(np.complex64)
+    back = p.exec(torch.from_numpy(half).cuda(), inverse=True)
+    rt = p.exec(spec, inverse=True)
+    torch.cuda.synchronize()
+    iref = oracle.fft2d(herm_extend_2d(half, nx).astype(np.complex64), inverse=True)
+    ei = oracle.rel_l2_f32(_as_c64(back.cpu().numpy()), iref)
+    er = oracle.rel_l2_f32(_as_c64(rt.cpu().numpy()), x.astype(np.complex128))
+    say(f"   forward max {ef.max():.3e} inverse max {ei.max():.3e} round trip max {er.max():.3e}")
+    assert ef.max() <= TOL_FP32 and ei.max() <= TOL_FP32 and er.max() <= TOL_FP32
+
+
 def test_real_2d_c3_every_image():
     """The 16 greyscale images of 2048 x 2048 (the image workload), every
     image, both directions, plus the round trip and the exact DC bins."""

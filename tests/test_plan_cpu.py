@@ -293,7 +293,8 @@ def test_real_2d_plan_layout():
     (dict(n=1 << 25, batch=2, flags=16), "FFT_E_UNSUPPORTED"),     # above 2^24
     (dict(n=64, batch=2, dist=64, flags=16), "FFT_E_INVALID"),     # dense only
     (dict(n=64, batch=2, flags=16, precision="bf16"), "FFT_E_UNSUPPORTED"),
-    (dict(rank=2, shape=(3, 64), batch=1, flags=16), "FFT_E_UNSUPPORTED"),
+    (dict(rank=2, shape=(22, 64), batch=1, flags=16), "FFT_E_UNSUPPORTED"),  # prime factor 11
+    (dict(rank=2, shape=(64, 15), batch=1, flags=16), "FFT_E_UNSUPPORTED"),  # odd rows
     (dict(rank=2, shape=(32768, 64), batch=1, flags=16), "FFT_E_UNSUPPORTED"),
     (dict(ragged_sizes=[64, 128], flags=16), "FFT_E_UNSUPPORTED"),
 ])
